@@ -1,0 +1,223 @@
+"""Shadow potential, forces, KSA-XL-BOMD integration and the initial SCF.
+
+Paper references:
+  * shadow potential U(R, X) = 2Tr[h D0] + Tr[(2D0 - X)G(X)] - 2 T_e S + V_nn
+    (eq. 13 with S = I).  Eq. 13 and eq. 26 print -T_e S while eqs. 1 and 12
+    print -2 T_e S; this oracle reads -2 T_e S throughout, the only choice
+    for which D0 of eq. 12 (Fermi at beta = 1/(k_B T_e)) is stationary for U
+    (eq. 22), and the one the finite-difference force test confirms;
+  * forces -dU/dR_I at fixed X (eq. 24) from eq. 37: 2Tr[h_R D0] +
+    Tr[(2D0 - P)G_R] + dV_nn/dR; the Pulay term vanishes because S = I;
+  * leapfrog velocity Verlet for the nuclei (eqs. 27, 28, 30) and the damped
+    X-Verlet of eq. 35: X(t+dt) = 2X(t) - X(t-dt) - kappa Y(t)
+    + alpha sum_k c_k X(t - k dt), with Y the Krylov kernel of eq. 34.  Eq. 29
+    prints "+ kappa Xddot" with kappa = dt^2 omega^2, which would count omega^2
+    twice given eq. 25; eq. 35's form is used.  The paper takes kappa, alpha,
+    c_k for k_max = 6 from its ref. [24]; the values below are that table's
+    k_max = 6 row (they satisfy sum c_k = 0 and sum k c_k = 0);
+  * the initial history X(t0 - k dt) = D_min for k = 0..k_max (Methods
+    section 5), D_min from a Newton-Krylov SCF (X <- X - Y, the KSA SCF of the
+    paper's last results section).
+All densities here are spin-summed (P = 2D, X likewise), which leaves J, the
+Krylov kernel and the integrator unchanged because they are linear.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import model, density, krylov
+
+EV_PER_AMU_TO_A2_PER_FS2 = 9.648533e-3   # 1 eV/(Angstrom amu) in Angstrom/fs^2
+XL_KAPPA = 1.84
+XL_ALPHA = 0.0055
+XL_C = (-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0)
+
+
+def pair_w_energy(Wp, a, b, P0, X, params) -> np.ndarray:
+    """Per-pair sum of every energy term that is linear in W_AB (Np,):
+    core-electron attraction, electron Coulomb, exchange and core-core Coulomb.
+    ``Wp`` holds the (Np, 10, 10) blocks (or their radial derivatives)."""
+    N = P0.shape[0] // 4
+    Z = params.z_core
+    Q = P0 - 0.5 * X
+    p0d = model._pack(model._atom_blocks(P0, N))
+    xd = model._pack(model._atom_blocks(X, N))
+    qd = model._pack(model._atom_blocks(Q, N))
+    core = -Z * (np.einsum("pi,pi->p", Wp[:, :, 0], p0d[a]) + np.einsum("pj,pj->p", Wp[:, 0, :], p0d[b]))
+    coul = np.einsum("pi,pij,pj->p", qd[a], Wp, xd[b]) + np.einsum("pi,pij,pj->p", xd[a], Wp, qd[b])
+    W4 = Wp[:, model.IDX10[:, :, None, None], model.IDX10[None, None, :, :]]
+    Qab = Q.reshape(N, 4, N, 4)[a, :, b, :]
+    Xab = X.reshape(N, 4, N, 4)[a, :, b, :]
+    exch = -np.einsum("pml,pns,pmnls->p", Qab, Xab, W4)
+    nn = Z * Z * Wp[:, 0, 0]
+    return core + coul + exch + nn
+
+
+def forces(R, P0, X, sys_params, noise55, chunk: int = 20000) -> np.ndarray:
+    """F_I = -dU/dR_I at fixed X (eq. 24, eq. 37 with S = I), (N, 3) eV/Angstrom."""
+    params = sys_params
+    N = R.shape[0]
+    Fout = np.zeros((N, 3))
+    if N < 2:
+        return Fout
+    g = model.pair_geometry(R, params)
+    a_all, b_all = g["a"], g["b"]
+    P0b = P0.reshape(N, 4, N, 4)
+    for s in range(0, a_all.size, chunk):
+        sl = slice(s, s + chunk)
+        a, b = a_all[sl], b_all[sl]
+        r, l, t, dt = g["r"][sl], g["l"][sl], g["t"][sl], g["dt"][sl]
+        # d l_i / d R_B = (delta_ik - l_i l_k) / r
+        dl = (np.eye(3)[None] - l[:, :, None] * l[:, None, :]) / r[:, None, None]   # (p, i, k)
+        # derivative of the hopping block w.r.t. R_B, (p, 4, 4, k)
+        dblk = np.empty((a.size, 4, 4, 3))
+        dblk[:, 0, 0, :] = dt[:, None] * l
+        dblk[:, 0, 1:, :] = dt[:, None, None] * l[:, :, None] * l[:, None, :] + t[:, None, None] * dl
+        dblk[:, 1:, 0, :] = -dblk[:, 0, 1:, :]
+        ll = l[:, :, None] * l[:, None, :]
+        dll = (dl[:, :, None, :] * l[:, None, :, None] + l[:, :, None, None] * dl[:, None, :, :])
+        dblk[:, 1:, 1:, :] = dt[:, None, None, None] * ll[..., None] * l[:, None, None, :] + t[:, None, None, None] * dll
+        # Tr[h_R P0] over both off-diagonal blocks (h and P0 symmetric)
+        dE_hop = 2.0 * np.einsum("pij,pijk->pk", P0b[a, :, b, :], dblk)
+        # terms linear in W: dW/dR_B = gamma'(r) l (J + noise)
+        base = model.two_centre_base(noise55[sl], params)
+        dEw_dr = pair_w_energy(g["dgamma"][sl, None, None] * base, a, b, P0, X, params)
+        drep_dr = -params.a_rep / params.rho_rep * np.exp(-(r - params.r0_rep) / params.rho_rep)
+        dE_dRB = dE_hop + (dEw_dr + drep_dr)[:, None] * l
+        np.add.at(Fout, b, -dE_dRB)
+        np.add.at(Fout, a, dE_dRB)
+    return Fout
+
+
+@dataclass
+class Settings:
+    T_e: float
+    m: int
+    dt: float
+    kappa: float = XL_KAPPA
+    alpha: float = XL_ALPHA
+    c: tuple = XL_C
+    krylov_tol: float = 0.0
+
+    @property
+    def beta(self) -> float:
+        return density.beta_of(self.T_e)
+
+
+def evaluate(R, X, sys_, st: Settings, with_kernel: bool = True) -> dict:
+    """Everything the method needs at a state (R, X): F (eq. 17), P0 (eq. 19),
+    Y (eq. 34), forces (eq. 37), U (eq. 13) and its parts."""
+    p = sys_.params
+    beta = st.beta
+    h = model.hcore(R, sys_.onecenter, sys_.noise, p)
+    G = model.two_electron(X, R, sys_.onecenter, sys_.noise, p)
+    F = h + G
+    dm = density.density_matrix(F, sys_.n_elec, beta)
+    P0 = dm["P"]
+    out = dict(F=F, P0=P0, mu=dm["mu"], eps=dm["eps"], f=dm["f"])
+    S = density.entropy(dm["f"])
+    Vnn = model.nuclear_repulsion(R, sys_.noise, p)
+    E_elec = float(np.sum(h * P0) + np.sum((P0 - 0.5 * X) * G))
+    out["S"] = S
+    out["Vnn"] = Vnn
+    out["U"] = E_elec - 2.0 * S / beta + Vnn
+    out["forces"] = forces(R, P0, X, p, sys_.noise)
+    if with_kernel:
+        def jac(V):
+            F1 = model.two_electron(V, R, sys_.onecenter, sys_.noise, p)
+            return density.response(F, F1, sys_.n_elec, beta, dm) - V
+        Y, rank, rel = krylov.krylov_kernel(X, P0, jac, st.m, st.krylov_tol)
+        out.update(Y=Y, rank=rank, relres=rel)
+    return out
+
+
+def kinetic_energy(V, mass) -> float:
+    return float(0.5 * mass * np.sum(V * V) / EV_PER_AMU_TO_A2_PER_FS2)
+
+
+@dataclass
+class MDState:
+    R: np.ndarray
+    V: np.ndarray
+    A: np.ndarray               # acceleration, Angstrom/fs^2
+    Xhist: list = field(default_factory=list)   # [X(t), X(t-dt), ..., X(t-6dt)]
+    Y: np.ndarray | None = None
+    mu: float = 0.0
+    U: float = 0.0
+    step: int = 0
+
+
+def scf(sys_, st: Settings, X0=None, m: int = 20, tol: float = 1e-10, max_iter: int = 200,
+        mix: float = 0.04, mix_tol: float = 1e-2, max_mix: int = 20000):
+    """Ground state D_min with ||D0[X] - X||_F <= tol (spin-summed).
+
+    Linear mixing X <- X + mix (D0[X] - X) until the residual is below
+    ``mix_tol`` (it only settles into stable fixed points), then Newton-Krylov
+    steps X <- X - lam Y with Y ~ J^-1 (D0[X] - X) (eq. 34) and lam halved
+    until the residual decreases."""
+    n = sys_.n_orb
+    X = np.eye(n) * (sys_.n_elec / n) if X0 is None else np.array(X0, dtype=np.float64)
+    beta = st.beta
+    h = model.hcore(sys_.R, sys_.onecenter, sys_.noise, sys_.params)
+    for _ in range(max_mix):
+        F = h + model.two_electron(X, sys_.R, sys_.onecenter, sys_.noise, sys_.params)
+        P = density.density_matrix(F, sys_.n_elec, beta)["P"]
+        res = np.linalg.norm(P - X)
+        if res <= mix_tol:
+            break
+        X = X + mix * (P - X)
+    sub = Settings(T_e=st.T_e, m=m, dt=st.dt)
+    ev = evaluate(sys_.R, X, sys_, sub)
+    res = np.linalg.norm(ev["P0"] - X)
+    for _ in range(max_iter):
+        if res <= tol:
+            return ev["P0"]
+        lam = 1.0
+        while True:
+            Xt = X - lam * ev["Y"]
+            evt = evaluate(sys_.R, Xt, sys_, sub)
+            rt = np.linalg.norm(evt["P0"] - Xt)
+            if rt < res or lam < 1e-4:
+                break
+            lam *= 0.5
+        X, ev, res = Xt, evt, rt
+    raise RuntimeError(f"SCF did not converge (residual {res:.3e})")
+
+
+def init_state(sys_, st: Settings, X_min) -> MDState:
+    """t0 state: history filled with D_min, forces and kernel evaluated there."""
+    ev = evaluate(sys_.R, X_min, sys_, st)
+    A = ev["forces"] / sys_.params.mass * EV_PER_AMU_TO_A2_PER_FS2
+    return MDState(R=sys_.R.copy(), V=sys_.V.copy(), A=A, Xhist=[X_min.copy() for _ in range(7)],
+                   Y=ev["Y"], mu=ev["mu"], U=ev["U"], step=0)
+
+
+def integrate_x(Xhist, Y, st: Settings) -> np.ndarray:
+    """Damped X-Verlet with the Krylov kernel (eq. 35)."""
+    Xn = 2.0 * Xhist[0] - Xhist[1] - st.kappa * Y
+    for k, ck in enumerate(st.c):
+        Xn = Xn + st.alpha * ck * Xhist[k]
+    return Xn
+
+
+def md_step(state: MDState, sys_, st: Settings):
+    """One KSA-XL-BOMD NVE step (eqs. 27, 28, 35, 30).  Returns (state, report)."""
+    dt = st.dt
+    mass = sys_.params.mass
+    Vh = state.V + 0.5 * dt * state.A
+    Rn = state.R + dt * Vh
+    Xn = integrate_x(state.Xhist, state.Y, st)
+    ev = evaluate(Rn, Xn, sys_, st)
+    An = ev["forces"] / mass * EV_PER_AMU_TO_A2_PER_FS2
+    Vn = Vh + 0.5 * dt * An
+    new = MDState(R=Rn, V=Vn, A=An, Xhist=[Xn] + state.Xhist[:-1], Y=ev["Y"], mu=ev["mu"],
+                  U=ev["U"], step=state.step + 1)
+    KE = kinetic_energy(Vn, mass)
+    dof = max(3 * sys_.n_atoms - 3, 1)
+    rep = dict(E_tot=KE + ev["U"], KE=KE, U=ev["U"], TS=2.0 * ev["S"] / st.beta,
+               T_ion=2.0 * KE / (dof * density.KB_EV_PER_K), mu=ev["mu"],
+               W0=float(np.linalg.norm(ev["P0"] - Xn)), relres=ev["relres"], rank=ev["rank"])
+    return new, rep

@@ -1,0 +1,158 @@
+"""Pins of the oracle's Krylov kernel, forces, integrator and SCF."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import carbon_cluster, ModelParams
+from oracle import model, density, krylov, dynamics
+
+
+def _jacobian_apply(sys_, X, beta):
+    F = model.fock(X, sys_.R, sys_.onecenter, sys_.noise, sys_.params)
+    dm = density.density_matrix(F, sys_.n_elec, beta)
+
+    def jac(V):
+        F1 = model.two_electron(V, sys_.R, sys_.onecenter, sys_.noise, sys_.params)
+        return density.response(F, F1, sys_.n_elec, beta, dm) - V
+    return dm["P"], jac
+
+
+def _start_density(sys_, rng):
+    n = sys_.n_orb
+    X = np.eye(n) * sys_.n_elec / n + 0.05 * rng.standard_normal((n, n))
+    return 0.5 * (X + X.T)
+
+
+def test_full_rank_krylov_equals_exact_inverse_jacobian():
+    sys_ = carbon_cluster(2, 8)
+    n = sys_.n_orb
+    beta = density.beta_of(3000.0)
+    X = _start_density(sys_, np.random.default_rng(8))
+    P0, jac = _jacobian_apply(sys_, X, beta)
+    # J assembled column by column on the orthonormal symmetric basis, solved by LU
+    iu = np.triu_indices(n)
+    basis = []
+    for i, j in zip(*iu):
+        E = np.zeros((n, n))
+        if i == j:
+            E[i, i] = 1.0
+        else:
+            E[i, j] = E[j, i] = 1.0 / np.sqrt(2.0)
+        basis.append(E)
+    coords = lambda M: np.array([np.sum(B * M) for B in basis])
+    J = np.array([coords(jac(B)) for B in basis]).T
+    W0 = P0 - X
+    y = np.linalg.solve(J, coords(W0))
+    Yref = sum(c * B for c, B in zip(y, basis))
+    Y, rank, rel = krylov.krylov_kernel(X, P0, jac, m=len(basis))
+    assert rel < 1e-10
+    np.testing.assert_allclose(Y, Yref, atol=1e-9 * np.abs(Yref).max())
+
+
+def test_rank_one_closed_form_and_zero_interaction_limit():
+    sys_ = carbon_cluster(3, 9)
+    beta = density.beta_of(3000.0)
+    X = _start_density(sys_, np.random.default_rng(9))
+    P0, jac = _jacobian_apply(sys_, X, beta)
+    W0 = P0 - X
+    V1 = W0 / np.linalg.norm(W0)
+    W1 = jac(V1)
+    Y, rank, _ = krylov.krylov_kernel(X, P0, jac, m=1)
+    np.testing.assert_allclose(Y, V1 * np.sum(W1 * W0) / np.sum(W1 * W1), atol=1e-13)
+    # no two-electron response: J = -I, so the kernel returns -W0 (original XL-BOMD, c = 1)
+    Y, rank, rel = krylov.krylov_kernel(X, P0, lambda V: -V, m=3)
+    np.testing.assert_allclose(Y, -W0, atol=1e-13)
+    assert rank == 1 and rel < 1e-14
+
+
+def test_forces_match_finite_differences_of_shadow_energy():
+    sys_ = carbon_cluster(4, 10)
+    st = dynamics.Settings(T_e=3000.0, m=2, dt=0.5)
+    X = _start_density(sys_, np.random.default_rng(10))
+    ev = dynamics.evaluate(sys_.R, X, sys_, st, with_kernel=False)
+    h = 1e-5
+    fd = np.zeros_like(sys_.R)
+    for i in range(sys_.n_atoms):
+        for k in range(3):
+            Rp, Rm = sys_.R.copy(), sys_.R.copy()
+            Rp[i, k] += h
+            Rm[i, k] -= h
+            Up = dynamics.evaluate(Rp, X, sys_, st, with_kernel=False)["U"]
+            Um = dynamics.evaluate(Rm, X, sys_, st, with_kernel=False)["U"]
+            fd[i, k] = -(Up - Um) / (2 * h)
+    np.testing.assert_allclose(ev["forces"], fd, atol=2e-6 * max(1.0, np.abs(fd).max()))
+    np.testing.assert_allclose(ev["forces"].sum(0), 0.0, atol=1e-10)
+
+
+def test_entropy_factor_two_is_the_stationary_one():
+    # With -T_e S instead of -2 T_e S the forces at fixed X would miss a term:
+    # the FD gradient of that alternative energy disagrees with eq. 37's forces.
+    sys_ = carbon_cluster(3, 12)
+    st = dynamics.Settings(T_e=8000.0, m=2, dt=0.5)
+    X = _start_density(sys_, np.random.default_rng(12))
+    ev = dynamics.evaluate(sys_.R, X, sys_, st, with_kernel=False)
+    h = 1e-5
+
+    def u_alt(R):
+        e = dynamics.evaluate(R, X, sys_, st, with_kernel=False)
+        return e["U"] + e["S"] / st.beta
+    Rp, Rm = sys_.R.copy(), sys_.R.copy()
+    Rp[0, 0] += h
+    Rm[0, 0] -= h
+    fd_alt = -(u_alt(Rp) - u_alt(Rm)) / (2 * h)
+    assert abs(fd_alt - ev["forces"][0, 0]) > 1e-4
+
+
+def test_energy_fluctuation_scales_as_dt_squared():
+    sys_ = carbon_cluster(6, 13)
+    st0 = dynamics.Settings(T_e=3000.0, m=3, dt=0.2)
+    Xmin = dynamics.scf(sys_, st0, m=30)
+    spans = []
+    for dt in (0.2, 0.1):
+        st = dataclasses.replace(st0, dt=dt)
+        s = dynamics.init_state(sys_, st, Xmin)
+        E = []
+        for _ in range(int(round(2.0 / dt))):
+            s, rep = dynamics.md_step(s, sys_, st)
+            E.append(rep["E_tot"])
+        spans.append(np.ptp(E))
+    ratio = spans[0] / spans[1]
+    assert 3.0 < ratio < 5.5, ratio
+
+
+def test_integration_is_time_reversible_without_damping():
+    sys_ = carbon_cluster(5, 14)
+    st = dynamics.Settings(T_e=3000.0, m=3, dt=0.2, alpha=0.0)
+    rng = np.random.default_rng(14)
+    X0 = _start_density(sys_, rng)
+    s = dynamics.init_state(sys_, st, X0)
+    s.Xhist[1] = s.Xhist[0] + 0.001 * (s.Xhist[0] - X0.T)
+    start = (s.R.copy(), s.Xhist[0].copy())
+    for _ in range(5):
+        s, _ = dynamics.md_step(s, sys_, st)
+    # reverse: flip the velocities; the backward X step from X(t) needs the
+    # history (X(t), X(t+dt)) with X(t+dt) the forward prediction of eq. 35
+    Xnext = dynamics.integrate_x(s.Xhist, s.Y, st)
+    back = dynamics.MDState(R=s.R, V=-s.V, A=s.A, Xhist=[s.Xhist[0], Xnext] + s.Xhist[2:],
+                            Y=s.Y, mu=s.mu)
+    for _ in range(5):
+        back, _ = dynamics.md_step(back, sys_, st)
+    np.testing.assert_allclose(back.R, start[0], atol=1e-9)
+    np.testing.assert_allclose(back.Xhist[0], start[1], atol=1e-9)
+
+
+def test_damping_coefficients_are_consistent():
+    c = np.array(dynamics.XL_C)
+    k = np.arange(7)
+    assert c.sum() == 0.0 and (k * c).sum() == 0.0
+
+
+def test_scf_reaches_fixed_point():
+    sys_ = carbon_cluster(5, 15)
+    st = dynamics.Settings(T_e=3000.0, m=3, dt=0.5)
+    X = dynamics.scf(sys_, st, m=30, tol=1e-10)
+    F = model.fock(X, sys_.R, sys_.onecenter, sys_.noise, sys_.params)
+    P = density.density_matrix(F, sys_.n_elec, st.beta)["P"]
+    assert np.linalg.norm(P - X) < 1e-9
