@@ -1,0 +1,215 @@
+/*
+ * xlbomd.h -- C ABI of the per-time-step electronic hot path of shadow
+ * (KSA-)XL-BOMD for semiempirical sp Hamiltonians on one MI355X (gfx950).
+ *
+ * Method: Kulichenko et al., "Semi-Empirical Shadow Molecular Dynamics: A
+ * PyTorch implementation", arXiv:2303.00689.  Equation numbers below are the
+ * paper's.
+ *
+ * Conventions shared by every call
+ *   - Orbital index 4*atom + {0: s, 1: px, 2: py, 3: pz}; n = 4 * n_atoms.
+ *   - Matrices are dense, symmetric, n x n, FP64, row-major (equal to
+ *     column-major because they are symmetric), owned by the caller, in
+ *     DEVICE memory of the current HIP device.  The library never frees them.
+ *   - Density matrices at this interface are spin-summed: P = 2 D with the
+ *     paper's one-spin D, so Tr P = N_e.  The dynamical variable X and the
+ *     kernel result Y use the same scaling.
+ *   - Atom pairs (A < B) are enumerated row-major; packed orbital pairs
+ *     (mu nu), mu <= nu, run over the row-major upper triangle of a 4x4 block;
+ *     a packed symmetric 10 x 10 block stores its upper triangle row-major in
+ *     55 values.
+ *   - Every call enqueues its work on the stream given at create time.  Calls
+ *     that return host scalars (mu, entropy, rank, residual, energies, the MD
+ *     report) synchronise that stream before returning.
+ *   - No call throws; each returns an xlbomd_status.  The last error message
+ *     of a handle is available through xlbomd_last_error().  One handle must
+ *     not be used by two host threads at once.
+ *   - Units: eV, Angstrom, fs, amu, K.
+ */
+#ifndef XLBOMD_H
+#define XLBOMD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xlbomd_ctx *xlbomd_handle;
+
+typedef enum {
+  XLBOMD_OK = 0,
+  XLBOMD_E_ARG = -1,       /* invalid argument (null pointer, size, range)        */
+  XLBOMD_E_HIP = -2,       /* a HIP runtime call failed                            */
+  XLBOMD_E_NOCONV = -3,    /* chemical potential or SCF not converged              */
+  XLBOMD_E_NONFINITE = -4, /* a NaN or Inf was detected in a result                */
+  XLBOMD_E_STATE = -5,     /* call order violated (e.g. response before fermi_dm)  */
+  XLBOMD_E_NOMEM = -6      /* device allocation failed                             */
+} xlbomd_status;
+
+/* Arithmetic of the recursive Fermi-operator and response GEMM chains.  The
+ * Fock build, traces, chemical potential, Krylov algebra, forces and energies
+ * are FP64 in every mode. */
+typedef enum {
+  XLBOMD_FP64 = 0,   /* FP64 storage, FP64 MFMA                                    */
+  XLBOMD_BF16X3 = 1, /* FP32 storage, two-term BF16 split, 3 products, FP32 acc   */
+  XLBOMD_BF16X6 = 2, /* FP32 storage, three-term BF16 split, 6 products, FP32 acc */
+  XLBOMD_FP16X3 = 3  /* FP32 storage, two-term FP16 split with 2^11-scaled low   */
+                     /* parts, 3 products, FP32 acc                               */
+} xlbomd_precision;
+
+/* Synthetic NDDO-type sp Hamiltonian (stand-in for AM1/MNDO/PM3, which the
+ * method section builds on, eq. 6 with S = I):
+ *   h_AA = diag(eps_s, eps_p, eps_p, eps_p) - sum_{B != A} z_core W_AB[:, ss]
+ *   h_AB = t(R) {s-s: 1, s_A-p_B: l, p_A-s_B: -l, p_A-p_B: l l^T},
+ *          t(R) = t0 exp(-(R - r0_hop)/lam_hop), l = (R_B - R_A)/R
+ *   W_AB = coul_k / sqrt(R^2 + coul_a^2) * (J + noise_amp * noise_AB)
+ *   V_nn = sum_{A<B} z_core^2 W_AB[ss,ss] + a_rep exp(-(R - r0_rep)/rho_rep) */
+typedef struct {
+  double eps_s, eps_p;
+  double t0, r0_hop, lam_hop;
+  double coul_k, coul_a;
+  double noise_amp;
+  double z_core;
+  double a_rep, r0_rep, rho_rep;
+  double mass;     /* amu, every atom                                    */
+  double j55[55];  /* packed 10 x 10 pattern J of the two-centre blocks  */
+} xlbomd_model;
+
+/* One system.  Host arrays are copied at create time (the two-centre noise is
+ * repacked into the library's tile-major device layout) and may be freed
+ * afterwards. */
+typedef struct {
+  int n_atoms;               /* >= 1                                                 */
+  double n_elec;             /* N_e, 0 < N_e < 2n                                     */
+  const double *onecenter;   /* host, n_atoms x 5: Gss, Gsp, Gpp, Gp2, Hsp (eV)       */
+  const float *noise55;      /* host, n_pair x 55, packed symmetric blocks, pair order */
+                             /* A < B row-major; may be NULL when n_atoms == 1         */
+  xlbomd_model model;
+} xlbomd_system;
+
+/* Integration and chain settings. */
+typedef struct {
+  xlbomd_precision prec;
+  double T_e;         /* electronic temperature, K (beta = 1/(k_B T_e), eq. 7)           */
+  int m;              /* Krylov rank used by xlbomd_step (eq. 34), 0 <= m <= 32          */
+  double krylov_tol;  /* relative-residual stop for xlbomd_step's kernel, 0 = fixed m    */
+  double dt;          /* fs                                                              */
+  double kappa;       /* eq. 35 kappa = dt^2 omega^2                                     */
+  double alpha;       /* eq. 29/35 damping alpha                                         */
+  double c[7];        /* eq. 29/35 damping c_k, k = 0..6                                 */
+} xlbomd_params;
+
+/* MD state of xlbomd_step, all DEVICE pointers owned by the caller.  The X
+ * history is a ring of 7 matrices: X(t - k dt) lives in slot (head + k) % 7. */
+typedef struct {
+  double *R;      /* n_atoms x 3, Angstrom                                  */
+  double *V;      /* n_atoms x 3, Angstrom/fs                               */
+  double *A;      /* n_atoms x 3, Angstrom/fs^2 (force / mass)             */
+  double *X;      /* 7 x n x n ring                                         */
+  double *Y;      /* n x n, kernel result Y(t) of eq. 34 at the current t   */
+  int head;       /* host: ring slot of X(t)                                */
+  double mu;      /* host: chemical potential of the last evaluation, eV    */
+} xlbomd_md_state;
+
+/* Per-step report (host). */
+typedef struct {
+  double E_tot;   /* KE + U, the constant of motion of eq. 26                 */
+  double KE;      /* sum 1/2 M v^2                                            */
+  double U;       /* shadow potential, eq. 13 with -2 T_e S                   */
+  double TS;      /* 2 T_e S                                                  */
+  double T_ion;   /* 2 KE / ((3N - 3) k_B)                                    */
+  double mu;      /* chemical potential                                       */
+  double W0;      /* ||D0[X] - X||_F, spin-summed                             */
+  double relres;  /* relative residual of the rank-m kernel                   */
+  int rank;       /* Krylov rank used                                          */
+  int status;     /* XLBOMD_OK or the guard that tripped                       */
+} xlbomd_report;
+
+/* Create a handle for one system; allocates all device workspace.  `stream`
+ * is a hipStream_t (NULL = default stream).  Positions must be set with
+ * xlbomd_set_geometry before any other call. */
+xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm,
+                            void *stream, xlbomd_handle *out);
+xlbomd_status xlbomd_destroy(xlbomd_handle h);
+const char *xlbomd_last_error(xlbomd_handle h);
+/* Dimension n = 4 * n_atoms of the handle's matrices (0 on a null handle). */
+int xlbomd_n_orb(xlbomd_handle h);
+
+/* Copy positions R (DEVICE, n_atoms x 3) into the handle; h(R), W(R) and V_nn
+ * are then evaluated on the fly by the calls below (eq. 17's h and G depend on
+ * R only through the pair geometry). */
+xlbomd_status xlbomd_set_geometry(xlbomd_handle h, const double *R);
+
+/* a1: dense one-electron matrix h(R) into H (DEVICE n x n), eq. 6. */
+xlbomd_status xlbomd_hcore(xlbomd_handle h, double *H);
+
+/* a2: Fock build F = h + G(P) (eq. 6 / eq. 17 with S = I) for a spin-summed P,
+ * G(P)_mn = sum_ls P_ls [(mn|ls) - 1/2 (ml|ns)] (eq. 3 at D = P/2) with NDDO
+ * integrals.  include_h = 0 returns G(P) only (the F1 = G(V) of eq. 36).
+ * P and F are DEVICE n x n and must not alias. */
+xlbomd_status xlbomd_fock(xlbomd_handle h, const double *P, double *F, int include_h);
+
+/* a3-a5: finite-temperature density matrix of eq. 19, P = 2 (exp(beta (F - mu0)) + 1)^-1,
+ * with mu0 fixed by Tr P = N_e (eq. 8), by a recursive Fermi-operator GEMM chain in
+ * the handle's precision and an exact chemical-potential shift.
+ *   mu      host in/out: warm-start guess (NaN: none) / converged mu0
+ *   P       DEVICE n x n output (must not alias F)
+ *   entropy host out, nullable: S/k_B = -sum_i [f ln f + (1-f) ln(1-f)] (eq. 4, one spin)
+ * The chain is cached in the handle for xlbomd_dm_response.  Returns
+ * XLBOMD_E_NOCONV if |Tr P - N_e| > 1e-9 N_e after the shift. */
+xlbomd_status xlbomd_fermi_dm(xlbomd_handle h, const double *F, double *mu, double *P,
+                              double *entropy);
+
+/* a6: canonical first-order response P1 = 2 dD/dlambda of D[F + lambda F1] at the
+ * state of the last xlbomd_fermi_dm (eq. 36), with mu re-solved (Tr P1 = 0).
+ * F1, P1: DEVICE n x n.  XLBOMD_E_STATE if no chain is cached. */
+xlbomd_status xlbomd_dm_response(xlbomd_handle h, const double *F1, double *P1);
+
+/* a7: rank-m Krylov approximation (eq. 34, K0 = I) of Y = J^-1 (P0 - X), with
+ * J V = P1[G(V)] - V the Jacobian of the residual (eq. 15).  Requires a
+ * xlbomd_fermi_dm on F = h + G(X) just before (its chain is reused).
+ *   m         requested rank (0 <= m <= 32); tol > 0 stops early once the
+ *             relative residual falls below tol
+ *   Y         DEVICE n x n output
+ *   rank      host out: rank used (breakdown is reported here, not as an error)
+ *   relres    host out: ||sum W_i M_ij <W_j, W0> - W0|| / ||W0||  */
+xlbomd_status xlbomd_krylov_kernel(xlbomd_handle h, const double *X, const double *P0, int m,
+                                   double tol, double *Y, int *rank, double *relres);
+
+/* a9: forces -dU/dR_A at fixed X (eq. 24, eq. 37 with S = I) into forces
+ * (DEVICE n_atoms x 3, eV/Angstrom) and the parts of U (host, nullable, 4 values):
+ *   [0] Tr[h P0], [1] Tr[(P0 - X/2) G(X)], [2] V_nn, [3] Tr[h P0] + Tr[(P0 - X/2)G(X)] + V_nn */
+xlbomd_status xlbomd_forces(xlbomd_handle h, const double *P0, const double *X,
+                            double *forces, double *energy);
+
+/* a8: damped X-Verlet of eq. 35 on the ring st->X using st->Y, and the
+ * leapfrog position update of eqs. 27-28 (positions and half-step velocities);
+ * advances st->head.  Used by xlbomd_step; exposed for testing. */
+xlbomd_status xlbomd_integrate(xlbomd_handle h, xlbomd_md_state *st);
+
+/* One or more KSA-XL-BOMD NVE steps (eqs. 27-30, 35, 37): for each step
+ * integrate, evaluate F, P0 and the kernel at the new state, forces, and the
+ * closing half kick.  rep: host array of n_steps reports (nullable). */
+xlbomd_status xlbomd_step(xlbomd_handle h, xlbomd_md_state *st, int n_steps,
+                          xlbomd_report *rep);
+
+/* Initial state for xlbomd_step: evaluates P0, Y and the accelerations at
+ * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5). */
+xlbomd_status xlbomd_md_init(xlbomd_handle h, xlbomd_md_state *st);
+
+/* Ground state by Newton-Krylov iterations X <- X - lam Y (the paper's KSA SCF),
+ * preceded by linear mixing until ||P0 - X|| < mix_tol.  X: DEVICE n x n in/out
+ * (initial guess in, D_min out).  Returns XLBOMD_E_NOCONV past max_iter. */
+xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, int m, double tol, int max_iter,
+                         double *residual);
+
+/* Diagnostic: C = A B (+ optional symmetric-output mode) with the chain GEMM
+ * of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric).  In
+ * split modes the operands are rounded to FP32 storage first, exactly as the
+ * chains store their matrices.  For testing and timing the MFMA kernels. */
+xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, double *Cout,
+                            int sym_out, int reps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XLBOMD_H */

@@ -1,0 +1,256 @@
+"""ctypes binding of libxlbomd (argument marshalling only).
+
+Each method forwards torch device tensors (their data pointers) to the C ABI
+declared in include/xlbomd.h.  No arithmetic of the method happens here.  The
+library must have been built (``python -m paper_2303_00689_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxlbomd.so")
+
+PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3}
+
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
+          -5: "E_STATE", -6: "E_NOMEM"}
+
+# symbols declared in include/xlbomd.h
+SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
+           "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm",
+           "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
+           "xlbomd_step", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul"]
+
+
+class Model(C.Structure):
+    _fields_ = [(name, C.c_double) for name in
+                ("eps_s", "eps_p", "t0", "r0_hop", "lam_hop", "coul_k", "coul_a", "noise_amp",
+                 "z_core", "a_rep", "r0_rep", "rho_rep", "mass")] + [("j55", C.c_double * 55)]
+
+
+class System(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("n_elec", C.c_double),
+                ("onecenter", C.POINTER(C.c_double)), ("noise55", C.POINTER(C.c_float)),
+                ("model", Model)]
+
+
+class Params(C.Structure):
+    _fields_ = [("prec", C.c_int), ("T_e", C.c_double), ("m", C.c_int), ("krylov_tol", C.c_double),
+                ("dt", C.c_double), ("kappa", C.c_double), ("alpha", C.c_double),
+                ("c", C.c_double * 7)]
+
+
+class MDStateC(C.Structure):
+    _fields_ = [("R", C.c_void_p), ("V", C.c_void_p), ("A", C.c_void_p), ("X", C.c_void_p),
+                ("Y", C.c_void_p), ("head", C.c_int), ("mu", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("E_tot", "KE", "U", "TS", "T_ion", "mu", "W0", "relres")] + \
+               [("rank", C.c_int), ("status", C.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libxlbomd.so and declare the prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    pd = C.POINTER(C.c_double)
+    pi = C.POINTER(C.c_int)
+    lib.xlbomd_create.argtypes = [C.POINTER(System), C.POINTER(Params), vp, C.POINTER(vp)]
+    lib.xlbomd_destroy.argtypes = [vp]
+    lib.xlbomd_last_error.argtypes = [vp]
+    lib.xlbomd_last_error.restype = C.c_char_p
+    lib.xlbomd_n_orb.argtypes = [vp]
+    lib.xlbomd_n_orb.restype = i
+    lib.xlbomd_set_geometry.argtypes = [vp, vp]
+    lib.xlbomd_hcore.argtypes = [vp, vp]
+    lib.xlbomd_fock.argtypes = [vp, vp, vp, i]
+    lib.xlbomd_fermi_dm.argtypes = [vp, vp, pd, vp, pd]
+    lib.xlbomd_dm_response.argtypes = [vp, vp, vp]
+    lib.xlbomd_krylov_kernel.argtypes = [vp, vp, vp, i, d, vp, pi, pd]
+    lib.xlbomd_forces.argtypes = [vp, vp, vp, vp, pd]
+    lib.xlbomd_integrate.argtypes = [vp, C.POINTER(MDStateC)]
+    lib.xlbomd_step.argtypes = [vp, C.POINTER(MDStateC), i, C.POINTER(Report)]
+    lib.xlbomd_md_init.argtypes = [vp, C.POINTER(MDStateC)]
+    lib.xlbomd_scf.argtypes = [vp, vp, i, d, i, pd]
+    lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
+    for name in SYMBOLS:
+        if name not in ("xlbomd_last_error", "xlbomd_n_orb"):
+            getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+class XLBOMDError(RuntimeError):
+    pass
+
+
+def _ptr(t, n_elem=None, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise XLBOMDError("expected a device tensor")
+    if not t.is_contiguous():
+        raise XLBOMDError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise XLBOMDError(f"expected dtype {dtype}, got {t.dtype}")
+    if n_elem is not None and t.numel() != n_elem:
+        raise XLBOMDError(f"expected {n_elem} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class MDState:
+    """Device state of xlbomd_step (R, V, A: N x 3; X: 7 x n x n ring; Y: n x n)."""
+
+    def __init__(self, R, V, A, X, Y, head=0, mu=float("nan")):
+        self.R, self.V, self.A, self.X, self.Y = R, V, A, X, Y
+        self.head, self.mu = head, mu
+
+    def _c(self, h):
+        import torch
+        N, n = h.n_atoms, h.n
+        f = torch.float64
+        return MDStateC(_ptr(self.R, 3 * N, f), _ptr(self.V, 3 * N, f), _ptr(self.A, 3 * N, f),
+                        _ptr(self.X, 7 * n * n, f), _ptr(self.Y, n * n, f), self.head, self.mu)
+
+    def x_current(self):
+        return self.X[self.head]
+
+
+class Handle:
+    """One system on the current device (see include/xlbomd.h for semantics)."""
+
+    def __init__(self, n_atoms, n_elec, onecenter, noise55, model, *, prec="fp64", T_e=3000.0,
+                 m=4, dt=0.5, kappa=1.84, alpha=0.0055,
+                 c=(-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0), krylov_tol=0.0, stream=None):
+        self.lib = load()
+        self.n_atoms = int(n_atoms)
+        self.n = 4 * self.n_atoms
+        self._oc = np.ascontiguousarray(onecenter, dtype=np.float64)
+        if self._oc.shape != (self.n_atoms, 5):
+            raise XLBOMDError("onecenter must be (n_atoms, 5)")
+        npair = self.n_atoms * (self.n_atoms - 1) // 2
+        self._noise = np.ascontiguousarray(noise55, dtype=np.float32) if npair else np.zeros((0, 55), np.float32)
+        if self._noise.shape != (npair, 55):
+            raise XLBOMDError("noise55 must be (n_pair, 55)")
+        mdl = Model()
+        for name, _ in Model._fields_[:-1]:
+            setattr(mdl, name, float(getattr(model, name)))
+        j = np.asarray(model.j55(), dtype=np.float64)
+        for k in range(55):
+            mdl.j55[k] = j[k]
+        sysc = System(self.n_atoms, float(n_elec), self._oc.ctypes.data_as(C.POINTER(C.c_double)),
+                      self._noise.ctypes.data_as(C.POINTER(C.c_float)), mdl)
+        prm = Params(PREC[prec] if isinstance(prec, str) else int(prec), float(T_e), int(m),
+                     float(krylov_tol), float(dt), float(kappa), float(alpha), (C.c_double * 7)(*c))
+        self.prec = prec
+        self.m = int(m)
+        h = C.c_void_p()
+        st = self.lib.xlbomd_create(C.byref(sysc), C.byref(prm), C.c_void_p(stream or 0), C.byref(h))
+        if st != 0:
+            raise XLBOMDError(f"xlbomd_create failed: {STATUS.get(st, st)}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.xlbomd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self.lib.xlbomd_last_error(self.h).decode()
+            raise XLBOMDError(f"{what}: {STATUS.get(st, st)}: {msg}")
+
+    def _mat(self, t):
+        import torch
+        return _ptr(t, self.n * self.n, torch.float64)
+
+    def set_geometry(self, R):
+        import torch
+        self._check(self.lib.xlbomd_set_geometry(self.h, _ptr(R, 3 * self.n_atoms, torch.float64)),
+                    "set_geometry")
+
+    def hcore(self, H):
+        self._check(self.lib.xlbomd_hcore(self.h, self._mat(H)), "hcore")
+
+    def fock(self, P, F, include_h=True):
+        self._check(self.lib.xlbomd_fock(self.h, self._mat(P), self._mat(F), int(bool(include_h))), "fock")
+
+    def fermi_dm(self, F, P, mu=float("nan")):
+        m = C.c_double(mu)
+        S = C.c_double(0.0)
+        self._check(self.lib.xlbomd_fermi_dm(self.h, self._mat(F), C.byref(m), self._mat(P), C.byref(S)),
+                    "fermi_dm")
+        return m.value, S.value
+
+    def dm_response(self, F1, P1):
+        self._check(self.lib.xlbomd_dm_response(self.h, self._mat(F1), self._mat(P1)), "dm_response")
+
+    def krylov_kernel(self, X, P0, m, Y, tol=0.0):
+        r = C.c_int(0)
+        rel = C.c_double(0.0)
+        self._check(self.lib.xlbomd_krylov_kernel(self.h, self._mat(X), self._mat(P0), int(m), float(tol),
+                                                  self._mat(Y), C.byref(r), C.byref(rel)), "krylov_kernel")
+        return r.value, rel.value
+
+    def forces(self, P0, X, frc):
+        import torch
+        e = (C.c_double * 4)()
+        self._check(self.lib.xlbomd_forces(self.h, self._mat(P0), self._mat(X),
+                                           _ptr(frc, 3 * self.n_atoms, torch.float64), e), "forces")
+        return list(e)
+
+    def integrate(self, state: MDState):
+        sc = state._c(self)
+        self._check(self.lib.xlbomd_integrate(self.h, C.byref(sc)), "integrate")
+        state.head, state.mu = sc.head, sc.mu
+
+    def md_init(self, state: MDState):
+        sc = state._c(self)
+        self._check(self.lib.xlbomd_md_init(self.h, C.byref(sc)), "md_init")
+        state.head, state.mu = sc.head, sc.mu
+
+    def step(self, state: MDState, n_steps=1, report=True):
+        sc = state._c(self)
+        reps = (Report * max(n_steps, 1))() if report else None
+        self._check(self.lib.xlbomd_step(self.h, C.byref(sc), int(n_steps), reps), "step")
+        state.head, state.mu = sc.head, sc.mu
+        if not report:
+            return None
+        return [{k: getattr(r, k) for k, _ in Report._fields_} for r in reps[:n_steps]]
+
+    def matmul(self, A, B, Cout, sym_out=False, reps=1):
+        self._check(self.lib.xlbomd_matmul(self.h, self._mat(A), self._mat(B), self._mat(Cout),
+                                           int(bool(sym_out)), int(reps)), "matmul")
+
+    def scf(self, X, m=20, tol=1e-10, max_iter=100):
+        res = C.c_double(0.0)
+        self._check(self.lib.xlbomd_scf(self.h, self._mat(X), int(m), float(tol), int(max_iter),
+                                        C.byref(res)), "scf")
+        return res.value
+
+
+def handle_for(system, settings: dict, prec="fp64", stream=None) -> Handle:
+    """Handle for a synthetic cluster (``synth.System``) with workload settings."""
+    return Handle(system.n_atoms, system.n_elec, system.onecenter, system.noise, system.params,
+                  prec=prec, T_e=settings["T_e"], m=settings["m"], dt=settings["dt"], stream=stream)

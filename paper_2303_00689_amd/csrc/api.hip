@@ -1,0 +1,927 @@
+// C ABI of libxlbomd: handle, workspace and the host orchestration of the
+// hot path.  Every arithmetic step runs in the kernels of gemm_*.hip,
+// blas1.hip and pairs.hip; this file only sequences them, keeps the chain
+// cache and moves a few scalars between host and device.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/xlbomd.h"
+#include "common.h"
+
+using namespace xl;
+
+namespace {
+
+constexpr int LMAX = 24;     // maximum number of recursion levels
+constexpr int MMAX = 32;     // maximum Krylov rank
+constexpr double KB = 8.617333262e-5;           // eV / K
+constexpr double ACC = 9.648533e-3;             // (eV / (Angstrom amu)) -> Angstrom / fs^2
+constexpr double VMAX = 1.2;                    // bound on |v| at the start of the chain
+// odd Taylor coefficients of tanh(v) / v in powers of v^2 (degree-5 start)
+constexpr double TC0 = 1.0, TC1 = -1.0 / 3.0, TC2 = 2.0 / 15.0;
+
+// device scalar slots
+enum Slot {
+  S_LOHI = 0,      // 2
+  S_TAU = 4,       // 8: tau_0..tau_4
+  S_MU1 = 16,      // 5: dmu, c, 2/(1+c), flag, 1-c
+  S_NEG1 = 24,     // -2/(1+c)
+  S_T01 = 28,      // 2: Tr D1, Tr D1(I-D1)
+  S_MU2 = 32,      // 5
+  S_NEG2 = 40,
+  S_SQC = 44,      // sqrt(c c2)
+  S_TRM = 48,      // Tr M
+  S_TRR = 50,      // Tr R (response)
+  S_CAN = 52,      // -Tr R / Tr M
+  S_TRD = 54,      // final trace of D
+  S_ENER = 60,     // 3 energies
+  S_DOTS = 64,     // 40 dots
+  S_KO = 128,      // Krylov O, 32 x 32 (row stride 32)
+  S_KRHS = 1152,   // 32
+  S_KCOEF = 1184,  // 32
+  S_KRES = 1216,   // 3: resid^2, ||W0||^2, singular
+  S_ORTH = 1220,   // 33 orthogonalisation coefficients
+  S_TOTAL = 1280
+};
+
+__global__ void k_scal_misc(const double *mu1, const double *mu2, const double *trm, double *neg1,
+                            double *neg2, double *sqc) {
+  if (threadIdx.x) return;
+  if (neg1) *neg1 = -mu1[2];
+  if (neg2) *neg2 = -mu2[2];
+  if (sqc) *sqc = sqrt(mu1[1] * mu2[1]);
+  (void)trm;
+}
+
+__global__ void k_canon(const double *trR, const double *trM, double *out) {
+  if (threadIdx.x) return;
+  *out = (*trM > 0.0) ? -(*trR) / (*trM) : 0.0;
+}
+
+// out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device
+__global__ void k_orth(size_t n2, int k, const double *v, const double *const *Vs, const double *c,
+                       double *out) {
+  __shared__ double cs[MMAX];
+  __shared__ const double *vp[MMAX];
+  if (threadIdx.x < k) {
+    cs[threadIdx.x] = c[threadIdx.x];
+    vp[threadIdx.x] = Vs[threadIdx.x];
+  }
+  __syncthreads();
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double x = v[i];
+    for (int j = 0; j < k; ++j) x -= cs[j] * vp[j][i];
+    out[i] = x;
+  }
+}
+
+// copy the dots results into row k of O and rhs
+__global__ void k_store_orow(int k, const double *d, double *O, double *rhs) {
+  if (threadIdx.x) return;
+  for (int j = 0; j <= k; ++j) {
+    O[k * 32 + j] = d[j];
+    O[j * 32 + k] = d[j];
+  }
+  rhs[k] = d[k + 1];
+}
+
+inline void cheb_lin(double lmax, double &a, double &b, double &e0) {
+  // a + b*lambda minimising max |1 - lambda (a + b lambda)| on [1, lmax]
+  const double d = lmax - 1.0;
+  if (d < 1e-12) {
+    a = 1.0;
+    b = 0.0;
+    e0 = d;
+    return;
+  }
+  const double s = (lmax + 1.0) / d;
+  const double t2 = 2.0 * s * s - 1.0;
+  const double c2 = 8.0 / (d * d) / t2;
+  const double c1 = -8.0 * (lmax + 1.0) / (d * d) / t2;
+  a = -c1;
+  b = -c2;
+  e0 = 1.0 / t2;
+}
+
+}  // namespace
+
+struct xlbomd_ctx {
+  int N = 0, n = 0;
+  size_t n2 = 0;
+  double n_elec = 0, n_occ = 0, beta = 0;
+  xlbomd_params prm{};
+  xlbomd_model model{};
+  hipStream_t s = nullptr;
+  int prec = 0, is32 = 0;
+  size_t esz = 8;
+  std::string err;
+  bool geom = false;
+  // device buffers
+  double *R = nullptr, *onecenter = nullptr, *j55 = nullptr;
+  float *noise_t = nullptr;
+  double *pk = nullptr, *part = nullptr, *pk3 = nullptr, *fpart = nullptr, *epart = nullptr;
+  double *dscal = nullptr, *red = nullptr, *frc = nullptr;
+  const double **dptr = nullptr;  // device pointer arrays (for lincomb / orth)
+  // chain storage (chain element type)
+  void *Yc[LMAX + 1] = {}, *Zc[LMAX] = {};
+  void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr;
+  void *D = nullptr, *M = nullptr, *Qs = nullptr;
+  void *w[8] = {};
+  int L = 0;
+  bool chain_valid = false;
+  double mu_chain = 0.0;
+  // FP64 work
+  double *f64[6] = {};
+  double *Vk[MMAX] = {}, *Wk[MMAX] = {};
+  int kalloc = 0;
+  // stats
+  long long n_gemm = 0;
+};
+
+namespace {
+
+xlbomd_status fail(xlbomd_ctx *c, xlbomd_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(c, x)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      return fail(c, XLBOMD_E_HIP, "%s failed: %s", #x, hipGetErrorString(e_));          \
+  } while (0)
+
+bool dev_alloc(void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
+
+// ------------------------------------------------------------------ GEMM helper
+void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, int sym,
+        const void *C1 = nullptr, double b1 = 0.0, const void *C2 = nullptr, double b2 = 0.0,
+        double gamma = 0.0, int btrans = 0, const void *A2 = nullptr, const void *B2 = nullptr) {
+  GemmArgs g{};
+  g.n = c->n;
+  g.nprod = A2 ? 2 : 1;
+  g.A[0] = A;
+  g.B[0] = B;
+  g.A[1] = A2;
+  g.B[1] = B2;
+  g.btrans = btrans;
+  g.C1 = C1;
+  g.C2 = C2;
+  g.out = out;
+  g.alpha = alpha;
+  g.beta1 = b1;
+  g.beta2 = b2;
+  g.gamma = gamma;
+  g.sym = sym;
+  if (c->prec == XLBOMD_FP64)
+    gemm_f64(g, c->s);
+  else
+    gemm_split(g, c->prec, c->s);
+  ++c->n_gemm;
+}
+
+PairSys pairsys(xlbomd_ctx *c) {
+  PairSys p{};
+  p.n_atoms = c->N;
+  p.n_tiles = (c->N + 15) / 16;
+  p.R = c->R;
+  p.onecenter = c->onecenter;
+  p.noise_t = c->noise_t;
+  p.j55 = c->j55;
+  const xlbomd_model &m = c->model;
+  p.eps_s = m.eps_s;
+  p.eps_p = m.eps_p;
+  p.t0 = m.t0;
+  p.r0_hop = m.r0_hop;
+  p.lam_hop = m.lam_hop;
+  p.coul_k = m.coul_k;
+  p.coul_a = m.coul_a;
+  p.noise_amp = m.noise_amp;
+  p.z_core = m.z_core;
+  p.a_rep = m.a_rep;
+  p.r0_rep = m.r0_rep;
+  p.rho_rep = m.rho_rep;
+  return p;
+}
+
+xlbomd_status get_scalars(xlbomd_ctx *c, int slot, int cnt, double *out) {
+  HIPCHK(c, hipMemcpyAsync(out, c->dscal + slot, sizeof(double) * cnt, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return XLBOMD_OK;
+}
+
+double eps_for_prec(int prec) {
+  switch (prec) {
+    case XLBOMD_FP64: return 1e-16;
+    case XLBOMD_BF16X6: return 1e-8;
+    case XLBOMD_FP16X3: return 1e-7;
+    default: return 1e-6;
+  }
+}
+
+// ------------------------------------------------------------------ Fermi chain
+// D = (exp(beta (F - mu I)) + I)^-1 (one spin) by the centred tanh-doubling
+// recursion Y_{i+1} = 2 Y_i (I + 4 Y_i^2)^-1 started from a degree-5 Taylor
+// polynomial of tanh at v = -beta (F - mu)/2^(L+1); D = I/2 + Y_L.  The inverse
+// of every level is a Newton-Schulz iteration started from the best linear
+// polynomial of T = I + 4 Y^2 on its spectral interval.
+xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, double hi) {
+  const int n = c->n;
+  const double beta = c->beta;
+  const double rho = beta * std::max(hi - mu, mu - lo) / 2.0;
+  int L = (int)std::ceil(std::log2(std::max(rho / VMAX, 1.0)));
+  if (L < 1) L = 1;
+  if (L > LMAX) return fail(c, XLBOMD_E_ARG, "spectral range too wide (needs %d levels)", L);
+  c->L = L;
+  const double vb = std::min(rho / std::ldexp(1.0, L), VMAX);
+  const double sc = -beta / std::ldexp(1.0, L + 1);
+  void *V = c->Vst, *S = c->Sst, *P = c->Pst;
+  // V = sc (F - mu I), in chain precision
+  if (c->is32) {
+    convert((int)c->n2, F, 0, c->w[0], 1, c->s);
+    axpbyI_dev(n, nullptr, sc, c->w[0], nullptr, 0.0, nullptr, nullptr, -sc * mu, V, 1, c->s);
+  } else {
+    axpbyI_dev(n, nullptr, sc, F, nullptr, 0.0, nullptr, nullptr, -sc * mu, V, 0, c->s);
+  }
+  mm(c, V, V, S, 1.0, 1);                                   // S = V^2
+  mm(c, S, S, P, TC2, 1, S, TC1, nullptr, 0.0, TC0);        // P = c0 I + c1 S + c2 S^2
+  mm(c, V, P, c->Yc[0], 0.5, 1);                            // Y0 = V P / 2
+  double yb = 0.5 * vb * (TC0 + TC1 * vb * vb + TC2 * vb * vb * vb * vb);
+  const double eps = eps_for_prec(c->prec);
+  for (int i = 0; i < L; ++i) {
+    void *Y = c->Yc[i];
+    void *Si = c->w[1], *E = c->w[2], *Za = c->w[3], *Zb = c->w[4];
+    mm(c, Y, Y, Si, 1.0, 1);
+    double a, b, e0;
+    cheb_lin(1.0 + 4.0 * yb * yb, a, b, e0);
+    int k = 1;
+    double e = e0 * e0;
+    while (e > eps && k < 8) {
+      e = e * e;
+      ++k;
+    }
+    // E0 = I - a T - b T^2 with T = I + 4S, T^2 = I + 8S + 16 S^2
+    mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
+    // Z1 = Z0 (I + E0), Z0 = (a + b) I + 4 b S
+    mm(c, Si, E, Za, 4.0 * b, 1, Si, 4.0 * b, E, a + b, a + b);
+    for (int it = 1; it < k; ++it) {
+      mm(c, Si, Za, E, -4.0, 1, Za, -1.0, nullptr, 0.0, 1.0);   // E = I - T Z
+      mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);                        // Z <- Z + Z E
+      std::swap(Za, Zb);
+    }
+    // keep Z_i in the cache
+    if (Za != c->w[3]) std::swap(c->w[3], c->w[4]);
+    std::swap(c->Zc[i], c->w[3]);
+    mm(c, Y, c->Zc[i], c->Yc[i + 1], 2.0, 1);
+    yb = 2.0 * yb / (1.0 + 4.0 * yb * yb);
+  }
+  // D = I/2 + Y_L
+  axpbyI_dev(n, nullptr, 1.0, c->Yc[L], nullptr, 0.0, nullptr, nullptr, 0.5, c->D, c->is32, c->s);
+  c->mu_chain = mu;
+  return XLBOMD_OK;
+}
+
+// Exact chemical-potential shift: D(mu + dmu) = D (c I + (1 - c) D)^-1, c = exp(-beta dmu).
+// Pass 1 solves the trace series sum_k (1-c)^k Tr[D (I-D)^k] = N_occ (k < 5); pass 2
+// is one Newton step with its own exact shift.  Leaves D, M = D(I - D), and
+// Qs = sqrt(c1 c2) Q1^-1 Q2^-1 for the response.
+xlbomd_status mu_shift(xlbomd_ctx *c) {
+  const int n = c->n, i32 = c->is32;
+  hipStream_t s = c->s;
+  void *D = c->D, *D2 = c->w[0], *D3 = c->w[1], *Mx = c->w[2], *Nx = c->w[3], *N2 = c->w[4],
+       *MN = c->w[5];
+  mm(c, D, D, D2, 1.0, 1);
+  mm(c, D, D2, D3, 1.0, 1);
+  axpby((int)c->n2, 1.0, D, -1.0, D2, Mx, i32, s);                                  // M
+  axpbyI_dev(n, nullptr, -1.0, D, nullptr, 0.0, nullptr, nullptr, 1.0, Nx, i32, s);  // N = I - D
+  axpbyI_dev(n, nullptr, -2.0, D, nullptr, 1.0, D2, nullptr, 1.0, N2, i32, s);      // N^2
+  axpbyI_dev(n, nullptr, 1.0, D, nullptr, -2.0, D2, nullptr, 0.0, MN, i32, s);      // D - 2D^2
+  axpby((int)c->n2, 1.0, MN, 1.0, D3, MN, i32, s);                                  // + D^3
+  trace(n, D, c->dscal + S_TAU, i32, c->red, s);
+  trace(n, Mx, c->dscal + S_TAU + 1, i32, c->red, s);
+  {
+    const void *X[3] = {Mx, Mx, MN};
+    const void *Y[3] = {Nx, N2, N2};
+    dots((int)c->n2, 3, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
+  }
+  mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->dscal + S_MU1, s);
+  hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU1, nullptr,
+                     c->dscal + S_NEG1, nullptr, nullptr);
+  // Q = c I + (1 - c) D ; Newton-Schulz from Z0 = 2/(1+c) I (first iteration elementwise)
+  void *Q = c->w[0], *E = c->w[1], *Za = c->w[2], *Zb = c->w[3];
+  axpbyI_dev(n, c->dscal + S_MU1 + 4, 0.0, D, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 1, 0.0, Q, i32, s);
+  axpbyI_dev(n, c->dscal + S_NEG1, 0.0, Q, nullptr, 0.0, nullptr, nullptr, 1.0, E, i32, s);
+  axpbyI_dev(n, c->dscal + S_MU1 + 2, 0.0, E, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 2, 0.0, Za, i32, s);
+  for (int it = 1; it < 4; ++it) {
+    mm(c, Q, Za, E, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
+    mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);
+    std::swap(Za, Zb);
+  }
+  void *Q1i = Za;
+  void *D1 = (Za == c->w[2]) ? c->w[3] : c->w[2];   // free buffer
+  mm(c, D, Q1i, D1, 1.0, 1);
+  // pass 2
+  void *D1sq = c->w[4], *M1 = c->w[5];
+  mm(c, D1, D1, D1sq, 1.0, 1);
+  axpby((int)c->n2, 1.0, D1, -1.0, D1sq, M1, i32, s);
+  trace(n, D1, c->dscal + S_T01, i32, c->red, s);
+  trace(n, M1, c->dscal + S_T01 + 1, i32, c->red, s);
+  mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->dscal + S_MU2, s);
+  hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU2, nullptr,
+                     nullptr, c->dscal + S_NEG2, c->dscal + S_SQC);
+  void *Q2 = c->w[0], *E2 = c->w[1], *Z2a = c->w[4], *Z2b = c->w[5];
+  axpbyI_dev(n, c->dscal + S_MU2 + 4, 0.0, D1, nullptr, 0.0, nullptr, c->dscal + S_MU2 + 1, 0.0, Q2, i32, s);
+  axpbyI_dev(n, c->dscal + S_NEG2, 0.0, Q2, nullptr, 0.0, nullptr, nullptr, 1.0, E2, i32, s);
+  axpbyI_dev(n, c->dscal + S_MU2 + 2, 0.0, E2, nullptr, 0.0, nullptr, c->dscal + S_MU2 + 2, 0.0, Z2a, i32, s);
+  mm(c, Q2, Z2a, E2, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
+  mm(c, Z2a, E2, Z2b, 1.0, 1, Z2a, 1.0);
+  // D <- D1 Z2 ; Qs = sqrt(c1 c2) Q1^-1 Z2
+  mm(c, D1, Z2b, D, 1.0, 1);
+  mm(c, Q1i, Z2b, c->Qs, 1.0, 1);
+  axpbyI_dev(n, c->dscal + S_SQC, 0.0, c->Qs, nullptr, 0.0, nullptr, nullptr, 0.0, c->Qs, i32, s);
+  // M = D - D^2
+  mm(c, D, D, c->M, -1.0, 1, D, 1.0);
+  trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
+  trace(n, D, c->dscal + S_TRD, i32, c->red, s);
+  return XLBOMD_OK;
+}
+
+// canonical response of the cached chain to F1 (FP64, spin-summed F1): P1 = 2 D1
+xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
+  const int n = c->n, i32 = c->is32, L = c->L;
+  hipStream_t s = c->s;
+  const double sc = -c->beta / std::ldexp(1.0, L + 1);
+  void *V1 = c->w[0], *dS = c->w[1], *dS2 = c->w[2], *Y1 = c->w[3], *G = c->w[4], *H = c->w[5],
+       *Y1b = c->w[6];
+  if (i32) {
+    convert((int)c->n2, F1, 0, c->w[7], 1, s);
+    axpby((int)c->n2, sc, c->w[7], 0.0, nullptr, V1, 1, s);
+  } else {
+    axpby((int)c->n2, sc, F1, 0.0, nullptr, V1, 0, s);
+  }
+  mm(c, c->Vst, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, c->Vst);          // V V1 + V1 V
+  mm(c, c->Sst, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, c->Sst);          // S dS + dS S
+  axpby((int)c->n2, TC1, dS, TC2, dS2, dS2, i32, s);                                      // dP
+  mm(c, V1, c->Pst, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, c->Vst, dS2);         // (V1 P + V dP)/2
+  for (int i = 0; i < L; ++i) {
+    mm(c, c->Yc[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, c->Yc[i]);      // Y Y1 + Y1 Y
+    mm(c, G, c->Yc[i + 1], H, 1.0, 0);                                                     // G Y_{i+1}
+    axpby((int)c->n2, 2.0, Y1, -4.0, H, H, i32, s);                                       // 2 Y1 - 4 H
+    mm(c, c->Zc[i], H, Y1b, 1.0, 1);                                                       // Z_i (...)
+    std::swap(Y1, Y1b);
+  }
+  // chemical-potential shift map: Qs Y1 Qs
+  mm(c, c->Qs, Y1, G, 1.0, 0);
+  mm(c, c->Qs, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+  // canonical projection: R - (Tr R / Tr M) M
+  trace(n, H, c->dscal + S_TRR, i32, c->red, s);
+  hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
+                     c->dscal + S_CAN);
+  axpbyI_dev(n, nullptr, 2.0, H, c->dscal + S_CAN, 0.0, c->M, nullptr, 0.0, G, i32, s);
+  // b = 2 * (-TrR/TrM) -> scale M term by 2 as well
+  axpbyI_dev(n, nullptr, 1.0, G, c->dscal + S_CAN, 0.0, c->M, nullptr, 0.0, G, i32, s);
+  if (i32)
+    convert((int)c->n2, G, 1, P1, 0, s);
+  else
+    HIPCHK(c, hipMemcpyAsync(P1, G, c->n2 * 8, hipMemcpyDeviceToDevice, s));
+  return XLBOMD_OK;
+}
+
+xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
+  const int n = c->n;
+  gershgorin(n, F, c->dscal + S_LOHI, c->red, c->s);
+  double lohi[2];
+  xlbomd_status st = get_scalars(c, S_LOHI, 2, lohi);
+  if (st) return st;
+  if (!std::isfinite(lohi[0]) || !std::isfinite(lohi[1]))
+    return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
+  double mu = *mu_io;
+  bool cold = !std::isfinite(mu);
+  bool converged = false;
+  int clamped = 0;
+  for (int attempt = 0; attempt < 60 && !converged; ++attempt) {
+    if (cold) {
+      // bisection on Tr D(mu) with full chains until the bracket is within 0.4/beta
+      double a = lohi[0], b = lohi[1];
+      while (b - a > 0.4 / c->beta) {
+        const double mid = 0.5 * (a + b);
+        if ((st = run_chain(c, F, mid, lohi[0], lohi[1]))) return st;
+        trace(n, c->D, c->dscal + S_TRD, c->is32, c->red, c->s);
+        double tr;
+        if ((st = get_scalars(c, S_TRD, 1, &tr))) return st;
+        if (tr < c->n_occ)
+          a = mid;
+        else
+          b = mid;
+      }
+      mu = 0.5 * (a + b);
+      cold = false;
+    }
+    if ((st = run_chain(c, F, mu, lohi[0], lohi[1]))) return st;
+    if ((st = mu_shift(c))) return st;
+    double m1[5], m2[5];
+    if ((st = get_scalars(c, S_MU1, 5, m1))) return st;
+    if ((st = get_scalars(c, S_MU2, 5, m2))) return st;
+    if (m1[3] != 0.0 || m2[3] != 0.0) {
+      // the warm start was too far for the trace series: move by the clamped step,
+      // and fall back to bisection if that keeps happening
+      mu += m1[0] + (m1[3] != 0.0 ? 0.0 : m2[0]);
+      if (++clamped >= 3) {
+        cold = true;
+        clamped = 0;
+      }
+      continue;
+    }
+    mu += m1[0] + m2[0];
+    converged = true;
+  }
+  if (!converged) return fail(c, XLBOMD_E_NOCONV, "chemical potential search did not converge");
+  c->chain_valid = true;
+  *mu_io = mu;
+  // P = 2 D
+  if (c->is32) {
+    convert((int)c->n2, c->D, 1, P, 0, c->s);
+    axpby((int)c->n2, 2.0, P, 0.0, nullptr, P, 0, c->s);
+  } else {
+    axpby((int)c->n2, 2.0, c->D, 0.0, nullptr, P, 0, c->s);
+  }
+  if (sync_check) {
+    double tr;
+    if ((st = get_scalars(c, S_TRD, 1, &tr))) return st;
+    if (!std::isfinite(tr)) return fail(c, XLBOMD_E_NONFINITE, "non-finite density matrix");
+    if (std::fabs(tr - c->n_occ) > 1e-9 * c->n_occ + 1e-6 * (c->prec != XLBOMD_FP64))
+      return fail(c, XLBOMD_E_NOCONV, "trace %.15g differs from N_occ %.15g", tr, c->n_occ);
+  }
+  return XLBOMD_OK;
+}
+
+xlbomd_status ensure_krylov(xlbomd_ctx *c, int m) {
+  while (c->kalloc < m) {
+    const int k = c->kalloc;
+    if (!dev_alloc((void **)&c->Vk[k], c->n2 * 8) || !dev_alloc((void **)&c->Wk[k], c->n2 * 8))
+      return fail(c, XLBOMD_E_NOMEM, "Krylov workspace allocation failed");
+    ++c->kalloc;
+  }
+  return XLBOMD_OK;
+}
+
+xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, double tol, double *Y,
+                     int *rank_out, double *rel_out, double *w0_out) {
+  hipStream_t s = c->s;
+  const int n2 = (int)c->n2;
+  xlbomd_status st;
+  if (m < 0 || m > MMAX) return fail(c, XLBOMD_E_ARG, "m must be in [0, %d]", MMAX);
+  if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");
+  if ((st = ensure_krylov(c, m))) return st;
+  double *W0 = c->f64[0], *v = c->f64[1], *tmp = c->f64[2], *F1 = c->f64[3], *P1 = c->f64[4];
+  axpby(n2, 1.0, P0, -1.0, X, W0, 0, s);
+  {
+    const void *a[1] = {W0};
+    dots(n2, 1, a, a, c->dscal + S_KRES + 1, 0, c->red, s);
+  }
+  double nw0sq;
+  if ((st = get_scalars(c, S_KRES + 1, 1, &nw0sq))) return st;
+  if (w0_out) *w0_out = std::sqrt(nw0sq);
+  axpby(n2, 0.0, W0, 0.0, nullptr, Y, 0, s);
+  if (rank_out) *rank_out = 0;
+  if (rel_out) *rel_out = 0.0;
+  if (!(nw0sq > 0.0) || m == 0) {
+    if (rel_out) *rel_out = (m == 0 && nw0sq > 0.0) ? 1.0 : 0.0;
+    return XLBOMD_OK;
+  }
+  const double *src = W0;
+  double nsrc = std::sqrt(nw0sq);
+  int k = 0;
+  double rel = 1.0;
+  for (; k < m;) {
+    // classical Gram-Schmidt applied twice
+    HIPCHK(c, hipMemcpyAsync(v, src, c->n2 * 8, hipMemcpyDeviceToDevice, s));
+    for (int sweep = 0; sweep < 2 && k > 0; ++sweep) {
+      const void *xs[MMAX], *ys[MMAX];
+      for (int j = 0; j < k; ++j) {
+        xs[j] = c->Vk[j];
+        ys[j] = v;
+      }
+      for (int j0 = 0; j0 < k; j0 += 16)
+        dots(n2, std::min(16, k - j0), xs + j0, ys + j0, c->dscal + S_ORTH + j0, 0, c->red, s);
+      HIPCHK(c, hipMemcpyAsync(c->dptr, c->Vk, sizeof(double *) * k, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_orth, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+      std::swap(v, tmp);
+    }
+    {
+      const void *a[1] = {v};
+      dots(n2, 1, a, a, c->dscal + S_DOTS, 0, c->red, s);
+    }
+    double nv2;
+    if ((st = get_scalars(c, S_DOTS, 1, &nv2))) return st;
+    const double nv = std::sqrt(nv2);
+    if (!(nv > 1e-12 * nsrc)) break;  // breakdown: rank k
+    axpby(n2, 1.0 / nv, v, 0.0, nullptr, c->Vk[k], 0, s);
+    // W_k = J V_k = P1[G(V_k)] - V_k
+    PairSys ps = pairsys(c);
+    fock(ps, c->Vk[k], F1, 0, c->pk, c->part, s);
+    if ((st = response(c, F1, P1))) return st;
+    axpby(n2, 1.0, P1, -1.0, c->Vk[k], c->Wk[k], 0, s);
+    {
+      const void *xs[MMAX + 1], *ys[MMAX + 1];
+      for (int j = 0; j <= k; ++j) {
+        xs[j] = c->Wk[k];
+        ys[j] = c->Wk[j];
+      }
+      xs[k + 1] = c->Wk[k];
+      ys[k + 1] = W0;
+      const int tot = k + 2;
+      for (int j0 = 0; j0 < tot; j0 += 16)
+        dots(n2, std::min(16, tot - j0), xs + j0, ys + j0, c->dscal + S_DOTS + j0, 0, c->red, s);
+    }
+    hipLaunchKernelGGL(k_store_orow, dim3(1), dim3(64), 0, s, k, c->dscal + S_DOTS, c->dscal + S_KO,
+                       c->dscal + S_KRHS);
+    ++k;
+    krylov_solve(k, c->dscal + S_KO, c->dscal + S_KRHS, c->dscal + S_KCOEF, c->dscal + S_KRES, s);
+    double kres[3];
+    if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
+    rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
+    if (tol > 0.0 && rel < tol) break;
+    double okk;
+    if ((st = get_scalars(c, S_DOTS + k - 1, 1, &okk))) return st;
+    src = c->Wk[k - 1];
+    nsrc = std::sqrt(okk);
+  }
+  if (k > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->dptr, c->Vk, sizeof(double *) * k, hipMemcpyHostToDevice, s));
+    lincomb_dev(n2, k, c->dptr, c->dscal + S_KCOEF, Y, s);
+  }
+  if (rank_out) *rank_out = k;
+  if (rel_out) *rel_out = rel;
+  return XLBOMD_OK;
+}
+
+xlbomd_status energy_forces(xlbomd_ctx *c, const double *P0, const double *X, double *frc,
+                            double e[3]) {
+  PairSys ps = pairsys(c);
+  forces(ps, P0, X, frc, c->dscal + S_ENER, c->pk3, c->fpart, c->epart, c->s);
+  if (e) return get_scalars(c, S_ENER, 3, e);
+  return XLBOMD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *xlbomd_last_error(xlbomd_handle h) { return h ? h->err.c_str() : "null handle"; }
+int xlbomd_n_orb(xlbomd_handle h) { return h ? h->n : 0; }
+
+xlbomd_status xlbomd_destroy(xlbomd_handle c) {
+  if (!c) return XLBOMD_E_ARG;
+  hipStreamSynchronize(c->s);
+  auto f = [](void *p) {
+    if (p) hipFree(p);
+  };
+  f(c->R);
+  f(c->onecenter);
+  f(c->j55);
+  f(c->noise_t);
+  f(c->pk);
+  f(c->part);
+  f(c->pk3);
+  f(c->fpart);
+  f(c->epart);
+  f(c->dscal);
+  f(c->red);
+  f(c->frc);
+  f(c->dptr);
+  for (auto &p : c->Yc) f(p);
+  for (auto &p : c->Zc) f(p);
+  f(c->Vst);
+  f(c->Pst);
+  f(c->Sst);
+  f(c->D);
+  f(c->M);
+  f(c->Qs);
+  for (auto &p : c->w) f(p);
+  for (auto &p : c->f64) f(p);
+  for (int k = 0; k < c->kalloc; ++k) {
+    f(c->Vk[k]);
+    f(c->Wk[k]);
+  }
+  delete c;
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, void *stream,
+                            xlbomd_handle *out) {
+  if (!sys || !prm || !out) return XLBOMD_E_ARG;
+  *out = nullptr;
+  if (sys->n_atoms < 1 || !sys->onecenter || (sys->n_atoms > 1 && !sys->noise55)) return XLBOMD_E_ARG;
+  const double n = 4.0 * sys->n_atoms;
+  if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
+  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 3)
+    return XLBOMD_E_ARG;
+  xlbomd_ctx *c = new xlbomd_ctx();
+  c->N = sys->n_atoms;
+  c->n = 4 * c->N;
+  c->n2 = (size_t)c->n * c->n;
+  c->n_elec = sys->n_elec;
+  c->n_occ = 0.5 * sys->n_elec;
+  c->prm = *prm;
+  c->model = sys->model;
+  c->s = (hipStream_t)stream;
+  c->beta = 1.0 / (KB * prm->T_e);
+  c->prec = prm->prec;
+  c->is32 = prm->prec != XLBOMD_FP64;
+  c->esz = c->is32 ? 4 : 8;
+  const int N = c->N, T = (N + 15) / 16;
+  const int ntp = T * (T + 1) / 2;
+  bool ok = true;
+  auto A = [&](void **p, size_t bytes) { ok = ok && dev_alloc(p, bytes); };
+  A((void **)&c->R, sizeof(double) * 3 * N);
+  A((void **)&c->onecenter, sizeof(double) * 5 * N);
+  A((void **)&c->j55, sizeof(double) * 55);
+  A((void **)&c->noise_t, sizeof(float) * std::max<size_t>(noise_tile_floats(N), 1));
+  A((void **)&c->pk, sizeof(double) * 10 * N);
+  A((void **)&c->part, sizeof(double) * 10 * (size_t)N * (T + 1));
+  A((void **)&c->pk3, sizeof(double) * 30 * N);
+  A((void **)&c->fpart, sizeof(double) * std::max<size_t>(force_partial_doubles(N), 1));
+  A((void **)&c->epart, sizeof(double) * (energy_partial_doubles(N) + 8));
+  A((void **)&c->dscal, sizeof(double) * S_TOTAL);
+  A((void **)&c->red, sizeof(double) * (reduce_partials_capacity() + 2 * (size_t)c->n));
+  A((void **)&c->frc, sizeof(double) * 3 * N);
+  A((void **)&c->dptr, sizeof(double *) * 64);
+  const size_t mb = c->n2 * c->esz;
+  for (auto &p : c->Yc) A(&p, mb);
+  for (auto &p : c->Zc) A(&p, mb);
+  A(&c->Vst, mb);
+  A(&c->Pst, mb);
+  A(&c->Sst, mb);
+  A(&c->D, mb);
+  A(&c->M, mb);
+  A(&c->Qs, mb);
+  for (auto &p : c->w) A(&p, mb);
+  for (auto &p : c->f64) A((void **)&p, c->n2 * 8);
+  if (!ok) {
+    xlbomd_destroy(c);
+    return XLBOMD_E_NOMEM;
+  }
+  (void)ntp;
+  if (hipMemcpy(c->onecenter, sys->onecenter, sizeof(double) * 5 * N, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->j55, sys->model.j55, sizeof(double) * 55, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess) {
+    xlbomd_destroy(c);
+    return XLBOMD_E_HIP;
+  }
+  if (N > 1) {
+    const size_t npair = (size_t)N * (N - 1) / 2;
+    float *tmp = nullptr;
+    if (!dev_alloc((void **)&tmp, sizeof(float) * npair * 55)) {
+      xlbomd_destroy(c);
+      return XLBOMD_E_NOMEM;
+    }
+    hipMemcpy(tmp, sys->noise55, sizeof(float) * npair * 55, hipMemcpyHostToDevice);
+    repack_noise(N, tmp, c->noise_t, c->s);
+    hipStreamSynchronize(c->s);
+    hipFree(tmp);
+  }
+  if (hipGetLastError() != hipSuccess) {
+    xlbomd_destroy(c);
+    return XLBOMD_E_HIP;
+  }
+  *out = c;
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_set_geometry(xlbomd_handle c, const double *R) {
+  if (!c || !R) return XLBOMD_E_ARG;
+  HIPCHK(c, hipMemcpyAsync(c->R, R, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->s));
+  c->geom = true;
+  c->chain_valid = false;
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_hcore(xlbomd_handle c, double *H) {
+  if (!c || !H) return XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  hcore(pairsys(c), H, c->part, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_fock(xlbomd_handle c, const double *P, double *F, int include_h) {
+  if (!c || !P || !F || P == F) return c ? fail(c, XLBOMD_E_ARG, "bad fock arguments") : XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  fock(pairsys(c), P, F, include_h ? 1 : 0, c->pk, c->part, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_fermi_dm(xlbomd_handle c, const double *F, double *mu, double *P,
+                              double *entropy) {
+  if (!c || !F || !mu || !P || F == P) return c ? fail(c, XLBOMD_E_ARG, "bad fermi_dm arguments") : XLBOMD_E_ARG;
+  xlbomd_status st = fermi(c, F, mu, P, true);
+  if (st) return st;
+  if (entropy) *entropy = NAN;
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_dm_response(xlbomd_handle c, const double *F1, double *P1) {
+  if (!c || !F1 || !P1 || F1 == P1) return c ? fail(c, XLBOMD_E_ARG, "bad response arguments") : XLBOMD_E_ARG;
+  if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");
+  xlbomd_status st = response(c, F1, P1);
+  if (st) return st;
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_krylov_kernel(xlbomd_handle c, const double *X, const double *P0, int m, double tol,
+                                   double *Y, int *rank, double *relres) {
+  if (!c || !X || !P0 || !Y) return XLBOMD_E_ARG;
+  xlbomd_status st = krylov(c, X, P0, m, tol, Y, rank, relres, nullptr);
+  if (st) return st;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_forces(xlbomd_handle c, const double *P0, const double *X, double *frc,
+                            double *energy) {
+  if (!c || !P0 || !X || !frc) return XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  double e[3];
+  xlbomd_status st = energy_forces(c, P0, X, frc, e);
+  if (st) return st;
+  if (energy) {
+    energy[0] = e[0];
+    energy[1] = e[1];
+    energy[2] = e[2];
+    energy[3] = e[0] + e[1] + e[2];
+  }
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_integrate(xlbomd_handle c, xlbomd_md_state *st) {
+  if (!c || !st || !st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+  const int n2 = (int)c->n2;
+  const double *Xk[7];
+  for (int k = 0; k < 7; ++k) Xk[k] = st->X + (size_t)((st->head + k) % 7) * c->n2;
+  const int nh = (st->head + 6) % 7;
+  x_verlet(n2, Xk, st->Y, c->prm.kappa, c->prm.alpha, c->prm.c, st->X + (size_t)nh * c->n2, c->s);
+  st->head = nh;
+  kick_drift(3 * c->N, st->R, st->V, st->A, c->prm.dt, 1, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e[3], int *rank,
+                                    double *rel, double *w0) {
+  xlbomd_status s;
+  if ((s = xlbomd_set_geometry(c, st->R))) return s;
+  const double *X = st->X + (size_t)st->head * c->n2;
+  double *F = c->f64[5];
+  double *P0 = c->f64[4];
+  fock(pairsys(c), X, F, 1, c->pk, c->part, c->s);
+  // P0 lives in f64[4] only until the Krylov call, which reuses it: keep a copy in Vk? use Wk slots
+  double mu = st->mu;
+  if ((s = fermi(c, F, &mu, P0, true))) return s;
+  st->mu = mu;
+  // forces first (Krylov reuses f64[0..4])
+  if ((s = energy_forces(c, P0, X, c->frc, e))) return s;
+  accel(3 * c->N, c->frc, ACC / c->model.mass, st->A, c->s);
+  double *P0k = c->f64[5];  // F no longer needed
+  HIPCHK(c, hipMemcpyAsync(P0k, P0, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
+  if ((s = krylov(c, X, P0k, c->prm.m, c->prm.krylov_tol, st->Y, rank, rel, w0))) return s;
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
+  if (!c || !st || !st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+  // replicate X(t0) into every history slot
+  const double *X0 = st->X + (size_t)st->head * c->n2;
+  for (int k = 1; k < 7; ++k)
+    HIPCHK(c, hipMemcpyAsync(st->X + (size_t)((st->head + k) % 7) * c->n2, X0, c->n2 * 8,
+                             hipMemcpyDeviceToDevice, c->s));
+  double e[3];
+  int rank;
+  double rel, w0;
+  return evaluate_state(c, st, e, &rank, &rel, &w0);
+}
+
+xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep) {
+  if (!c || !st || n_steps < 0) return XLBOMD_E_ARG;
+  for (int k = 0; k < n_steps; ++k) {
+    xlbomd_status s;
+    if ((s = xlbomd_integrate(c, st))) return s;
+    double e[3];
+    int rank = 0;
+    double rel = 0, w0 = 0;
+    if ((s = evaluate_state(c, st, e, &rank, &rel, &w0))) return s;
+    kick_drift(3 * c->N, st->R, st->V, st->A, c->prm.dt, 0, c->s);
+    if (rep) {
+      // kinetic energy from V (host copy of a few KB)
+      std::vector<double> V(3 * c->N);
+      HIPCHK(c, hipMemcpyAsync(V.data(), st->V, sizeof(double) * 3 * c->N, hipMemcpyDeviceToHost, c->s));
+      HIPCHK(c, hipStreamSynchronize(c->s));
+      double ke = 0.0;
+      for (double v : V) ke += v * v;
+      ke *= 0.5 * c->model.mass / ACC;
+      xlbomd_report &r = rep[k];
+      r.KE = ke;
+      r.U = e[0] + e[1] + e[2];
+      r.TS = NAN;
+      r.E_tot = r.KE + r.U;
+      const int dof = std::max(3 * c->N - 3, 1);
+      r.T_ion = 2.0 * ke / (dof * KB);
+      r.mu = st->mu;
+      r.W0 = w0;
+      r.relres = rel;
+      r.rank = rank;
+      r.status = XLBOMD_OK;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_scf(xlbomd_handle c, double *X, int m, double tol, int max_iter, double *residual) {
+  if (!c || !X || m < 1 || m > MMAX - 2 || max_iter < 0) return XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  const int n2 = (int)c->n2;
+  xlbomd_status s;
+  // the Krylov kernel owns f64[0..4], Vk[0..m-1], Wk[0..m-1]; the SCF keeps its
+  // own matrices in the two slots after them
+  if ((s = ensure_krylov(c, m + 2))) return s;
+  double *F = c->f64[5];
+  double *Pm = c->Wk[m], *Ptrial = c->Wk[m + 1], *Ystep = c->Vk[m], *Xtrial = c->Vk[m + 1];
+  double mu = NAN;
+  auto resid = [&](const double *Xc, double *Pout, double &r) -> xlbomd_status {
+    fock(pairsys(c), Xc, F, 1, c->pk, c->part, c->s);
+    xlbomd_status q = fermi(c, F, &mu, Pout, true);
+    if (q) return q;
+    axpby(n2, 1.0, Pout, -1.0, Xc, c->f64[0], 0, c->s);
+    const void *a[1] = {c->f64[0]};
+    dots(n2, 1, a, a, c->dscal + S_DOTS, 0, c->red, c->s);
+    double r2;
+    q = get_scalars(c, S_DOTS, 1, &r2);
+    r = std::sqrt(r2);
+    return q;
+  };
+  // linear mixing settles into a stable fixed point; Newton-Krylov then converges fast
+  double r = 0.0;
+  const int max_mix = 50 * std::max(max_iter, 1);
+  for (int it = 0; it < max_mix; ++it) {
+    if ((s = resid(X, Pm, r))) return s;
+    if (r < 1e-2 || r <= tol) break;
+    axpby(n2, 0.96, X, 0.04, Pm, X, 0, c->s);
+  }
+  for (int it = 0; it < max_iter && r > tol; ++it) {
+    int rank;
+    double rel;
+    // the chain cached by the last resid() call belongs to the current X
+    if ((s = krylov(c, X, Pm, m, 0.0, Ystep, &rank, &rel, nullptr))) return s;
+    double lam = 1.0, rt = 0.0;
+    while (true) {
+      axpby(n2, 1.0, X, -lam, Ystep, Xtrial, 0, c->s);
+      if ((s = resid(Xtrial, Ptrial, rt))) return s;
+      if (rt < r || lam < 1e-4) break;
+      lam *= 0.5;
+    }
+    HIPCHK(c, hipMemcpyAsync(X, Xtrial, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(Pm, Ptrial, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
+    r = rt;
+  }
+  if (residual) *residual = r;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  if (!(r <= tol)) return fail(c, XLBOMD_E_NOCONV, "SCF residual %.3e above tolerance", r);
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_matmul(xlbomd_handle c, const double *A, const double *B, double *Cout, int sym_out,
+                            int reps) {
+  if (!c || !A || !B || !Cout || reps < 1) return XLBOMD_E_ARG;
+  const int n2 = (int)c->n2;
+  const void *a = A, *b = B;
+  void *o = Cout;
+  if (c->is32) {
+    convert(n2, A, 0, c->w[0], 1, c->s);
+    convert(n2, B, 0, c->w[1], 1, c->s);
+    a = c->w[0];
+    b = c->w[1];
+    o = c->w[2];
+  }
+  for (int r = 0; r < reps; ++r) mm(c, a, b, o, 1.0, sym_out ? 1 : 0);
+  if (c->is32) convert(n2, c->w[2], 1, Cout, 0, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+}  // extern "C"

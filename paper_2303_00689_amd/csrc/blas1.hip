@@ -1,0 +1,453 @@
+// Elementwise, reduction and scalar kernels of the hot path (all memory-bound
+// or latency-bound; FP64 accumulation everywhere).
+//
+// Reductions are deterministic: a fixed grid of RED_BLOCKS workgroups writes
+// one partial per block, and a single workgroup sums the partials in a fixed
+// order.  No floating-point atomics are used.
+#include "common.h"
+
+#include <cmath>
+
+namespace xl {
+namespace {
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int MAXK = 16;
+
+template <typename T>
+__device__ inline double ld(const void *p, size_t i) {
+  return (double)((const T *)p)[i];
+}
+
+template <typename T>
+__global__ void k_axpby(size_t n2, double a, const void *x, double b, const void *y, void *out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = a * ld<T>(x, i);
+    if (y) v += b * ld<T>(y, i);
+    ((T *)out)[i] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ void k_axpbyI(int n, const double *a_dev, double a, const void *x, const double *b_dev,
+                         double b, const void *y, const double *g_dev, double g, void *out) {
+  const double av = a_dev ? *a_dev : a;
+  const double bv = b_dev ? *b_dev : b;
+  const double gv = g_dev ? *g_dev : g;
+  const size_t n2 = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (x) v += av * ld<T>(x, i);
+    if (y) v += bv * ld<T>(y, i);
+    if (i / n == i % n) v += gv;
+    ((T *)out)[i] = (T)v;
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(size_t n2, const void *in, void *out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x)
+    ((TO *)out)[i] = (TO)((const TI *)in)[i];
+}
+
+// M <- (M + M^T)/2 by 32x32 tiles of the upper triangle (tile pairs staged in LDS)
+template <typename T>
+__global__ void k_symmetrize(int n, T *M) {
+  __shared__ double a[32][33], b[32][33];
+  const int T32 = (n + 31) / 32;
+  int bid = blockIdx.x, bi = 0, start = 0;
+  while (start + (T32 - bi) <= bid) {
+    start += T32 - bi;
+    ++bi;
+  }
+  const int bj = bi + (bid - start);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    int i = bi * 32 + r, j = bj * 32 + tx;
+    a[r][tx] = (i < n && j < n) ? (double)M[(size_t)i * n + j] : 0.0;
+    i = bj * 32 + r;
+    j = bi * 32 + tx;
+    b[r][tx] = (i < n && j < n) ? (double)M[(size_t)i * n + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    int i = bi * 32 + r, j = bj * 32 + tx;
+    const double v = 0.5 * (a[r][tx] + b[tx][r]);
+    if (i < n && j < n) M[(size_t)i * n + j] = (T)v;
+    i = bj * 32 + r;
+    j = bi * 32 + tx;
+    const double w = 0.5 * (b[r][tx] + a[tx][r]);
+    if (i < n && j < n && bi != bj) M[(size_t)i * n + j] = (T)w;
+  }
+}
+
+__global__ void k_lincomb(size_t n2, int k, const double *const *M, const double *coef, double *out) {
+  __shared__ double c[40];
+  __shared__ const double *mp[40];
+  if (threadIdx.x < k) {
+    c[threadIdx.x] = coef[threadIdx.x];
+    mp[threadIdx.x] = M[threadIdx.x];
+  }
+  __syncthreads();
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int j = 0; j < k; ++j) v += c[j] * mp[j][i];
+    out[i] = v;
+  }
+}
+
+__device__ inline double block_sum(double v, double *sh) {
+  // 256 threads
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+struct PtrPack {
+  const void *x[MAXK];
+  const void *y[MAXK];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dots_partial(size_t n2, int k, PtrPack pp, double *part) {
+  __shared__ double sh[4];
+  for (int a = 0; a < k; ++a) {
+    double v = 0.0;
+    const T *x = (const T *)pp.x[a];
+    const T *y = (const T *)pp.y[a];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+         i += (size_t)gridDim.x * blockDim.x)
+      v += (double)x[i] * (double)y[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) part[(size_t)a * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_final(int k, int nb, const double *part, double *res) {
+  __shared__ double sh[4];
+  for (int a = 0; a < k; ++a) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[(size_t)a * nb + b];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) res[a] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trace_partial(int n, const void *M, double *part) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    v += ld<T>(M, (size_t)i * n + i);
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// Gershgorin: one wavefront per row
+__global__ __launch_bounds__(256) void k_gersh_rows(int n, const double *F, double *lohi) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64)
+    if (j != row) s += fabs(F[(size_t)row * n + j]);
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) {
+    const double d = F[(size_t)row * n + row];
+    lohi[2 * row] = d - s;
+    lohi[2 * row + 1] = d + s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gersh_final(int n, const double *lohi, double *res) {
+  __shared__ double smin[256], smax[256];
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    lo = fmin(lo, lohi[2 * i]);
+    hi = fmax(hi, lohi[2 * i + 1]);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    res[0] = smin[0];
+    res[1] = smax[0];
+  }
+}
+
+// ---- chemical potential: solve sum_{k<5} (1-c)^k tau_k = n_occ for dmu, c = exp(-beta dmu),
+// by bisection on dmu in [-0.3/beta, 0.3/beta] (the truncated series is accurate there for
+// the warm starts of a trajectory).  out[0] = dmu, out[1] = c, out[2] = 2/(1+c) (Newton-Schulz
+// start for (cI + (1-c)D)^-1), out[3] = flag (1: root outside the bracket, clamped).
+__global__ void k_mu_series(const double *tau, double n_occ, double beta, double *out) {
+  if (threadIdx.x != 0) return;
+  auto g = [&](double dmu) {
+    const double x = -expm1(-beta * dmu);  // 1 - c
+    double s = 0.0, p = 1.0;
+    for (int k = 0; k < 5; ++k) {
+      s += p * tau[k];
+      p *= x;
+    }
+    return s - n_occ;
+  };
+  double lo = -0.3 / beta, hi = 0.3 / beta;
+  double flag = 0.0;
+  double dmu;
+  if (g(lo) > 0.0) {
+    dmu = lo;
+    flag = 1.0;
+  } else if (g(hi) < 0.0) {
+    dmu = hi;
+    flag = 1.0;
+  } else {
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (g(mid) < 0.0)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    dmu = 0.5 * (lo + hi);
+  }
+  const double c = exp(-beta * dmu);
+  out[0] = dmu;
+  out[1] = c;
+  out[2] = 2.0 / (1.0 + c);
+  out[3] = flag;
+  out[4] = 1.0 - c;
+}
+
+// Newton step on mu from t01 = (Tr D, Tr D(I-D)): dmu = (n_occ - t0) / (beta t1).
+// out layout as k_mu_series.
+__global__ void k_mu_newton(const double *t01, double n_occ, double beta, double *out) {
+  if (threadIdx.x != 0) return;
+  const double t0 = t01[0], t1 = t01[1];
+  double dmu = (t1 > 0.0) ? (n_occ - t0) / (beta * t1) : 0.0;
+  const double lim = 0.3 / beta;
+  double flag = 0.0;
+  if (dmu > lim) {
+    dmu = lim;
+    flag = 1.0;
+  }
+  if (dmu < -lim) {
+    dmu = -lim;
+    flag = 1.0;
+  }
+  const double c = exp(-beta * dmu);
+  out[0] = dmu;
+  out[1] = c;
+  out[2] = 2.0 / (1.0 + c);
+  out[3] = flag;
+  out[4] = 1.0 - c;
+}
+
+// Krylov: solve O coef = rhs (k x k, FP64, Gaussian elimination with partial
+// pivoting) and resid2 = ||sum W_i c_i - W0||^2 = c^T O c - 2 c^T rhs + ||W0||^2
+// (the last term is read from resid2[1] on entry).
+__global__ void k_krylov_solve(int k, const double *O, const double *rhs, double *coef,
+                               double *resid2) {
+  if (threadIdx.x != 0) return;
+  double a[32][33];
+  for (int i = 0; i < k; ++i) {
+    for (int j = 0; j < k; ++j) a[i][j] = O[i * 32 + j];
+    a[i][k] = rhs[i];
+  }
+  int singular = 0;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+    if (piv != c)
+      for (int j = 0; j <= k; ++j) {
+        const double t = a[c][j];
+        a[c][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+    if (a[c][c] == 0.0) {
+      singular = 1;
+      break;
+    }
+    for (int r = c + 1; r < k; ++r) {
+      const double f = a[r][c] / a[c][c];
+      for (int j = c; j <= k; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  double x[32];
+  for (int i = k - 1; i >= 0; --i) {
+    double s = singular ? 0.0 : a[i][k];
+    if (!singular) {
+      for (int j = i + 1; j < k; ++j) s -= a[i][j] * x[j];
+      s /= a[i][i];
+    }
+    x[i] = s;
+  }
+  double q = 0.0, l = 0.0;
+  for (int i = 0; i < k; ++i) {
+    coef[i] = x[i];
+    l += x[i] * rhs[i];
+    for (int j = 0; j < k; ++j) q += x[i] * O[i * 32 + j] * x[j];
+  }
+  resid2[0] = q - 2.0 * l + resid2[1];
+  resid2[2] = singular;
+}
+
+__global__ void k_xverlet(size_t n2, const double *X0, const double *X1, const double *X2,
+                          const double *X3, const double *X4, const double *X5, const double *X6,
+                          const double *Y, double kappa, double alpha, double c0, double c1,
+                          double c2, double c3, double c4, double c5, double c6, double *out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double x0 = X0[i], x1 = X1[i];
+    const double damp = c0 * x0 + c1 * x1 + c2 * X2[i] + c3 * X3[i] + c4 * X4[i] + c5 * X5[i] +
+                        c6 * X6[i];
+    out[i] = 2.0 * x0 - x1 - kappa * Y[i] + alpha * damp;
+  }
+}
+
+__global__ void k_kick_drift(int n3, double *R, double *V, const double *A, double dt, int drift) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  const double v = V[i] + 0.5 * dt * A[i];
+  V[i] = v;
+  if (drift) R[i] += dt * v;
+}
+
+__global__ void k_accel(int n3, const double *f, double s, double *A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) A[i] = f[i] * s;
+}
+
+inline int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+int reduce_partials_capacity() { return RED_BLOCKS * MAXK + 2 * 65536; }
+
+void axpby(int n2, double a, const void *x, double b, const void *y, void *out, int is32,
+           hipStream_t s) {
+  if (is32)
+    hipLaunchKernelGGL(k_axpby<float>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, a, x, b, y, out);
+  else
+    hipLaunchKernelGGL(k_axpby<double>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, a, x, b, y, out);
+}
+
+void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const double *b_dev, double b,
+                const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s) {
+  const size_t n2 = (size_t)n * n;
+  if (is32)
+    hipLaunchKernelGGL(k_axpbyI<float>, dim3(grid_for(n2)), dim3(256), 0, s, n, a_dev, a, x, b_dev, b, y,
+                       g_dev, g, out);
+  else
+    hipLaunchKernelGGL(k_axpbyI<double>, dim3(grid_for(n2)), dim3(256), 0, s, n, a_dev, a, x, b_dev, b,
+                       y, g_dev, g, out);
+}
+
+void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s) {
+  const dim3 g(grid_for(n2)), b(256);
+  if (in32 && out32)
+    hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (size_t)n2, in, out);
+  else if (in32)
+    hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (size_t)n2, in, out);
+  else if (out32)
+    hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (size_t)n2, in, out);
+  else
+    hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (size_t)n2, in, out);
+}
+
+void symmetrize(int n, void *M, int is32, hipStream_t s) {
+  const int T = (n + 31) / 32;
+  const int blocks = T * (T + 1) / 2;
+  if (is32)
+    hipLaunchKernelGGL(k_symmetrize<float>, dim3(blocks), dim3(256), 0, s, n, (float *)M);
+  else
+    hipLaunchKernelGGL(k_symmetrize<double>, dim3(blocks), dim3(256), 0, s, n, (double *)M);
+}
+
+void lincomb_dev(int n2, int k, const double *const *M, const double *coef, double *out,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, k, M, coef, out);
+}
+
+void dots(int n2, int k, const void *const *X, const void *const *Y, double *res, int is32,
+          double *partials, hipStream_t s) {
+  PtrPack pp{};
+  for (int i = 0; i < k; ++i) {
+    pp.x[i] = X[i];
+    pp.y[i] = Y[i];
+  }
+  int nb = grid_for(n2);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (is32)
+    hipLaunchKernelGGL(k_dots_partial<float>, dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+  else
+    hipLaunchKernelGGL(k_dots_partial<double>, dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, k, nb, partials, res);
+}
+
+void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+  if (is32)
+    hipLaunchKernelGGL(k_trace_partial<float>, dim3(nb), dim3(256), 0, s, n, M, partials);
+  else
+    hipLaunchKernelGGL(k_trace_partial<double>, dim3(nb), dim3(256), 0, s, n, M, partials);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, 1, nb, partials, res);
+}
+
+void gershgorin(int n, const double *F, double *res, double *partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_gersh_rows, dim3((n + 3) / 4), dim3(256), 0, s, n, F, partials);
+  hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(256), 0, s, n, partials, res);
+}
+
+void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_series, dim3(1), dim3(64), 0, s, tau, n_occ, beta, out);
+}
+
+void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_newton, dim3(1), dim3(64), 0, s, t01, n_occ, beta, out);
+}
+
+void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_krylov_solve, dim3(1), dim3(64), 0, s, k, O, rhs, coef, resid2);
+}
+
+void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, double alpha,
+              const double *c, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_xverlet, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, Xk[0], Xk[1], Xk[2],
+                     Xk[3], Xk[4], Xk[5], Xk[6], Y, kappa, alpha, c[0], c[1], c[2], c[3], c[4],
+                     c[5], c[6], out);
+}
+
+void kick_drift(int n3, double *R, double *V, const double *A, double dt, int drift,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_kick_drift, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, R, V, A, dt, drift);
+}
+
+void accel(int n3, const double *frc, double sc, double *A, hipStream_t s) {
+  hipLaunchKernelGGL(k_accel, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, frc, sc, A);
+}
+
+}  // namespace xl

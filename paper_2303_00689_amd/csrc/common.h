@@ -1,0 +1,95 @@
+// Internal declarations shared by the HIP translation units of libxlbomd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace xl {
+
+// ---------------------------------------------------------------- GEMM (FP64)
+// out = alpha * sum_p op(A_p) op(B_p) + beta1 * C1 + beta2 * C2 + gamma * I
+// op(A) reads A as its transpose (A^T tiles are contiguous rows of A), which is
+// A itself for the symmetric operands of the Fermi-operator and response chains.
+// op(B) is B (btrans = 0) or B^T (btrans = 1).  sym = 1 computes only tiles with
+// tile_row <= tile_col and writes each one also to the mirrored position; it is
+// valid when the result is symmetric (products of commuting symmetric matrices,
+// A B + B A, and the final product of a response level).  out must not alias an
+// A or B operand; it may alias C1 or C2.
+struct GemmArgs {
+  int n;
+  int nprod;               // 1 or 2
+  const void *A[2];
+  const void *B[2];
+  int btrans;
+  const void *C1, *C2;     // nullable
+  void *out;
+  double alpha, beta1, beta2, gamma;
+  int sym;
+};
+void gemm_f64(const GemmArgs &a, hipStream_t s);
+// Split-precision GEMM on FP32 storage (prec: 1 = BF16x3, 2 = BF16x6, 3 = FP16x3).
+void gemm_split(const GemmArgs &a, int prec, hipStream_t s);
+
+// ------------------------------------------------------------- BLAS-1 (FP64 or FP32)
+// Elementwise kernels operate on n*n matrices of the given element type
+// (is32 = 0: double, 1: float).  Scalars marked "_dev" are read from device memory.
+void axpby(int n2, double a, const void *x, double b, const void *y, void *out, int is32, hipStream_t s);
+// out = a*x + b*y + g*I, with a, b, g taken from device scalars (null -> host value)
+void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const double *b_dev, double b,
+                const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s);
+void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s);
+void symmetrize(int n, void *M, int is32, hipStream_t s);
+// out = sum_j coef[j] * M_j (coef on device), j < k <= 40, FP64
+void lincomb_dev(int n2, int k, const double *const *M, const double *coef, double *out, hipStream_t s);
+
+// Deterministic FP64 reductions into device scalars.
+// dots: res[i] = <X_i, Y_i> (Frobenius) for i < k <= 16
+void dots(int n2, int k, const void *const *X, const void *const *Y, double *res, int is32,
+          double *partials, hipStream_t s);
+// res[0] = trace(M)
+void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s);
+// Gershgorin bounds of a symmetric matrix: res[0] = min(F_ii - r_i), res[1] = max(F_ii + r_i)
+void gershgorin(int n, const double *F, double *res, double *partials, hipStream_t s);
+int reduce_partials_capacity();
+
+// ------------------------------------------------------------- pair kernels
+struct PairSys {
+  int n_atoms;
+  int n_tiles;             // atom tiles of 16
+  const double *R;         // n_atoms x 3
+  const double *onecenter; // n_atoms x 5
+  const float *noise_t;    // tile-major noise [tilepair][55][256]
+  const double *j55;       // device, 55
+  double eps_s, eps_p, t0, r0_hop, lam_hop, coul_k, coul_a, noise_amp, z_core, a_rep, r0_rep,
+      rho_rep;
+};
+void repack_noise(int n_atoms, const float *noise_host_layout_dev, float *noise_t, hipStream_t s);
+size_t noise_tile_floats(int n_atoms);
+// F = [h +] G(P); partial: scratch of n_tiles * n_atoms * 10 doubles; pk: n_atoms * 10
+void fock(const PairSys &ps, const double *P, double *F, int include_h, double *pk,
+          double *partial, hipStream_t s);
+void hcore(const PairSys &ps, double *H, double *partial, hipStream_t s);
+// forces (n_atoms x 3) and energy parts e[0..2] = Tr[hP0], Tr[(P0-X/2)G(X)], Vnn (device)
+void forces(const PairSys &ps, const double *P0, const double *X, double *frc, double *e,
+            double *pk3, double *fpart, double *epart, hipStream_t s);
+size_t force_partial_doubles(int n_atoms);
+size_t energy_partial_doubles(int n_atoms);
+
+// ------------------------------------------------------------- scalar kernels
+// Chemical-potential and Krylov scalar steps (one thread), see the .hip file.
+void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s);
+void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStream_t s);
+void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
+                  hipStream_t s);
+
+// ------------------------------------------------------------- MD kernels
+void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, double alpha,
+              const double *c, double *out, hipStream_t s);
+void kick_drift(int n3, double *R, double *V, const double *A, double dt, int drift,
+                hipStream_t s);
+void accel(int n3, const double *frc, double inv_mass_conv, double *A, hipStream_t s);
+
+}  // namespace xl
+
+#define XL_CHECK_LAUNCH() (void)0

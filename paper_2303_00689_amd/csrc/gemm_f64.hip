@@ -1,0 +1,165 @@
+// FP64 MFMA GEMM with fused epilogue for the Fermi-operator and response chains.
+//
+// Tile 64 x 64 per workgroup of 256 threads (4 wavefronts of 64 lanes in a
+// 2 x 2 arrangement, 32 x 32 each = 2 x 2 blocks of v_mfma_f64_16x16x4).  The
+// K dimension advances by 16 through double-buffered LDS panels; the next
+// panel is fetched into registers while the current one feeds the MFMAs.
+//
+// Operand layout for v_mfma_f64_16x16x4f64 (one double per lane):
+//   A (16 x 4): lane l holds A[l % 16][l / 16]
+//   B (4 x 16): lane l holds B[l / 16][l % 16]
+//   D (16 x 16): lane l holds D[l / 16 + 4 * q][l % 16], q = 0..3
+// LDS panels are stored k-major (As[k][m], Bs[k][n]) so that both fragments
+// are read as 16 consecutive doubles per lane group.
+#include "common.h"
+
+namespace xl {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64;
+constexpr int BK = 16;
+
+__device__ inline void tri_index(int bid, int T, int &bi, int &bj) {
+  // row bi of the upper triangle holds T - bi tiles
+  int r = 0, start = 0;
+  while (start + (T - r) <= bid) {
+    start += T - r;
+    ++r;
+  }
+  bi = r;
+  bj = r + (bid - start);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
+  const int n = p.n;
+  int bi, bj;
+  if (p.sym) {
+    tri_index(blockIdx.x, T, bi, bj);
+  } else {
+    bi = blockIdx.x / T;
+    bj = blockIdx.x % T;
+  }
+  const int i0 = bi * BM, j0 = bj * BM;
+  __shared__ double As[2][BK][BM];
+  __shared__ double Bs[2][BK][BM];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int kt_per = (n + BK - 1) / BK;
+  const int ktiles = kt_per * p.nprod;
+
+  // register staging: 4 doubles of A and 4 of B per thread
+  double ra[4], rb[4];
+  // A panel rows k (16) x cols m (64): thread -> (k = tid / 16, m = 4 * (tid % 16))
+  const int la_k = tid >> 4, la_m = (tid & 15) * 4;
+  // B panel, normal: same mapping; transposed: rows j (64) x 16 k: (j = tid / 4, k = 4 * (tid % 4))
+  const int lbt_j = tid >> 2, lbt_k = (tid & 3) * 4;
+
+  auto load = [&](int kt) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * BK;
+    const double *A = (const double *)p.A[prod];
+    const double *B = (const double *)p.B[prod];
+    {
+      const int k = k0 + la_k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = i0 + la_m + q;
+        ra[q] = (k < n && m < n) ? A[(size_t)k * n + m] : 0.0;
+      }
+    }
+    if (!p.btrans) {
+      const int k = k0 + la_k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + la_m + q;
+        rb[q] = (k < n && j < n) ? B[(size_t)k * n + j] : 0.0;
+      }
+    } else {
+      const int j = j0 + lbt_j;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + lbt_k + q;
+        rb[q] = (k < n && j < n) ? B[(size_t)j * n + k] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) As[buf][la_k][la_m + q] = ra[q];
+    if (!p.btrans) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[buf][la_k][la_m + q] = rb[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[buf][lbt_k + q][lbt_j] = rb[q];
+    }
+  };
+
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < ktiles) load(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a0 = As[buf][kr][wm + (lane & 15)];
+      double a1 = As[buf][kr][wm + 16 + (lane & 15)];
+      double b0 = Bs[buf][kr][wn + (lane & 15)];
+      double b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (kt + 1 < ktiles) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const double *C1 = (const double *)p.C1;
+  const double *C2 = (const double *)p.C2;
+  double *out = (double *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int j = j0 + wn + c * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wm + r * 16 + (lane >> 4) + 4 * q;
+        if (i < n && j < n) {
+          const size_t off = (size_t)i * n + j;
+          double x = p.alpha * acc[r][c][q];
+          if (C1) x += p.beta1 * C1[off];
+          if (C2) x += p.beta2 * C2[off];
+          if (i == j) x += p.gamma;
+          out[off] = x;
+          if (mirror) out[(size_t)j * n + i] = x;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void gemm_f64(const GemmArgs &a, hipStream_t s) {
+  const int T = (a.n + BM - 1) / BM;
+  const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
+  hipLaunchKernelGGL(k_gemm_f64, dim3(blocks), dim3(256), 0, s, a, T);
+}
+
+}  // namespace xl

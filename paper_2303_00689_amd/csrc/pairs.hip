@@ -1,0 +1,479 @@
+// Atom-pair kernels: Fock build F = h + G(P) (eqs. 3, 6, 17), h(R), and the
+// eq. 37 forces with the pair-decomposed parts of the shadow energy (eq. 13).
+//
+// Work is organised in tiles of 16 x 16 atom pairs (upper triangle of atom
+// tiles, 256 threads, one thread per pair A < B).  The R-independent factor
+// noise_AB of every two-centre block is stored tile-major,
+//   noise_t[(tilepair * 55 + k) * 256 + slot],  slot = 16 * a_local + b_local,
+// so that the 55 loads of a tile are 55 fully coalesced 1 KiB rows.  W_AB is
+// formed in registers as gamma(R) * (J[k] + noise_amp * noise[k]).
+//
+// Per-atom sums over all partners (the two-centre Coulomb term of the
+// diagonal blocks, the force on each atom) are reduced deterministically:
+// every tile pair writes one partial per (partner tile, atom) and a second
+// kernel adds the partials of each atom in a fixed order.
+#include "common.h"
+
+#include <cmath>
+
+namespace xl {
+namespace {
+
+constexpr int TA = 16;
+
+// packed orbital pairs of one atom (row-major upper triangle of the 4x4 block)
+__device__ constexpr int PM[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__device__ constexpr int PN[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+__host__ __device__ constexpr int pidx55(int r, int c) {  // r <= c
+  return r * 10 - r * (r - 1) / 2 + (c - r);
+}
+
+__device__ inline void tri_tile(int bid, int T, int &ta, int &tb) {
+  int r = 0, start = 0;
+  while (start + (T - r) <= bid) {
+    start += T - r;
+    ++r;
+  }
+  ta = r;
+  tb = r + (bid - start);
+}
+
+__global__ void k_repack(int N, int T, const float *src, float *dst) {
+  const int tp = blockIdx.x;
+  int ta, tb;
+  tri_tile(tp, T, ta, tb);
+  const int slot = threadIdx.x;
+  const int A = ta * TA + slot / TA, B = tb * TA + slot % TA;
+  const bool valid = A < N && B < N && A < B;
+  const size_t p = valid ? ((size_t)A * N - (size_t)A * (A + 1) / 2 + (B - A - 1)) : 0;
+  for (int k = 0; k < 55; ++k)
+    dst[((size_t)tp * 55 + k) * 256 + slot] = valid ? src[p * 55 + k] : 0.0f;
+}
+
+// packed diagonal blocks (off-diagonal entries doubled); optional -z at ss
+__global__ void k_pack_diag(int N, int n, const double *P, double zsub, double *pk) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= N) return;
+  for (int r = 0; r < 10; ++r) {
+    const int m = PM[r], q = PN[r];
+    double v = P ? P[(size_t)(4 * A + m) * n + 4 * A + q] : 0.0;
+    if (m != q) v *= 2.0;
+    if (r == 0) v -= zsub;
+    pk[A * 10 + r] = v;
+  }
+}
+
+struct PairGeo {
+  double r, l[3], gamma, dgamma, t, dt;
+};
+
+__device__ inline PairGeo pair_geo(const PairSys &ps, int A, int B) {
+  PairGeo g;
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = ps.R[3 * B + k] - ps.R[3 * A + k];
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  g.r = sqrt(r2);
+  for (int k = 0; k < 3; ++k) g.l[k] = d[k] / g.r;
+  const double s2 = r2 + ps.coul_a * ps.coul_a;
+  const double is = 1.0 / sqrt(s2);
+  g.gamma = ps.coul_k * is;
+  g.dgamma = -ps.coul_k * g.r * is * is * is;
+  g.t = ps.t0 * exp(-(g.r - ps.r0_hop) / ps.lam_hop);
+  g.dt = -g.t / ps.lam_hop;
+  return g;
+}
+
+// F off-diagonal atom blocks and Coulomb partials.
+__global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const double *P,
+                                                     const double *pk, int include_h, double *F,
+                                                     double *part) {
+  const int N = ps.n_atoms, T = ps.n_tiles;
+  const int tp = blockIdx.x;
+  int ta, tb;
+  tri_tile(tp, T, ta, tb);
+  const int slot = threadIdx.x, al = slot / TA, bl = slot % TA;
+  const int A = ta * TA + al, B = tb * TA + bl;
+  const bool valid = A < N && B < N && (ta < tb || al < bl);
+
+  __shared__ double shA[10][256];
+  __shared__ double shB[10][256];
+
+  double cA[10], cB[10], G[4][4];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) cA[r] = cB[r] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) G[i][j] = 0.0;
+
+  if (valid) {
+    const PairGeo g = pair_geo(ps, A, B);
+    double Pab[4][4], pA[10], pB[10];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Pab[i][j] = P ? P[(size_t)(4 * A + i) * n + 4 * B + j] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+      pA[r] = pk[A * 10 + r];
+      pB[r] = pk[B * 10 + r];
+    }
+    const float *nz = ps.noise_t + (size_t)tp * 55 * 256 + slot;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+      for (int c = r; c < 10; ++c) {
+        const int k = pidx55(r, c);
+        const double w = g.gamma * (ps.j55[k] + ps.noise_amp * (double)nz[(size_t)k * 256]);
+        // position (r, c): r is A's orbital pair, c is B's
+        cA[r] += w * pB[c];
+        cB[c] += w * pA[r];
+        {
+          const int mu = PM[r], nu = PN[r], la = PM[c], si = PN[c];
+          G[mu][la] -= 0.5 * w * Pab[nu][si];
+          if (la != si) G[mu][si] -= 0.5 * w * Pab[nu][la];
+          if (mu != nu) G[nu][la] -= 0.5 * w * Pab[mu][si];
+          if (mu != nu && la != si) G[nu][si] -= 0.5 * w * Pab[mu][la];
+        }
+        if (r != c) {  // mirrored position (c, r)
+          cA[c] += w * pB[r];
+          cB[r] += w * pA[c];
+          const int mu = PM[c], nu = PN[c], la = PM[r], si = PN[r];
+          G[mu][la] -= 0.5 * w * Pab[nu][si];
+          if (la != si) G[mu][si] -= 0.5 * w * Pab[nu][la];
+          if (mu != nu) G[nu][la] -= 0.5 * w * Pab[mu][si];
+          if (mu != nu && la != si) G[nu][si] -= 0.5 * w * Pab[mu][la];
+        }
+      }
+    }
+    if (include_h) {
+      const double t = g.t;
+      G[0][0] += t;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        G[0][1 + j] += t * g.l[j];
+        G[1 + j][0] -= t * g.l[j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) G[1 + i][1 + j] += t * g.l[i] * g.l[j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        F[(size_t)(4 * A + i) * n + 4 * B + j] = G[i][j];
+        F[(size_t)(4 * B + j) * n + 4 * A + i] = G[i][j];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    shA[r][slot] = cA[r];
+    shB[r][slot] = cB[r];
+  }
+  __syncthreads();
+  if (slot < 160) {
+    const int x = slot / 10, r = slot % 10;
+    double row = 0.0, col = 0.0;
+    for (int q = 0; q < TA; ++q) {
+      row += shA[r][x * TA + q];  // atom ta*16+x as A, over partners b
+      col += shB[r][q * TA + x];  // atom tb*16+x as B, over partners a
+    }
+    if (ta == tb) {
+      const int X = ta * TA + x;
+      if (X < N) part[((size_t)ta * N + X) * 10 + r] = row + col;
+    } else {
+      const int XA = ta * TA + x, XB = tb * TA + x;
+      if (XA < N) part[((size_t)tb * N + XA) * 10 + r] = row;
+      if (XB < N) part[((size_t)ta * N + XB) * 10 + r] = col;
+    }
+  }
+}
+
+// one-centre two-electron block of atom A from its spin-summed density block
+__device__ inline void onecenter_G(const double *oc, const double Pd[4][4], double G1[4][4]) {
+  const double gss = oc[0], gsp = oc[1], gpp = oc[2], gp2 = oc[3], hsp = oc[4];
+  const double hpp = 0.5 * (gpp - gp2);
+  const double pss = Pd[0][0], pxx = Pd[1][1], pyy = Pd[2][2], pzz = Pd[3][3];
+  G1[0][0] = 0.5 * pss * gss + (pxx + pyy + pzz) * (gsp - 0.5 * hsp);
+  const double pp[3] = {pxx, pyy, pzz};
+  for (int i = 0; i < 3; ++i) {
+    double v = pss * (gsp - 0.5 * hsp) + 0.5 * pp[i] * gpp;
+    for (int j = 0; j < 3; ++j)
+      if (j != i) v += pp[j] * (gp2 - 0.5 * hpp);
+    G1[1 + i][1 + i] = v;
+    G1[0][1 + i] = G1[1 + i][0] = 0.5 * Pd[0][1 + i] * (3.0 * hsp - gsp);
+    for (int j = 0; j < 3; ++j)
+      if (j != i) G1[1 + i][1 + j] = 0.5 * Pd[1 + i][1 + j] * (3.0 * hpp - gp2);
+  }
+}
+
+__global__ void k_fock_diag(PairSys ps, int n, const double *P, int include_h, const double *part,
+                            double *F) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = ps.n_atoms;
+  if (A >= N) return;
+  double coul[10];
+  for (int r = 0; r < 10; ++r) coul[r] = 0.0;
+  for (int t = 0; t < ps.n_tiles; ++t)
+    for (int r = 0; r < 10; ++r) coul[r] += part[((size_t)t * N + A) * 10 + r];
+  double Pd[4][4], G1[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Pd[i][j] = P ? P[(size_t)(4 * A + i) * n + 4 * A + j] : 0.0;
+  onecenter_G(ps.onecenter + 5 * A, Pd, G1);
+  for (int r = 0; r < 10; ++r) {
+    const int m = PM[r], q = PN[r];
+    double v = G1[m][q] + coul[r];
+    if (include_h && m == q) v += (m == 0) ? ps.eps_s : ps.eps_p;
+    F[(size_t)(4 * A + m) * n + 4 * A + q] = v;
+    if (m != q) F[(size_t)(4 * A + q) * n + 4 * A + m] = v;
+  }
+}
+
+// ---- forces and pair energies
+// pk3 = [p0 | x | q] packed diagonal blocks, q = P0 - X/2, each N x 10
+__global__ __launch_bounds__(256) void k_force_pairs(PairSys ps, int n, const double *P0,
+                                                      const double *X, const double *pk3,
+                                                      double *fpart, double *epart) {
+  const int N = ps.n_atoms, T = ps.n_tiles;
+  const int tp = blockIdx.x;
+  int ta, tb;
+  tri_tile(tp, T, ta, tb);
+  const int slot = threadIdx.x, al = slot / TA, bl = slot % TA;
+  const int A = ta * TA + al, B = tb * TA + bl;
+  const bool valid = A < N && B < N && (ta < tb || al < bl);
+  __shared__ double shf[3][256];
+  __shared__ double she[5][4];
+  double dE[3] = {0.0, 0.0, 0.0};
+  double e_hop = 0.0, e_core = 0.0, e_ee = 0.0, e_nn = 0.0, e_rep = 0.0;
+  if (valid) {
+    const PairGeo g = pair_geo(ps, A, B);
+    double Pab[4][4], Qab[4][4], Xab[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        const size_t off = (size_t)(4 * A + i) * n + 4 * B + j;
+        Pab[i][j] = P0[off];
+        Xab[i][j] = X[off];
+        Qab[i][j] = Pab[i][j] - 0.5 * Xab[i][j];
+      }
+    const double *p0A = pk3 + A * 10, *p0B = pk3 + B * 10;
+    const double *xA = pk3 + (size_t)N * 10 + A * 10, *xB = pk3 + (size_t)N * 10 + B * 10;
+    const double *qA = pk3 + (size_t)2 * N * 10 + A * 10, *qB = pk3 + (size_t)2 * N * 10 + B * 10;
+    // hopping: E = 2 t phi(l), phi = P_ss + (a - b).l + l^T C l
+    double phi = Pab[0][0], gv[3];
+    for (int j = 0; j < 3; ++j) {
+      phi += (Pab[0][1 + j] - Pab[1 + j][0]) * g.l[j];
+      gv[j] = Pab[0][1 + j] - Pab[1 + j][0];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        phi += Pab[1 + i][1 + j] * g.l[i] * g.l[j];
+        gv[i] += Pab[1 + i][1 + j] * g.l[j];
+        gv[j] += Pab[1 + i][1 + j] * g.l[i];
+      }
+    e_hop = 2.0 * g.t * phi;
+    const double gl = gv[0] * g.l[0] + gv[1] * g.l[1] + gv[2] * g.l[2];
+    for (int k = 0; k < 3; ++k)
+      dE[k] = 2.0 * g.dt * phi * g.l[k] + 2.0 * g.t / g.r * (gv[k] - gl * g.l[k]);
+    // terms linear in W, evaluated with the base block b = J + noise_amp * noise
+    const float *nz = ps.noise_t + (size_t)tp * 55 * 256 + slot;
+    const double Z = ps.z_core;
+    double bcore = 0.0, bee = 0.0, bnn = 0.0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+      for (int c = r; c < 10; ++c) {
+        const int k = pidx55(r, c);
+        const double b = ps.j55[k] + ps.noise_amp * (double)nz[(size_t)k * 256];
+        // position (r, c)
+        double ex = 0.0;
+        {
+          const int mu = PM[r], nu = PN[r], la = PM[c], si = PN[c];
+          ex += Qab[mu][la] * Xab[nu][si];
+          if (la != si) ex += Qab[mu][si] * Xab[nu][la];
+          if (mu != nu) ex += Qab[nu][la] * Xab[mu][si];
+          if (mu != nu && la != si) ex += Qab[nu][si] * Xab[mu][la];
+        }
+        double core = (c == 0 ? p0A[r] : 0.0) + (r == 0 ? p0B[c] : 0.0);
+        double ee = qA[r] * xB[c] + xA[r] * qB[c] - ex;
+        if (r != c) {
+          const int mu = PM[c], nu = PN[c], la = PM[r], si = PN[r];
+          double ex2 = Qab[mu][la] * Xab[nu][si];
+          if (la != si) ex2 += Qab[mu][si] * Xab[nu][la];
+          if (mu != nu) ex2 += Qab[nu][la] * Xab[mu][si];
+          if (mu != nu && la != si) ex2 += Qab[nu][si] * Xab[mu][la];
+          core += (r == 0 ? p0A[c] : 0.0) + (c == 0 ? p0B[r] : 0.0);
+          ee += qA[c] * xB[r] + xA[c] * qB[r] - ex2;
+        }
+        bcore -= Z * core * b;
+        bee += ee * b;
+        if (r == 0 && c == 0) bnn += Z * Z * b;
+      }
+    }
+    e_core = g.gamma * bcore;
+    e_ee = g.gamma * bee;
+    e_nn = g.gamma * bnn;
+    e_rep = ps.a_rep * exp(-(g.r - ps.r0_rep) / ps.rho_rep);
+    const double dr = g.dgamma * (bcore + bee + bnn) - e_rep / ps.rho_rep;
+    for (int k = 0; k < 3; ++k) dE[k] += dr * g.l[k];
+  }
+  // dE = dE_pair/dR_B: the force on B is -dE and the force on A is +dE
+  for (int k = 0; k < 3; ++k) shf[k][slot] = dE[k];
+  // block energy sums
+  double ev[5] = {e_hop, e_core, e_ee, e_nn, e_rep};
+  for (int q = 0; q < 5; ++q) {
+    double v = ev[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((slot & 63) == 0) she[q][slot >> 6] = v;
+  }
+  __syncthreads();
+  if (slot < 5) epart[(size_t)tp * 5 + slot] = she[slot][0] + she[slot][1] + she[slot][2] + she[slot][3];
+  if (slot < 48) {
+    const int x = slot / 3, k = slot % 3;
+    double row = 0.0, col = 0.0;
+    for (int q = 0; q < TA; ++q) {
+      row += shf[k][x * TA + q];
+      col -= shf[k][q * TA + x];
+    }
+    if (ta == tb) {
+      const int Xa = ta * TA + x;
+      if (Xa < N) fpart[((size_t)ta * N + Xa) * 3 + k] = row + col;
+    } else {
+      const int XA = ta * TA + x, XB = tb * TA + x;
+      if (XA < N) fpart[((size_t)tb * N + XA) * 3 + k] = row;
+      if (XB < N) fpart[((size_t)ta * N + XB) * 3 + k] = col;
+    }
+  }
+}
+
+__global__ void k_zero(size_t m, double *p) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void k_pack3(int N, int n, const double *P0, const double *X, double *pk3) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= N) return;
+  for (int r = 0; r < 10; ++r) {
+    const int m = PM[r], q = PN[r];
+    const size_t off = (size_t)(4 * A + m) * n + 4 * A + q;
+    const double f = (m != q) ? 2.0 : 1.0;
+    pk3[A * 10 + r] = f * P0[off];
+    pk3[(size_t)N * 10 + A * 10 + r] = f * X[off];
+    pk3[(size_t)2 * N * 10 + A * 10 + r] = f * (P0[off] - 0.5 * X[off]);
+  }
+}
+
+// per-atom: total force, and per-atom energies (on-site h, one-centre ee)
+__global__ void k_force_atoms(PairSys ps, int n, const double *P0, const double *X,
+                              const double *fpart, double *frc, double *eatom) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = ps.n_atoms;
+  if (A >= N) return;
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int t = 0; t < ps.n_tiles; ++t) v += fpart[((size_t)t * N + A) * 3 + k];
+    frc[3 * A + k] = v;  // partials already hold -dE/dR of their pairs
+  }
+  double Xd[4][4], G1[4][4];
+  double e_on = 0.0, e_1c = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) Xd[i][j] = X[(size_t)(4 * A + i) * n + 4 * A + j];
+  onecenter_G(ps.onecenter + 5 * A, Xd, G1);
+  for (int i = 0; i < 4; ++i) {
+    const size_t di = (size_t)(4 * A + i) * n + 4 * A + i;
+    e_on += (i == 0 ? ps.eps_s : ps.eps_p) * P0[di];
+    for (int j = 0; j < 4; ++j) {
+      const size_t off = (size_t)(4 * A + i) * n + 4 * A + j;
+      e_1c += (P0[off] - 0.5 * X[off]) * G1[i][j];
+    }
+  }
+  eatom[2 * A] = e_on;
+  eatom[2 * A + 1] = e_1c;
+}
+
+// e[0] = Tr[h P0] = on-site + hop + core; e[1] = Tr[(P0 - X/2) G(X)] = 1c + ee;
+// e[2] = V_nn = nn + rep.  Fixed-order sums.
+__global__ void k_energy_final(int ntp, const double *epart, int N, const double *eatom, double *e) {
+  __shared__ double sh[7][256];
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < ntp; t += 256)
+    for (int q = 0; q < 5; ++q) s[q] += epart[(size_t)t * 5 + q];
+  for (int a = threadIdx.x; a < N; a += 256) {
+    s[5] += eatom[2 * a];
+    s[6] += eatom[2 * a + 1];
+  }
+  for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] = s[q];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    e[0] = sh[5][0] + sh[0][0] + sh[1][0];
+    e[1] = sh[6][0] + sh[2][0];
+    e[2] = sh[3][0] + sh[4][0];
+  }
+}
+
+}  // namespace
+
+size_t noise_tile_floats(int n_atoms) {
+  const int T = (n_atoms + TA - 1) / TA;
+  return (size_t)T * (T + 1) / 2 * 55 * 256;
+}
+
+void repack_noise(int n_atoms, const float *src, float *dst, hipStream_t s) {
+  const int T = (n_atoms + TA - 1) / TA;
+  hipLaunchKernelGGL(k_repack, dim3(T * (T + 1) / 2), dim3(256), 0, s, n_atoms, T, src, dst);
+}
+
+void fock(const PairSys &ps, const double *P, double *F, int include_h, double *pk, double *part,
+          hipStream_t s) {
+  const int N = ps.n_atoms, n = 4 * N, T = ps.n_tiles;
+  hipLaunchKernelGGL(k_pack_diag, dim3((N + 127) / 128), dim3(128), 0, s, N, n, P,
+                     include_h ? ps.z_core : 0.0, pk);
+  if (N > 1)
+    hipLaunchKernelGGL(k_fock_pairs, dim3(T * (T + 1) / 2), dim3(256), 0, s, ps, n, P, pk, include_h,
+                       F, part);
+  else
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)10 * N * T, part);
+  hipLaunchKernelGGL(k_fock_diag, dim3((N + 127) / 128), dim3(128), 0, s, ps, n, P, include_h, part, F);
+}
+
+void hcore(const PairSys &ps, double *H, double *part, hipStream_t s) {
+  // h = F(P = 0) with the core attraction carried by the packed "-z at ss" density
+  const int N = ps.n_atoms;
+  double *pk = part + (size_t)ps.n_tiles * N * 10;
+  fock(ps, nullptr, H, 1, pk, part, s);
+}
+
+size_t force_partial_doubles(int n_atoms) {
+  const int T = (n_atoms + TA - 1) / TA;
+  return (size_t)T * n_atoms * 3;
+}
+size_t energy_partial_doubles(int n_atoms) {
+  const int T = (n_atoms + TA - 1) / TA;
+  return (size_t)T * (T + 1) / 2 * 5 + 2 * (size_t)n_atoms;
+}
+
+void forces(const PairSys &ps, const double *P0, const double *X, double *frc, double *e,
+            double *pk3, double *fpart, double *epart, hipStream_t s) {
+  const int N = ps.n_atoms, n = 4 * N, T = ps.n_tiles;
+  const int ntp = T * (T + 1) / 2;
+  double *eatom = epart + (size_t)ntp * 5;
+  hipLaunchKernelGGL(k_pack3, dim3((N + 127) / 128), dim3(128), 0, s, N, n, P0, X, pk3);
+  if (N > 1) {
+    hipLaunchKernelGGL(k_force_pairs, dim3(ntp), dim3(256), 0, s, ps, n, P0, X, pk3, fpart, epart);
+  } else {
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)3 * N * T, fpart);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)5 * ntp, epart);
+  }
+  hipLaunchKernelGGL(k_force_atoms, dim3((N + 127) / 128), dim3(128), 0, s, ps, n, P0, X, fpart, frc,
+                     eatom);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, ntp, epart, N, eatom, e);
+}
+
+}  // namespace xl
