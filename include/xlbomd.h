@@ -209,6 +209,17 @@ xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, int m, double tol, int max_
 xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, double *Cout,
                             int sym_out, int reps);
 
+/* Diagnostic timing: enable != 0 starts recording a pair of HIP events around
+ * every GEMM, Fock-build and force launch on the handle's stream (at most
+ * 65536 launches; later ones are not recorded); 0 stops.  Either call clears
+ * earlier records. */
+xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
+/* Sums over the recorded launches, 3 classes x {launches, milliseconds,
+ * algorithmic work}: [0..2] GEMM (work = flops the method needs: 2n^3 per
+ * product, n^3 for a product with symmetric output), [3..5] Fock build and
+ * [6..8] forces (work = HBM bytes: 220 per atom pair plus 16 n^2). */
+xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
+
 #ifdef __cplusplus
 }
 #endif

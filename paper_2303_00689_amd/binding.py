@@ -26,7 +26,8 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
 SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
            "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm",
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
-           "xlbomd_step", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul"]
+           "xlbomd_step", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul",
+           "xlbomd_profile", "xlbomd_profile_read"]
 
 
 class Model(C.Structure):
@@ -89,6 +90,8 @@ def load():
     lib.xlbomd_md_init.argtypes = [vp, C.POINTER(MDStateC)]
     lib.xlbomd_scf.argtypes = [vp, vp, i, d, i, pd]
     lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
+    lib.xlbomd_profile.argtypes = [vp, i]
+    lib.xlbomd_profile_read.argtypes = [vp, pd]
     for name in SYMBOLS:
         if name not in ("xlbomd_last_error", "xlbomd_n_orb"):
             getattr(lib, name).restype = i
@@ -243,10 +246,23 @@ class Handle:
         self._check(self.lib.xlbomd_matmul(self.h, self._mat(A), self._mat(B), self._mat(Cout),
                                            int(bool(sym_out)), int(reps)), "matmul")
 
-    def scf(self, X, m=20, tol=1e-10, max_iter=100):
+    def profile(self, enable=True):
+        self._check(self.lib.xlbomd_profile(self.h, int(bool(enable))), "profile")
+
+    def profile_read(self):
+        out = (C.c_double * 9)()
+        self._check(self.lib.xlbomd_profile_read(self.h, out), "profile_read")
+        names = ("gemm", "fock", "forces")
+        return {nm: dict(launches=int(out[3 * k]), ms=out[3 * k + 1], work=out[3 * k + 2])
+                for k, nm in enumerate(names)}
+
+    def scf(self, X, m=20, tol=1e-10, max_iter=100, allow_noconv=False):
+        """Returns the final residual ||D0[X] - X||_F; with allow_noconv a run that
+        stops above tol returns its residual instead of raising."""
         res = C.c_double(0.0)
-        self._check(self.lib.xlbomd_scf(self.h, self._mat(X), int(m), float(tol), int(max_iter),
-                                        C.byref(res)), "scf")
+        st = self.lib.xlbomd_scf(self.h, self._mat(X), int(m), float(tol), int(max_iter), C.byref(res))
+        if not (allow_noconv and st == -3):
+            self._check(st, "scf")
         return res.value
 
 

@@ -38,6 +38,8 @@ enum Slot {
   S_TRR = 50,      // Tr R (response)
   S_CAN = 52,      // -Tr R / Tr M
   S_TRD = 54,      // final trace of D
+  S_FIX = 56,      // first-order trace correction coefficient
+  S_TRP = 58,      // trace of the returned P
   S_ENER = 60,     // 3 energies
   S_DOTS = 64,     // 40 dots
   S_KO = 128,      // Krylov O, 32 x 32 (row stride 32)
@@ -60,6 +62,21 @@ __global__ void k_scal_misc(const double *mu1, const double *mu2, const double *
 __global__ void k_canon(const double *trR, const double *trM, double *out) {
   if (threadIdx.x) return;
   *out = (*trM > 0.0) ? -(*trR) / (*trM) : 0.0;
+}
+
+// first-order chemical-potential correction of the stored chain result:
+// P = 2 (D + c M) with c = (n_occ - Tr D) / Tr M, written in FP64.  dD/dmu =
+// beta M, so this is the exact derivative step that makes Tr P = 2 n_occ.
+__global__ void k_trace_fix(const double *trD, const double *trM, double n_occ, double *c) {
+  if (threadIdx.x) return;
+  *c = (*trM > 0.0) ? (n_occ - *trD) / *trM : 0.0;
+}
+template <typename T>
+__global__ void k_finalize_P(size_t n2, const T *D, const T *M, const double *c, double *P) {
+  const double cv = *c;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x)
+    P[i] = 2.0 * ((double)D[i] + cv * (double)M[i]);
 }
 
 // out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device
@@ -139,8 +156,12 @@ struct xlbomd_ctx {
   double *f64[6] = {};
   double *Vk[MMAX] = {}, *Wk[MMAX] = {};
   int kalloc = 0;
-  // stats
+  // stats and optional per-launch timing (HIP events on the handle's stream)
   long long n_gemm = 0;
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  struct Rec { int cls; int ev; double work; };
+  std::vector<Rec> recs;
 };
 
 namespace {
@@ -164,6 +185,22 @@ xlbomd_status fail(xlbomd_ctx *c, xlbomd_status st, const char *fmt, ...) {
 
 bool dev_alloc(void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
 
+// kernel classes of the timing hooks
+enum { PC_GEMM = 0, PC_FOCK = 1, PC_FORCE = 2, PC_N = 3 };
+
+int prof_begin(xlbomd_ctx *c) {
+  if (!c->prof) return -1;
+  const int e = (int)c->recs.size() * 2;
+  if (e + 2 > (int)c->evpool.size()) return -1;
+  hipEventRecord(c->evpool[e], c->s);
+  return e;
+}
+void prof_end(xlbomd_ctx *c, int e, int cls, double work) {
+  if (e < 0) return;
+  hipEventRecord(c->evpool[e + 1], c->s);
+  c->recs.push_back({cls, e, work});
+}
+
 // ------------------------------------------------------------------ GEMM helper
 void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, int sym,
         const void *C1 = nullptr, double b1 = 0.0, const void *C2 = nullptr, double b2 = 0.0,
@@ -184,11 +221,29 @@ void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, in
   g.beta2 = b2;
   g.gamma = gamma;
   g.sym = sym;
+  const int e = prof_begin(c);
   if (c->prec == XLBOMD_FP64)
     gemm_f64(g, c->s);
   else
     gemm_split(g, c->prec, c->s);
+  const double n = (double)c->n;
+  prof_end(c, e, PC_GEMM, g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
   ++c->n_gemm;
+}
+
+PairSys pairsys(xlbomd_ctx *c);
+
+// algorithmic HBM bytes of one pair pass: the FP32 noise blocks, two n x n FP64
+// matrices read or written (P and F, or P0 and X)
+double pair_pass_bytes(xlbomd_ctx *c) {
+  const double np = 0.5 * c->N * (c->N - 1.0);
+  return 220.0 * np + 16.0 * (double)c->n2;
+}
+
+void fock_t(xlbomd_ctx *c, const double *P, double *F, int include_h) {
+  const int e = prof_begin(c);
+  fock(pairsys(c), P, F, include_h, c->pk, c->part, c->s);
+  prof_end(c, e, PC_FOCK, pair_pass_bytes(c));
 }
 
 PairSys pairsys(xlbomd_ctx *c) {
@@ -374,11 +429,14 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   mm(c, c->Sst, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, c->Sst);          // S dS + dS S
   axpby((int)c->n2, TC1, dS, TC2, dS2, dS2, i32, s);                                      // dP
   mm(c, V1, c->Pst, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, c->Vst, dS2);         // (V1 P + V dP)/2
+  // level i: Y1 <- [2 Y1 - 4 Y_{i+1} (Y_i Y1 + Y1 Y_i)] Z_i, evaluated as the
+  // (symmetric) transpose Z_i [2 Y1 - 4 Y_{i+1} G]^T so that every GEMM operand
+  // is symmetric or explicitly transposed
   for (int i = 0; i < L; ++i) {
-    mm(c, c->Yc[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, c->Yc[i]);      // Y Y1 + Y1 Y
-    mm(c, G, c->Yc[i + 1], H, 1.0, 0);                                                     // G Y_{i+1}
+    mm(c, c->Yc[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, c->Yc[i]);      // G = Y Y1 + Y1 Y
+    mm(c, c->Yc[i + 1], G, H, 1.0, 0);                                                     // H = Y_{i+1} G
     axpby((int)c->n2, 2.0, Y1, -4.0, H, H, i32, s);                                       // 2 Y1 - 4 H
-    mm(c, c->Zc[i], H, Y1b, 1.0, 1);                                                       // Z_i (...)
+    mm(c, c->Zc[i], H, Y1b, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);                  // Z_i (..)^T
     std::swap(Y1, Y1b);
   }
   // chemical-potential shift map: Qs Y1 Qs
@@ -448,20 +506,27 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   }
   if (!converged) return fail(c, XLBOMD_E_NOCONV, "chemical potential search did not converge");
   c->chain_valid = true;
-  *mu_io = mu;
-  // P = 2 D
-  if (c->is32) {
-    convert((int)c->n2, c->D, 1, P, 0, c->s);
-    axpby((int)c->n2, 2.0, P, 0.0, nullptr, P, 0, c->s);
-  } else {
-    axpby((int)c->n2, 2.0, c->D, 0.0, nullptr, P, 0, c->s);
+  hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, c->s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
+                     c->dscal + S_FIX);
+  {
+    size_t blocks = std::min<size_t>((c->n2 + 255) / 256, 8192);
+    if (c->is32)
+      hipLaunchKernelGGL(k_finalize_P<float>, dim3(blocks), dim3(256), 0, c->s, c->n2, (const float *)c->D,
+                         (const float *)c->M, c->dscal + S_FIX, P);
+    else
+      hipLaunchKernelGGL(k_finalize_P<double>, dim3(blocks), dim3(256), 0, c->s, c->n2, (const double *)c->D,
+                         (const double *)c->M, c->dscal + S_FIX, P);
   }
+  trace(n, P, c->dscal + S_TRP, 0, c->red, c->s);
+  double fx[3];
+  if ((st = get_scalars(c, S_FIX, 3, fx))) return st;  // S_FIX, (pad), S_TRP
+  mu += fx[0] / c->beta;
+  *mu_io = mu;
   if (sync_check) {
-    double tr;
-    if ((st = get_scalars(c, S_TRD, 1, &tr))) return st;
+    const double tr = fx[2];
     if (!std::isfinite(tr)) return fail(c, XLBOMD_E_NONFINITE, "non-finite density matrix");
-    if (std::fabs(tr - c->n_occ) > 1e-9 * c->n_occ + 1e-6 * (c->prec != XLBOMD_FP64))
-      return fail(c, XLBOMD_E_NOCONV, "trace %.15g differs from N_occ %.15g", tr, c->n_occ);
+    if (std::fabs(tr - c->n_elec) > 1e-9 * c->n_elec)
+      return fail(c, XLBOMD_E_NOCONV, "trace %.15g differs from N_e %.15g", tr, c->n_elec);
   }
   return XLBOMD_OK;
 }
@@ -529,8 +594,7 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
     if (!(nv > 1e-12 * nsrc)) break;  // breakdown: rank k
     axpby(n2, 1.0 / nv, v, 0.0, nullptr, c->Vk[k], 0, s);
     // W_k = J V_k = P1[G(V_k)] - V_k
-    PairSys ps = pairsys(c);
-    fock(ps, c->Vk[k], F1, 0, c->pk, c->part, s);
+    fock_t(c, c->Vk[k], F1, 0);
     if ((st = response(c, F1, P1))) return st;
     axpby(n2, 1.0, P1, -1.0, c->Vk[k], c->Wk[k], 0, s);
     {
@@ -569,8 +633,9 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
 
 xlbomd_status energy_forces(xlbomd_ctx *c, const double *P0, const double *X, double *frc,
                             double e[3]) {
-  PairSys ps = pairsys(c);
-  forces(ps, P0, X, frc, c->dscal + S_ENER, c->pk3, c->fpart, c->epart, c->s);
+  const int ev = prof_begin(c);
+  forces(pairsys(c), P0, X, frc, c->dscal + S_ENER, c->pk3, c->fpart, c->epart, c->s);
+  prof_end(c, ev, PC_FORCE, pair_pass_bytes(c));
   if (e) return get_scalars(c, S_ENER, 3, e);
   return XLBOMD_OK;
 }
@@ -616,6 +681,7 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
     f(c->Vk[k]);
     f(c->Wk[k]);
   }
+  for (auto e : c->evpool) hipEventDestroy(e);
   delete c;
   return XLBOMD_OK;
 }
@@ -720,7 +786,7 @@ xlbomd_status xlbomd_hcore(xlbomd_handle c, double *H) {
 xlbomd_status xlbomd_fock(xlbomd_handle c, const double *P, double *F, int include_h) {
   if (!c || !P || !F || P == F) return c ? fail(c, XLBOMD_E_ARG, "bad fock arguments") : XLBOMD_E_ARG;
   if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
-  fock(pairsys(c), P, F, include_h ? 1 : 0, c->pk, c->part, c->s);
+  fock_t(c, P, F, include_h ? 1 : 0);
   HIPCHK(c, hipGetLastError());
   return XLBOMD_OK;
 }
@@ -789,7 +855,7 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
   const double *X = st->X + (size_t)st->head * c->n2;
   double *F = c->f64[5];
   double *P0 = c->f64[4];
-  fock(pairsys(c), X, F, 1, c->pk, c->part, c->s);
+  fock_t(c, X, F, 1);
   // P0 lives in f64[4] only until the Krylov call, which reuses it: keep a copy in Vk? use Wk slots
   double mu = st->mu;
   if ((s = fermi(c, F, &mu, P0, true))) return s;
@@ -864,7 +930,7 @@ xlbomd_status xlbomd_scf(xlbomd_handle c, double *X, int m, double tol, int max_
   double *Pm = c->Wk[m], *Ptrial = c->Wk[m + 1], *Ystep = c->Vk[m], *Xtrial = c->Vk[m + 1];
   double mu = NAN;
   auto resid = [&](const double *Xc, double *Pout, double &r) -> xlbomd_status {
-    fock(pairsys(c), Xc, F, 1, c->pk, c->part, c->s);
+    fock_t(c, Xc, F, 1);
     xlbomd_status q = fermi(c, F, &mu, Pout, true);
     if (q) return q;
     axpby(n2, 1.0, Pout, -1.0, Xc, c->f64[0], 0, c->s);
@@ -921,6 +987,32 @@ xlbomd_status xlbomd_matmul(xlbomd_handle c, const double *A, const double *B, d
   for (int r = 0; r < reps; ++r) mm(c, a, b, o, 1.0, sym_out ? 1 : 0);
   if (c->is32) convert(n2, c->w[2], 1, Cout, 0, c->s);
   HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_profile(xlbomd_handle c, int enable) {
+  if (!c) return XLBOMD_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  c->recs.clear();
+  c->prof = enable != 0;
+  if (c->prof && c->evpool.empty()) {
+    c->evpool.resize(2 * 65536);
+    for (auto &e : c->evpool) HIPCHK(c, hipEventCreate(&e));
+  }
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_profile_read(xlbomd_handle c, double *out) {
+  if (!c || !out) return XLBOMD_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  for (int i = 0; i < 3 * PC_N; ++i) out[i] = 0.0;
+  for (const auto &r : c->recs) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->evpool[r.ev], c->evpool[r.ev + 1]));
+    out[3 * r.cls + 0] += 1.0;
+    out[3 * r.cls + 1] += ms;
+    out[3 * r.cls + 2] += r.work;
+  }
   return XLBOMD_OK;
 }
 

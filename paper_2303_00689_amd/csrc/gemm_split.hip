@@ -1,6 +1,263 @@
-// Split-precision MFMA GEMM (BF16 / FP16 hi-lo splits of FP32 storage, FP32
-// accumulation).  Not enabled yet: every split mode reports an error.
+// Split-precision MFMA GEMM on FP32 storage for the Fermi-operator and
+// response chains.
+//
+// Every FP32 operand value x is split in registers into low-precision parts,
+//   BF16X3: x ~ h + l,           products h*h + h*l + l*h            (3 MFMA)
+//   BF16X6: x ~ h + l + l2,      + l*l + h*l2 + l2*h                 (6 MFMA)
+//   FP16X3: x ~ h + l / 2^11,    h*h into one accumulator, h*l + l*h into a
+//           second one that is scaled by 2^-11 at the end (the scaling keeps
+//           the low parts of small entries out of the FP16 subnormal range)
+// each part rounded to nearest-even, and the products accumulate in FP32 on
+// v_mfma_f32_16x16x32_{bf16,f16}.
+//
+// Tile 128 x 128 per workgroup of 256 threads (2 x 2 wavefronts of 64 x 64,
+// i.e. 4 x 4 MFMA blocks of 16 x 16 each).  K advances by 32 through
+// double-buffered LDS panels.  Both panels are stored k-fastest (row-major
+// [m][k] and [n][k]), which is what the MFMA operand layout wants:
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) .. 8 (l / 16) + 7]
+//   B (32 x 16): lane l holds B[8 (l / 16) .. + 7][l % 16]
+//   D (16 x 16): lane l holds D[4 (l / 16) + q][l % 16], q = 0..3
+// so operand rows are read straight from memory: op(A) = A for the symmetric
+// A operands of the chains, and op(B) = B^T, which is B for a symmetric B and
+// the requested transpose when btrans = 1.
 #include "common.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 namespace xl {
-void gemm_split(const GemmArgs &, int, hipStream_t) {}
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 128;
+constexpr int TK = 32;
+constexpr int PITCH = TK + 8;  // 16-bit elements per LDS row (padding breaks bank aliasing)
+
+template <int MODE>
+struct Parts {
+  static constexpr int P = (MODE == 1) ? 3 : 2;
+};
+
+__device__ inline unsigned short bf16_bits(float x) {
+  __bf16 b = (__bf16)x;  // round to nearest even
+  return __builtin_bit_cast(unsigned short, b);
 }
+__device__ inline float bf16_val(unsigned short u) {
+  return __builtin_bit_cast(float, (unsigned)u << 16);
+}
+__device__ inline unsigned short f16_bits(float x) {
+  _Float16 h = (_Float16)x;
+  return __builtin_bit_cast(unsigned short, h);
+}
+__device__ inline float f16_val(unsigned short u) {
+  return (float)__builtin_bit_cast(_Float16, u);
+}
+
+template <int MODE>
+__device__ inline void split(float x, unsigned short *out) {
+  if (MODE == 2) {
+    const unsigned short h = f16_bits(x);
+    out[0] = h;
+    out[1] = f16_bits((x - f16_val(h)) * 2048.0f);
+  } else {
+    const unsigned short h = bf16_bits(x);
+    const float r = x - bf16_val(h);
+    const unsigned short l = bf16_bits(r);
+    out[0] = h;
+    out[1] = l;
+    if (MODE == 1) out[2] = bf16_bits(r - bf16_val(l));
+  }
+}
+
+__device__ inline f4 mfma(us8 a, us8 b, f4 c, bool f16) {
+  if (f16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0,
+                                                  0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0,
+                                                 0, 0);
+}
+
+__device__ inline void tri_index(int bid, int T, int &bi, int &bj) {
+  int r = 0, start = 0;
+  while (start + (T - r) <= bid) {
+    start += T - r;
+    ++r;
+  }
+  bi = r;
+  bj = r + (bid - start);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
+  constexpr int P = Parts<MODE>::P;
+  constexpr bool F16 = (MODE == 2);
+  const int n = p.n;
+  int bi, bj;
+  if (p.sym) {
+    tri_index(blockIdx.x, T, bi, bj);
+  } else {
+    bi = blockIdx.x / T;
+    bj = blockIdx.x % T;
+  }
+  const int i0 = bi * TM, j0 = bj * TM;
+  // [buffer][part][row][k]
+  __shared__ unsigned short As[2][P][TM][PITCH];
+  __shared__ unsigned short Bs[2][P][TM][PITCH];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f4 acc[4][4];
+  f4 acc2[F16 ? 4 : 1][F16 ? 4 : 1];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+  if (F16) {
+#pragma unroll
+    for (int r = 0; r < (F16 ? 4 : 1); ++r)
+#pragma unroll
+      for (int c = 0; c < (F16 ? 4 : 1); ++c) acc2[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  const int kt_per = (n + TK - 1) / TK;
+  const int ktiles = kt_per * p.nprod;
+  // loader: 128 rows x 32 floats per operand; thread -> row tid / 2, 16 floats at 16 * (tid % 2)
+  const int lrow = tid >> 1, lk = (tid & 1) * 16;
+  float ra[16], rb[16];
+
+  auto load = [&](int kt) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * TK + lk;
+    const float *A = (const float *)p.A[prod];
+    const float *B = (const float *)p.B[prod];
+    const int ia = i0 + lrow, jb = j0 + lrow;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + 4 * v;
+      f4 x = f4{0.f, 0.f, 0.f, 0.f}, y = f4{0.f, 0.f, 0.f, 0.f};
+      if (ia < n && k < n) x = *(const f4 *)(A + (size_t)ia * n + k);
+      if (jb < n && k < n) y = *(const f4 *)(B + (size_t)jb * n + k);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[4 * v + q] = x[q];
+        rb[4 * v + q] = y[q];
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    unsigned short pa[P][16], pb[P][16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      unsigned short t[3];
+      split<MODE>(ra[e], t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) pa[q][e] = t[q];
+      split<MODE>(rb[e], t);
+#pragma unroll
+      for (int q = 0; q < P; ++q) pb[q][e] = t[q];
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      us8 *da = (us8 *)&As[buf][q][lrow][lk];
+      us8 *db = (us8 *)&Bs[buf][q][lrow][lk];
+      da[0] = us8{pa[q][0], pa[q][1], pa[q][2], pa[q][3], pa[q][4], pa[q][5], pa[q][6], pa[q][7]};
+      da[1] = us8{pa[q][8], pa[q][9], pa[q][10], pa[q][11], pa[q][12], pa[q][13], pa[q][14], pa[q][15]};
+      db[0] = us8{pb[q][0], pb[q][1], pb[q][2], pb[q][3], pb[q][4], pb[q][5], pb[q][6], pb[q][7]};
+      db[1] = us8{pb[q][8], pb[q][9], pb[q][10], pb[q][11], pb[q][12], pb[q][13], pb[q][14], pb[q][15]};
+    }
+  };
+
+  load(0);
+  store(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < ktiles) load(kt + 1);
+    us8 a[P][4], b[P][4];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[q][r] = *(const us8 *)&As[buf][q][wm + 16 * r + fr][fk];
+        b[q][r] = *(const us8 *)&Bs[buf][q][wn + 16 * r + fr][fk];
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (MODE == 2) {
+          acc[r][c] = mfma(a[0][r], b[0][c], acc[r][c], true);
+          acc2[r][c] = mfma(a[0][r], b[1][c], acc2[r][c], true);
+          acc2[r][c] = mfma(a[1][r], b[0][c], acc2[r][c], true);
+        } else {
+          // small terms first
+          if (MODE == 1) {
+            acc[r][c] = mfma(a[1][r], b[1][c], acc[r][c], false);
+            acc[r][c] = mfma(a[0][r], b[2][c], acc[r][c], false);
+            acc[r][c] = mfma(a[2][r], b[0][c], acc[r][c], false);
+          }
+          acc[r][c] = mfma(a[0][r], b[1][c], acc[r][c], false);
+          acc[r][c] = mfma(a[1][r], b[0][c], acc[r][c], false);
+          acc[r][c] = mfma(a[0][r], b[0][c], acc[r][c], false);
+        }
+      }
+    if (kt + 1 < ktiles) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const float *C1 = (const float *)p.C1;
+  const float *C2 = (const float *)p.C2;
+  float *out = (float *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+  const float alpha = (float)p.alpha, b1 = (float)p.beta1, b2 = (float)p.beta2, gam = (float)p.gamma;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + wn + 16 * c + fr;
+      const int ib = i0 + wm + 16 * r + 4 * (lane >> 4);
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ib + q;
+        float accv = acc[r][c][q];
+        if (MODE == 2) accv += acc2[r][c][q] * (1.0f / 2048.0f);
+        float x = alpha * accv;
+        if (i < n && j < n) {
+          const size_t off = (size_t)i * n + j;
+          if (C1) x += b1 * C1[off];
+          if (C2) x += b2 * C2[off];
+          if (i == j) x += gam;
+          out[off] = x;
+        }
+        v[q] = x;
+      }
+      if (mirror && j < n && ib < n) {
+        // four consecutive rows -> four consecutive columns of row j (ib % 4 == 0, n % 4 == 0)
+        *(f4 *)(out + (size_t)j * n + ib) = f4{v[0], v[1], v[2], v[3]};
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
+  const int T = (a.n + TM - 1) / TM;
+  const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
+  switch (prec) {
+    case 2: hipLaunchKernelGGL(k_gemm_split<1>, dim3(blocks), dim3(256), 0, s, a, T); break;
+    case 3: hipLaunchKernelGGL(k_gemm_split<2>, dim3(blocks), dim3(256), 0, s, a, T); break;
+    default: hipLaunchKernelGGL(k_gemm_split<0>, dim3(blocks), dim3(256), 0, s, a, T); break;
+  }
+}
+
+}  // namespace xl
