@@ -52,8 +52,15 @@ typedef enum {
   XLBOMD_FP64 = 0,   /* FP64 storage, FP64 MFMA                                    */
   XLBOMD_BF16X3 = 1, /* FP32 storage, two-term BF16 split, 3 products, FP32 acc   */
   XLBOMD_BF16X6 = 2, /* FP32 storage, three-term BF16 split, 6 products, FP32 acc */
-  XLBOMD_FP16X3 = 3  /* FP32 storage, two-term FP16 split with 2^11-scaled low   */
+  XLBOMD_FP16X3 = 3, /* FP32 storage, two-term FP16 split with 2^11-scaled low   */
                      /* parts, 3 products, FP32 acc                               */
+  /* Density matrix (Fermi chain and chemical potential) in FP64, the m response
+   * chains of the Krylov kernel in the named split precision.  The forces of
+   * eq. 37 depend on R, X and D0[X] only, so they keep FP64 accuracy while the
+   * split arithmetic carries the response chains. */
+  XLBOMD_DM64_BF16X3 = 4,
+  XLBOMD_DM64_BF16X6 = 5,
+  XLBOMD_DM64_FP16X3 = 6
 } xlbomd_precision;
 
 /* Synthetic NDDO-type sp Hamiltonian (stand-in for AM1/MNDO/PM3, which the
@@ -202,8 +209,8 @@ xlbomd_status xlbomd_md_init(xlbomd_handle h, xlbomd_md_state *st);
 xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, int m, double tol, int max_iter,
                          double *residual);
 
-/* Diagnostic: C = A B (+ optional symmetric-output mode) with the chain GEMM
- * of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric).  In
+/* Diagnostic: C = A B (+ optional symmetric-output mode) with the response-chain
+ * GEMM of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric).  In
  * split modes the operands are rounded to FP32 storage first, exactly as the
  * chains store their matrices.  For testing and timing the MFMA kernels. */
 xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, double *Cout,
@@ -214,10 +221,11 @@ xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, d
  * 65536 launches; later ones are not recorded); 0 stops.  Either call clears
  * earlier records. */
 xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
-/* Sums over the recorded launches, 3 classes x {launches, milliseconds,
- * algorithmic work}: [0..2] GEMM (work = flops the method needs: 2n^3 per
- * product, n^3 for a product with symmetric output), [3..5] Fock build and
- * [6..8] forces (work = HBM bytes: 220 per atom pair plus 16 n^2). */
+/* Sums over the recorded launches, 4 classes x {launches, milliseconds,
+ * algorithmic work}: [0..2] FP64 GEMM and [3..5] split-precision GEMM (work =
+ * flops of the products the method needs: 2n^3 per product, n^3 for a product
+ * with symmetric output, not counting the extra split products), [6..8] Fock
+ * build and [9..11] forces (work = HBM bytes: 220 per atom pair plus 16 n^2). */
 xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
 
 #ifdef __cplusplus

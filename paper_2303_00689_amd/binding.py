@@ -17,7 +17,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxlbomd.so")
 
-PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3}
+PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3,
+        "dm64_bf16x3": 4, "dm64_bf16x6": 5, "dm64_fp16x3": 6}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
           -5: "E_STATE", -6: "E_NOMEM"}
@@ -250,9 +251,9 @@ class Handle:
         self._check(self.lib.xlbomd_profile(self.h, int(bool(enable))), "profile")
 
     def profile_read(self):
-        out = (C.c_double * 9)()
+        out = (C.c_double * 12)()
         self._check(self.lib.xlbomd_profile_read(self.h, out), "profile_read")
-        names = ("gemm", "fock", "forces")
+        names = ("gemm_f64", "gemm_split", "fock", "forces")
         return {nm: dict(launches=int(out[3 * k]), ms=out[3 * k + 1], work=out[3 * k + 2])
                 for k, nm in enumerate(names)}
 

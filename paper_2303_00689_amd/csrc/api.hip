@@ -134,7 +134,9 @@ struct xlbomd_ctx {
   xlbomd_params prm{};
   xlbomd_model model{};
   hipStream_t s = nullptr;
-  int prec = 0, is32 = 0;
+  int prec = 0;                 // precision as requested at create
+  int prec_dm = 0, prec_rs = 0; // Fermi chain + mu shift / response chains
+  int is32 = 0, rs32 = 0;       // FP32 storage of the Fermi-chain / response-chain matrices
   size_t esz = 8;
   std::string err;
   bool geom = false;
@@ -148,10 +150,16 @@ struct xlbomd_ctx {
   void *Yc[LMAX + 1] = {}, *Zc[LMAX] = {};
   void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr;
   void *D = nullptr, *M = nullptr, *Qs = nullptr;
+  // response-precision copies of the cached chain (alias the above when the
+  // two chains share a precision)
+  void *Yr[LMAX + 1] = {}, *Zr[LMAX] = {};
+  void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *Mr = nullptr, *Qr = nullptr;
+  bool resp_copy = false;
   void *w[8] = {};
   int L = 0;
   bool chain_valid = false;
   double mu_chain = 0.0;
+  double mu_prev = NAN;   // chemical potential one MD step back (warm-start extrapolation)
   // FP64 work
   double *f64[6] = {};
   double *Vk[MMAX] = {}, *Wk[MMAX] = {};
@@ -186,7 +194,7 @@ xlbomd_status fail(xlbomd_ctx *c, xlbomd_status st, const char *fmt, ...) {
 bool dev_alloc(void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
 
 // kernel classes of the timing hooks
-enum { PC_GEMM = 0, PC_FOCK = 1, PC_FORCE = 2, PC_N = 3 };
+enum { PC_GEMM64 = 0, PC_GEMMS = 1, PC_FOCK = 2, PC_FORCE = 3, PC_N = 4 };
 
 int prof_begin(xlbomd_ctx *c) {
   if (!c->prof) return -1;
@@ -202,7 +210,7 @@ void prof_end(xlbomd_ctx *c, int e, int cls, double work) {
 }
 
 // ------------------------------------------------------------------ GEMM helper
-void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, int sym,
+void mm_p(xlbomd_ctx *c, int prec, const void *A, const void *B, void *out, double alpha, int sym,
         const void *C1 = nullptr, double b1 = 0.0, const void *C2 = nullptr, double b2 = 0.0,
         double gamma = 0.0, int btrans = 0, const void *A2 = nullptr, const void *B2 = nullptr) {
   GemmArgs g{};
@@ -222,13 +230,26 @@ void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, in
   g.gamma = gamma;
   g.sym = sym;
   const int e = prof_begin(c);
-  if (c->prec == XLBOMD_FP64)
+  if (prec == XLBOMD_FP64)
     gemm_f64(g, c->s);
   else
-    gemm_split(g, c->prec, c->s);
+    gemm_split(g, prec, c->s);
   const double n = (double)c->n;
-  prof_end(c, e, PC_GEMM, g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
+  prof_end(c, e, prec == XLBOMD_FP64 ? PC_GEMM64 : PC_GEMMS, g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
   ++c->n_gemm;
+}
+
+// GEMM in the Fermi-chain precision
+void mm(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, int sym,
+        const void *C1 = nullptr, double b1 = 0.0, const void *C2 = nullptr, double b2 = 0.0,
+        double gamma = 0.0, int btrans = 0, const void *A2 = nullptr, const void *B2 = nullptr) {
+  mm_p(c, c->prec_dm, A, B, out, alpha, sym, C1, b1, C2, b2, gamma, btrans, A2, B2);
+}
+// GEMM in the response-chain precision
+void mr(xlbomd_ctx *c, const void *A, const void *B, void *out, double alpha, int sym,
+        const void *C1 = nullptr, double b1 = 0.0, const void *C2 = nullptr, double b2 = 0.0,
+        double gamma = 0.0, int btrans = 0, const void *A2 = nullptr, const void *B2 = nullptr) {
+  mm_p(c, c->prec_rs, A, B, out, alpha, sym, C1, b1, C2, b2, gamma, btrans, A2, B2);
 }
 
 PairSys pairsys(xlbomd_ctx *c);
@@ -285,6 +306,15 @@ double eps_for_prec(int prec) {
   }
 }
 
+inline void split_prec(int prec, int &dm, int &rs) {
+  switch (prec) {
+    case XLBOMD_DM64_BF16X3: dm = XLBOMD_FP64; rs = XLBOMD_BF16X3; break;
+    case XLBOMD_DM64_BF16X6: dm = XLBOMD_FP64; rs = XLBOMD_BF16X6; break;
+    case XLBOMD_DM64_FP16X3: dm = XLBOMD_FP64; rs = XLBOMD_FP16X3; break;
+    default: dm = rs = prec; break;
+  }
+}
+
 // ------------------------------------------------------------------ Fermi chain
 // D = (exp(beta (F - mu I)) + I)^-1 (one spin) by the centred tanh-doubling
 // recursion Y_{i+1} = 2 Y_i (I + 4 Y_i^2)^-1 started from a degree-5 Taylor
@@ -313,7 +343,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   mm(c, S, S, P, TC2, 1, S, TC1, nullptr, 0.0, TC0);        // P = c0 I + c1 S + c2 S^2
   mm(c, V, P, c->Yc[0], 0.5, 1);                            // Y0 = V P / 2
   double yb = 0.5 * vb * (TC0 + TC1 * vb * vb + TC2 * vb * vb * vb * vb);
-  const double eps = eps_for_prec(c->prec);
+  const double eps = eps_for_prec(c->prec_dm);
   for (int i = 0; i < L; ++i) {
     void *Y = c->Yc[i];
     void *Si = c->w[1], *E = c->w[2], *Za = c->w[3], *Zb = c->w[4];
@@ -347,13 +377,18 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   return XLBOMD_OK;
 }
 
-// Exact chemical-potential shift: D(mu + dmu) = D (c I + (1 - c) D)^-1, c = exp(-beta dmu).
-// Pass 1 solves the trace series sum_k (1-c)^k Tr[D (I-D)^k] = N_occ (k < 5); pass 2
-// is one Newton step with its own exact shift.  Leaves D, M = D(I - D), and
-// Qs = sqrt(c1 c2) Q1^-1 Q2^-1 for the response.
-xlbomd_status mu_shift(xlbomd_ctx *c) {
+// Exact chemical-potential shift: D(mu + dmu) = D (c I + (1 - c) D)^-1 with
+// c = exp(-beta dmu), applied in passes.  Pass 1 solves the trace series
+// sum_k (1-c)^k Tr[D (I-D)^k] = N_occ (k < 5); every later pass is a Newton step
+// dmu = (N_occ - Tr D) / (beta Tr D(I-D)).  Each pass is clamped to
+// |beta dmu| <= 0.3 and is followed by its exact shift, so a poor warm start
+// costs a few shifts instead of a new chain.  Leaves D, M = D(I - D) and
+// Qs = sqrt(prod c_k) prod Q_k^-1 for the response; *dmu_out gets the total.
+// Returns XLBOMD_E_NOCONV (without changing mu) if the passes run out.
+xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   const int n = c->n, i32 = c->is32;
   hipStream_t s = c->s;
+  xlbomd_status st;
   void *D = c->D, *D2 = c->w[0], *D3 = c->w[1], *Mx = c->w[2], *Nx = c->w[3], *N2 = c->w[4],
        *MN = c->w[5];
   mm(c, D, D, D2, 1.0, 1);
@@ -371,51 +406,76 @@ xlbomd_status mu_shift(xlbomd_ctx *c) {
     dots((int)c->n2, 3, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
   }
   mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->dscal + S_MU1, s);
-  hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU1, nullptr,
-                     c->dscal + S_NEG1, nullptr, nullptr);
-  // Q = c I + (1 - c) D ; Newton-Schulz from Z0 = 2/(1+c) I (first iteration elementwise)
-  void *Q = c->w[0], *E = c->w[1], *Za = c->w[2], *Zb = c->w[3];
-  axpbyI_dev(n, c->dscal + S_MU1 + 4, 0.0, D, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 1, 0.0, Q, i32, s);
-  axpbyI_dev(n, c->dscal + S_NEG1, 0.0, Q, nullptr, 0.0, nullptr, nullptr, 1.0, E, i32, s);
-  axpbyI_dev(n, c->dscal + S_MU1 + 2, 0.0, E, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 2, 0.0, Za, i32, s);
-  for (int it = 1; it < 4; ++it) {
-    mm(c, Q, Za, E, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
-    mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);
-    std::swap(Za, Zb);
+  // buffers: Qacc accumulates prod Q_k^-1 (unscaled) in c->Qs
+  double dmu_total = 0.0, cprod = 1.0;
+  bool first = true, done = false;
+  for (int pass = 0; pass < 8 && !done; ++pass) {
+    double mres[5];
+    if (pass > 0) {
+      // Newton pass from Tr D and Tr D(I - D)
+      void *Dsq = c->w[0], *Mt = c->w[1];
+      mm(c, D, D, Dsq, 1.0, 1);
+      axpby((int)c->n2, 1.0, D, -1.0, Dsq, Mt, i32, s);
+      trace(n, D, c->dscal + S_T01, i32, c->red, s);
+      trace(n, Mt, c->dscal + S_T01 + 1, i32, c->red, s);
+      mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->dscal + S_MU1, s);
+    }
+    if ((st = get_scalars(c, S_MU1, 5, mres))) return st;
+    const bool clamped = mres[3] != 0.0;
+    const double cc = mres[1];
+    // the passes end with one unclamped Newton step after the last clamped one
+    if (pass > 0 && !clamped) done = true;
+    hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU1, nullptr,
+                       c->dscal + S_NEG1, nullptr, nullptr);
+    // Q = c I + (1 - c) D and its inverse by Newton-Schulz from Z0 = 2/(1+c) I
+    // (first iteration elementwise); e0 = |1-c|/(1+c) fixes the iteration count
+    void *Q = c->w[0], *E = c->w[1], *Za = c->w[2], *Zb = c->w[3];
+    axpbyI_dev(n, c->dscal + S_MU1 + 4, 0.0, D, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 1, 0.0, Q, i32, s);
+    axpbyI_dev(n, c->dscal + S_NEG1, 0.0, Q, nullptr, 0.0, nullptr, nullptr, 1.0, E, i32, s);
+    axpbyI_dev(n, c->dscal + S_MU1 + 2, 0.0, E, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 2, 0.0, Za, i32, s);
+    double e = std::fabs(1.0 - cc) / (1.0 + cc);
+    e = e * e;
+    const double eps = eps_for_prec(c->prec_dm);
+    for (int it = 1; it < 6 && e > eps; ++it) {
+      mm(c, Q, Za, E, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
+      mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);
+      std::swap(Za, Zb);
+      e = e * e;
+    }
+    // D <- D Q^-1 ; Qacc <- Qacc Q^-1
+    void *Dn = (Za == c->w[2]) ? c->w[3] : c->w[2];
+    mm(c, D, Za, Dn, 1.0, 1);
+    if (first) {
+      axpby((int)c->n2, 1.0, Za, 0.0, nullptr, c->Qs, i32, s);
+      first = false;
+    } else {
+      mm(c, c->Qs, Za, c->w[4], 1.0, 1);
+      axpby((int)c->n2, 1.0, c->w[4], 0.0, nullptr, c->Qs, i32, s);
+    }
+    axpby((int)c->n2, 1.0, Dn, 0.0, nullptr, D, i32, s);
+    dmu_total += mres[0];
+    cprod *= cc;
   }
-  void *Q1i = Za;
-  void *D1 = (Za == c->w[2]) ? c->w[3] : c->w[2];   // free buffer
-  mm(c, D, Q1i, D1, 1.0, 1);
-  // pass 2
-  void *D1sq = c->w[4], *M1 = c->w[5];
-  mm(c, D1, D1, D1sq, 1.0, 1);
-  axpby((int)c->n2, 1.0, D1, -1.0, D1sq, M1, i32, s);
-  trace(n, D1, c->dscal + S_T01, i32, c->red, s);
-  trace(n, M1, c->dscal + S_T01 + 1, i32, c->red, s);
-  mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->dscal + S_MU2, s);
-  hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU2, nullptr,
-                     nullptr, c->dscal + S_NEG2, c->dscal + S_SQC);
-  void *Q2 = c->w[0], *E2 = c->w[1], *Z2a = c->w[4], *Z2b = c->w[5];
-  axpbyI_dev(n, c->dscal + S_MU2 + 4, 0.0, D1, nullptr, 0.0, nullptr, c->dscal + S_MU2 + 1, 0.0, Q2, i32, s);
-  axpbyI_dev(n, c->dscal + S_NEG2, 0.0, Q2, nullptr, 0.0, nullptr, nullptr, 1.0, E2, i32, s);
-  axpbyI_dev(n, c->dscal + S_MU2 + 2, 0.0, E2, nullptr, 0.0, nullptr, c->dscal + S_MU2 + 2, 0.0, Z2a, i32, s);
-  mm(c, Q2, Z2a, E2, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
-  mm(c, Z2a, E2, Z2b, 1.0, 1, Z2a, 1.0);
-  // D <- D1 Z2 ; Qs = sqrt(c1 c2) Q1^-1 Z2
-  mm(c, D1, Z2b, D, 1.0, 1);
-  mm(c, Q1i, Z2b, c->Qs, 1.0, 1);
-  axpbyI_dev(n, c->dscal + S_SQC, 0.0, c->Qs, nullptr, 0.0, nullptr, nullptr, 0.0, c->Qs, i32, s);
+  if (!done) return XLBOMD_E_NOCONV;
+  axpby((int)c->n2, std::sqrt(cprod), c->Qs, 0.0, nullptr, c->Qs, i32, s);
   // M = D - D^2
   mm(c, D, D, c->M, -1.0, 1, D, 1.0);
   trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
   trace(n, D, c->dscal + S_TRD, i32, c->red, s);
+  *dmu_out = dmu_total;
   return XLBOMD_OK;
 }
 
 // canonical response of the cached chain to F1 (FP64, spin-summed F1): P1 = 2 D1
 xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
-  const int n = c->n, i32 = c->is32, L = c->L;
+  const int n = c->n, i32 = c->rs32, L = c->L;
   hipStream_t s = c->s;
+  // the Fermi-chain cache itself, or its response-precision copy
+  const bool cp = c->resp_copy;
+  void *const *Yr = cp ? c->Yr : c->Yc;
+  void *const *Zr = cp ? c->Zr : c->Zc;
+  void *Vr = cp ? c->Vr : c->Vst, *Pr = cp ? c->Pr : c->Pst, *Sr = cp ? c->Sr : c->Sst;
+  void *Mr = cp ? c->Mr : c->M, *Qr = cp ? c->Qr : c->Qs;
   const double sc = -c->beta / std::ldexp(1.0, L + 1);
   void *V1 = c->w[0], *dS = c->w[1], *dS2 = c->w[2], *Y1 = c->w[3], *G = c->w[4], *H = c->w[5],
        *Y1b = c->w[6];
@@ -425,30 +485,30 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   } else {
     axpby((int)c->n2, sc, F1, 0.0, nullptr, V1, 0, s);
   }
-  mm(c, c->Vst, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, c->Vst);          // V V1 + V1 V
-  mm(c, c->Sst, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, c->Sst);          // S dS + dS S
+  mr(c, Vr, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, Vr);          // V V1 + V1 V
+  mr(c, Sr, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, Sr);          // S dS + dS S
   axpby((int)c->n2, TC1, dS, TC2, dS2, dS2, i32, s);                                      // dP
-  mm(c, V1, c->Pst, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, c->Vst, dS2);         // (V1 P + V dP)/2
+  mr(c, V1, Pr, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Vr, dS2);         // (V1 P + V dP)/2
   // level i: Y1 <- [2 Y1 - 4 Y_{i+1} (Y_i Y1 + Y1 Y_i)] Z_i, evaluated as the
   // (symmetric) transpose Z_i [2 Y1 - 4 Y_{i+1} G]^T so that every GEMM operand
   // is symmetric or explicitly transposed
   for (int i = 0; i < L; ++i) {
-    mm(c, c->Yc[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, c->Yc[i]);      // G = Y Y1 + Y1 Y
-    mm(c, c->Yc[i + 1], G, H, 1.0, 0);                                                     // H = Y_{i+1} G
+    mr(c, Yr[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, Yr[i]);      // G = Y Y1 + Y1 Y
+    mr(c, Yr[i + 1], G, H, 1.0, 0);                                                     // H = Y_{i+1} G
     axpby((int)c->n2, 2.0, Y1, -4.0, H, H, i32, s);                                       // 2 Y1 - 4 H
-    mm(c, c->Zc[i], H, Y1b, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);                  // Z_i (..)^T
+    mr(c, Zr[i], H, Y1b, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);                  // Z_i (..)^T
     std::swap(Y1, Y1b);
   }
   // chemical-potential shift map: Qs Y1 Qs
-  mm(c, c->Qs, Y1, G, 1.0, 0);
-  mm(c, c->Qs, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+  mr(c, Qr, Y1, G, 1.0, 0);
+  mr(c, Qr, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
   // canonical projection: R - (Tr R / Tr M) M
   trace(n, H, c->dscal + S_TRR, i32, c->red, s);
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
                      c->dscal + S_CAN);
-  axpbyI_dev(n, nullptr, 2.0, H, c->dscal + S_CAN, 0.0, c->M, nullptr, 0.0, G, i32, s);
+  axpbyI_dev(n, nullptr, 2.0, H, c->dscal + S_CAN, 0.0, Mr, nullptr, 0.0, G, i32, s);
   // b = 2 * (-TrR/TrM) -> scale M term by 2 as well
-  axpbyI_dev(n, nullptr, 1.0, G, c->dscal + S_CAN, 0.0, c->M, nullptr, 0.0, G, i32, s);
+  axpbyI_dev(n, nullptr, 1.0, G, c->dscal + S_CAN, 0.0, Mr, nullptr, 0.0, G, i32, s);
   if (i32)
     convert((int)c->n2, G, 1, P1, 0, s);
   else
@@ -467,8 +527,7 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   double mu = *mu_io;
   bool cold = !std::isfinite(mu);
   bool converged = false;
-  int clamped = 0;
-  for (int attempt = 0; attempt < 60 && !converged; ++attempt) {
+  for (int attempt = 0; attempt < 4 && !converged; ++attempt) {
     if (cold) {
       // bisection on Tr D(mu) with full chains until the bracket is within 0.4/beta
       double a = lohi[0], b = lohi[1];
@@ -487,25 +546,29 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
       cold = false;
     }
     if ((st = run_chain(c, F, mu, lohi[0], lohi[1]))) return st;
-    if ((st = mu_shift(c))) return st;
-    double m1[5], m2[5];
-    if ((st = get_scalars(c, S_MU1, 5, m1))) return st;
-    if ((st = get_scalars(c, S_MU2, 5, m2))) return st;
-    if (m1[3] != 0.0 || m2[3] != 0.0) {
-      // the warm start was too far for the trace series: move by the clamped step,
-      // and fall back to bisection if that keeps happening
-      mu += m1[0] + (m1[3] != 0.0 ? 0.0 : m2[0]);
-      if (++clamped >= 3) {
-        cold = true;
-        clamped = 0;
-      }
+    double dmu = 0.0;
+    st = mu_shift(c, &dmu);
+    if (st == XLBOMD_E_NOCONV) {
+      // far from the warm start: bisection with full chains, then try again
+      cold = true;
       continue;
     }
-    mu += m1[0] + m2[0];
+    if (st) return st;
+    mu += dmu;
     converged = true;
   }
   if (!converged) return fail(c, XLBOMD_E_NOCONV, "chemical potential search did not converge");
   c->chain_valid = true;
+  if (c->resp_copy) {
+    const int n2 = (int)c->n2;
+    for (int i = 0; i <= c->L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, c->s);
+    for (int i = 0; i < c->L; ++i) convert(n2, c->Zc[i], c->is32, c->Zr[i], 1, c->s);
+    convert(n2, c->Vst, c->is32, c->Vr, 1, c->s);
+    convert(n2, c->Pst, c->is32, c->Pr, 1, c->s);
+    convert(n2, c->Sst, c->is32, c->Sr, 1, c->s);
+    convert(n2, c->Qs, c->is32, c->Qr, 1, c->s);
+    convert(n2, c->M, c->is32, c->Mr, 1, c->s);
+  }
   hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, c->s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
                      c->dscal + S_FIX);
   {
@@ -677,6 +740,15 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   f(c->Qs);
   for (auto &p : c->w) f(p);
   for (auto &p : c->f64) f(p);
+  if (c->resp_copy) {
+    for (auto &p : c->Yr) f(p);
+    for (auto &p : c->Zr) f(p);
+    f(c->Vr);
+    f(c->Pr);
+    f(c->Sr);
+    f(c->Mr);
+    f(c->Qr);
+  }
   for (int k = 0; k < c->kalloc; ++k) {
     f(c->Vk[k]);
     f(c->Wk[k]);
@@ -693,7 +765,7 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   if (sys->n_atoms < 1 || !sys->onecenter || (sys->n_atoms > 1 && !sys->noise55)) return XLBOMD_E_ARG;
   const double n = 4.0 * sys->n_atoms;
   if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
-  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 3)
+  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6)
     return XLBOMD_E_ARG;
   xlbomd_ctx *c = new xlbomd_ctx();
   c->N = sys->n_atoms;
@@ -706,7 +778,10 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   c->s = (hipStream_t)stream;
   c->beta = 1.0 / (KB * prm->T_e);
   c->prec = prm->prec;
-  c->is32 = prm->prec != XLBOMD_FP64;
+  split_prec(prm->prec, c->prec_dm, c->prec_rs);
+  c->is32 = c->prec_dm != XLBOMD_FP64;
+  c->rs32 = c->prec_rs != XLBOMD_FP64;
+  c->resp_copy = c->prec_dm != c->prec_rs;
   c->esz = c->is32 ? 4 : 8;
   const int N = c->N, T = (N + 15) / 16;
   const int ntp = T * (T + 1) / 2;
@@ -734,8 +809,18 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   A(&c->D, mb);
   A(&c->M, mb);
   A(&c->Qs, mb);
-  for (auto &p : c->w) A(&p, mb);
+  for (auto &p : c->w) A(&p, c->n2 * 8);  // work matrices hold either element type
   for (auto &p : c->f64) A((void **)&p, c->n2 * 8);
+  if (c->resp_copy) {
+    const size_t m4 = c->n2 * 4;
+    for (auto &p : c->Yr) A(&p, m4);
+    for (auto &p : c->Zr) A(&p, m4);
+    A(&c->Vr, m4);
+    A(&c->Pr, m4);
+    A(&c->Sr, m4);
+    A(&c->Mr, m4);
+    A(&c->Qr, m4);
+  }
   if (!ok) {
     xlbomd_destroy(c);
     return XLBOMD_E_NOMEM;
@@ -857,8 +942,11 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
   double *P0 = c->f64[4];
   fock_t(c, X, F, 1);
   // P0 lives in f64[4] only until the Krylov call, which reuses it: keep a copy in Vk? use Wk slots
+  // warm start: linear extrapolation of mu from the last two steps
   double mu = st->mu;
+  if (std::isfinite(st->mu) && std::isfinite(c->mu_prev)) mu = 2.0 * st->mu - c->mu_prev;
   if ((s = fermi(c, F, &mu, P0, true))) return s;
+  c->mu_prev = st->mu;
   st->mu = mu;
   // forces first (Krylov reuses f64[0..4])
   if ((s = energy_forces(c, P0, X, c->frc, e))) return s;
@@ -871,6 +959,7 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
 
 xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
   if (!c || !st || !st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+  c->mu_prev = NAN;
   // replicate X(t0) into every history slot
   const double *X0 = st->X + (size_t)st->head * c->n2;
   for (int k = 1; k < 7; ++k)
@@ -977,15 +1066,15 @@ xlbomd_status xlbomd_matmul(xlbomd_handle c, const double *A, const double *B, d
   const int n2 = (int)c->n2;
   const void *a = A, *b = B;
   void *o = Cout;
-  if (c->is32) {
+  if (c->rs32) {
     convert(n2, A, 0, c->w[0], 1, c->s);
     convert(n2, B, 0, c->w[1], 1, c->s);
     a = c->w[0];
     b = c->w[1];
     o = c->w[2];
   }
-  for (int r = 0; r < reps; ++r) mm(c, a, b, o, 1.0, sym_out ? 1 : 0);
-  if (c->is32) convert(n2, c->w[2], 1, Cout, 0, c->s);
+  for (int r = 0; r < reps; ++r) mr(c, a, b, o, 1.0, sym_out ? 1 : 0);
+  if (c->rs32) convert(n2, c->w[2], 1, Cout, 0, c->s);
   HIPCHK(c, hipGetLastError());
   return XLBOMD_OK;
 }

@@ -30,6 +30,9 @@ BOUND = {
     "bf16x3": dict(mm=1e-4, P=6e-4, P1=1e-2, F=2e-2),
     "bf16x6": dict(mm=2e-6, P=2e-5, P1=3e-4, F=1e-3),
     "fp16x3": dict(mm=2e-6, P=2e-5, P1=3e-4, F=1e-3),
+    # FP64 density matrix, split response chains: P and forces at the FP64 bar
+    "dm64_bf16x3": dict(mm=1e-4, P=1e-10, P1=1e-2, F=1e-9),
+    "dm64_fp16x3": dict(mm=2e-6, P=1e-10, P1=3e-4, F=1e-9),
 }
 MODES = sorted(BOUND)
 
@@ -62,6 +65,8 @@ def test_split_matmul(binding, mode, n_atoms, sym):
     A32 = A.astype(np.float32).astype(np.float64)
     B32 = B.astype(np.float32).astype(np.float64)
     err = _rel(C.cpu().numpy(), A32 @ B32)
+    if mode.startswith("dm64"):
+        pass  # matmul runs the response-chain (split) GEMM
     print(f"{mode} n={n} sym={sym} matmul rel err {err:.3e}")
     assert err <= BOUND[mode]["mm"]
     h.close()
@@ -100,6 +105,6 @@ def test_split_density_response_forces(binding, mode, name):
     print(f"{mode} {name}: P {errP:.3e}  P1 {errP1:.3e}  forces {errF:.3e} eV/A")
     assert errP <= BOUND[mode]["P"]
     assert errP1 <= BOUND[mode]["P1"]
-    assert errF <= BOUND[mode]["F"]
+    assert errF <= BOUND[mode]["F"] * (1.0 if not mode.startswith("dm64") else max(1.0, np.abs(fref).max()))
     assert abs(np.trace(P.cpu().numpy()) - sys_.n_elec) <= 1e-5 * sys_.n_elec
     h.close()
