@@ -9,6 +9,8 @@
 #include <string>
 #include <vector>
 
+#include <hipsolver/hipsolver.h>
+
 #include "../../include/xlbomd.h"
 #include "common.h"
 
@@ -39,6 +41,7 @@ enum Slot {
   S_CAN = 52,      // -Tr R / Tr M
   S_TRD = 54,      // final trace of D
   S_FIX = 56,      // first-order trace correction coefficient
+  S_ENT = 59,      // entropy S/k_B
   S_TRP = 58,      // trace of the returned P
   S_ENER = 60,     // 3 energies
   S_DOTS = 64,     // 40 dots
@@ -77,6 +80,29 @@ __global__ void k_finalize_P(size_t n2, const T *D, const T *M, const double *c,
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
        i += (size_t)gridDim.x * blockDim.x)
     P[i] = 2.0 * ((double)D[i] + cv * (double)M[i]);
+}
+
+// electronic entropy S/k_B = -sum [f ln f + (1-f) ln(1-f)] over one-spin levels
+// (eq. 4) with f from eq. 7, written through x = beta (eps - mu) as
+// ln(1 + e^-|x|) + |x| e^-|x| / (1 + e^-|x|), which is exact and cannot overflow
+__global__ void k_entropy_partial(int n, const double *eps, double mu, double beta, double *part) {
+  double v = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ax = fabs(beta * (eps[i] - mu));
+    const double e = exp(-ax);
+    v += log1p(e) + ax * e / (1.0 + e);
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __shared__ double sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+__global__ void k_sum_fixed(int m, const double *part, double *out) {
+  if (threadIdx.x) return;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += part[i];
+  *out = s;
 }
 
 // out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device
@@ -164,6 +190,11 @@ struct xlbomd_ctx {
   double *f64[6] = {};
   double *Vk[MMAX] = {}, *Wk[MMAX] = {};
   int kalloc = 0;
+  // entropy diagnostic: FP64 eigenvalues of F (library eigenvalue solve)
+  hipsolverHandle_t solver = nullptr;
+  double *eig = nullptr, *eig_work = nullptr;
+  int *eig_info = nullptr;
+  int eig_lwork = 0;
   // stats and optional per-launch timing (HIP events on the handle's stream)
   long long n_gemm = 0;
   bool prof = false;
@@ -703,6 +734,34 @@ xlbomd_status energy_forces(xlbomd_ctx *c, const double *P0, const double *X, do
   return XLBOMD_OK;
 }
 
+// S/k_B of the Fermi occupations of F at mu, from FP64 eigenvalues of F
+xlbomd_status entropy(xlbomd_ctx *c, const double *F, double mu, double *S) {
+  const int n = c->n;
+  if (!c->solver) {
+    if (hipsolverCreate(&c->solver) != HIPSOLVER_STATUS_SUCCESS)
+      return fail(c, XLBOMD_E_HIP, "hipsolverCreate failed");
+    int lwork = 0;
+    if (hipsolverDnDsyevd_bufferSize(c->solver, HIPSOLVER_EIG_MODE_NOVECTOR, HIPSOLVER_FILL_MODE_LOWER, n,
+                                     c->f64[2], n, c->f64[3], &lwork) != HIPSOLVER_STATUS_SUCCESS)
+      return fail(c, XLBOMD_E_HIP, "syevd buffer query failed");
+    c->eig_lwork = lwork;
+    if (!dev_alloc((void **)&c->eig, sizeof(double) * n) ||
+        !dev_alloc((void **)&c->eig_work, sizeof(double) * std::max(lwork, 1)) ||
+        !dev_alloc((void **)&c->eig_info, sizeof(int)))
+      return fail(c, XLBOMD_E_NOMEM, "eigenvalue workspace allocation failed");
+  }
+  hipsolverSetStream(c->solver, c->s);
+  double *Fw = c->f64[2];
+  HIPCHK(c, hipMemcpyAsync(Fw, F, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
+  if (hipsolverDnDsyevd(c->solver, HIPSOLVER_EIG_MODE_NOVECTOR, HIPSOLVER_FILL_MODE_LOWER, n, Fw, n, c->eig,
+                        c->eig_work, c->eig_lwork, c->eig_info) != HIPSOLVER_STATUS_SUCCESS)
+    return fail(c, XLBOMD_E_HIP, "syevd failed");
+  const int nb = std::min((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_entropy_partial, dim3(nb), dim3(256), 0, c->s, n, c->eig, mu, c->beta, c->red);
+  hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(64), 0, c->s, nb, c->red, c->dscal + S_ENT);
+  return get_scalars(c, S_ENT, 1, S);
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -754,6 +813,10 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
     f(c->Wk[k]);
   }
   for (auto e : c->evpool) hipEventDestroy(e);
+  if (c->solver) hipsolverDestroy(c->solver);
+  f(c->eig);
+  f(c->eig_work);
+  f(c->eig_info);
   delete c;
   return XLBOMD_OK;
 }
@@ -881,7 +944,7 @@ xlbomd_status xlbomd_fermi_dm(xlbomd_handle c, const double *F, double *mu, doub
   if (!c || !F || !mu || !P || F == P) return c ? fail(c, XLBOMD_E_ARG, "bad fermi_dm arguments") : XLBOMD_E_ARG;
   xlbomd_status st = fermi(c, F, mu, P, true);
   if (st) return st;
-  if (entropy) *entropy = NAN;
+  if (entropy && (st = ::entropy(c, F, *mu, entropy))) return st;
   HIPCHK(c, hipGetLastError());
   return XLBOMD_OK;
 }
@@ -934,7 +997,7 @@ xlbomd_status xlbomd_integrate(xlbomd_handle c, xlbomd_md_state *st) {
 }
 
 static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e[3], int *rank,
-                                    double *rel, double *w0) {
+                                    double *rel, double *w0, double *S = nullptr) {
   xlbomd_status s;
   if ((s = xlbomd_set_geometry(c, st->R))) return s;
   const double *X = st->X + (size_t)st->head * c->n2;
@@ -948,6 +1011,7 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
   if ((s = fermi(c, F, &mu, P0, true))) return s;
   c->mu_prev = st->mu;
   st->mu = mu;
+  if (S && (s = entropy(c, F, mu, S))) return s;
   // forces first (Krylov reuses f64[0..4])
   if ((s = energy_forces(c, P0, X, c->frc, e))) return s;
   accel(3 * c->N, c->frc, ACC / c->model.mass, st->A, c->s);
@@ -978,8 +1042,8 @@ xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlb
     if ((s = xlbomd_integrate(c, st))) return s;
     double e[3];
     int rank = 0;
-    double rel = 0, w0 = 0;
-    if ((s = evaluate_state(c, st, e, &rank, &rel, &w0))) return s;
+    double rel = 0, w0 = 0, S = 0.0;
+    if ((s = evaluate_state(c, st, e, &rank, &rel, &w0, rep ? &S : nullptr))) return s;
     kick_drift(3 * c->N, st->R, st->V, st->A, c->prm.dt, 0, c->s);
     if (rep) {
       // kinetic energy from V (host copy of a few KB)
@@ -991,8 +1055,8 @@ xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlb
       ke *= 0.5 * c->model.mass / ACC;
       xlbomd_report &r = rep[k];
       r.KE = ke;
-      r.U = e[0] + e[1] + e[2];
-      r.TS = NAN;
+      r.TS = 2.0 * S / c->beta;  // -2 T_e S with S in units of k_B: 2 k_B T_e S = 2 S / beta
+      r.U = e[0] + e[1] + e[2] - r.TS;
       r.E_tot = r.KE + r.U;
       const int dof = std::max(3 * c->N - 3, 1);
       r.T_ion = 2.0 * ke / (dof * KB);

@@ -87,9 +87,10 @@ def test_fermi_dm_cold_and_warm(case):
     s = case.sys
     F = case.t(case.F)
     P = torch.empty_like(F)
-    mu, _ = case.h.fermi_dm(F, P)
+    mu, S = case.h.fermi_dm(F, P)
     Pg = case.np(P)
     assert _rel(Pg, case.dm["P"]) <= TOL
+    assert S == pytest.approx(density.entropy(case.dm["f"]), rel=1e-9, abs=1e-9)
     assert abs(np.trace(Pg) - s.n_elec) <= 1e-11 * s.n_elec
     # warm start from a slightly wrong mu lands on the same density matrix
     mu2, _ = case.h.fermi_dm(F, P, mu=mu + 0.02)
@@ -164,7 +165,36 @@ def test_md_step_matches_oracle(case, lib):
     assert np.abs(case.np(state.A) - o2.A).max() <= 1e-9 * max(1e-3, np.abs(o2.A).max())
     W0 = np.linalg.norm(rep["W0"])
     assert np.abs(case.np(state.Y) - o2.Y).max() <= 1e-8 * max(W0, 1e-12)
-    assert reps[0]["U"] + 2.0 * 0 == pytest.approx(rep["U"] + rep["TS"], rel=1e-10)
+    assert reps[0]["TS"] == pytest.approx(rep["TS"], rel=1e-9, abs=1e-9)
+    assert reps[0]["U"] == pytest.approx(rep["U"], rel=1e-10)
+    assert reps[0]["E_tot"] == pytest.approx(rep["E_tot"], rel=1e-10)
+
+
+def test_nve_energy_fluctuation_scales_as_dt_squared(lib):
+    # the GPU trajectory from a converged 6-atom state: the spread of the
+    # constant of motion (eq. 26) over 2 fs shrinks ~4x when dt is halved
+    import dataclasses
+    sys_ = carbon_cluster(6, 13)
+    st0 = dynamics.Settings(T_e=3000.0, m=3, dt=0.2)
+    Xmin = dynamics.scf(sys_, st0, m=30)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    spans = []
+    for dt in (0.2, 0.1):
+        h = lib.Handle(sys_.n_atoms, sys_.n_elec, sys_.onecenter, sys_.noise, sys_.params,
+                       T_e=3000.0, m=3, dt=dt)
+        n = sys_.n_orb
+        Xr = torch.zeros((7, n, n), dtype=torch.float64, device=dev)
+        Xr[0] = t(Xmin)
+        state = lib.MDState(R=t(sys_.R), V=t(sys_.V), A=torch.zeros((sys_.n_atoms, 3), dtype=torch.float64, device=dev),
+                            X=Xr, Y=torch.zeros((n, n), dtype=torch.float64, device=dev))
+        h.md_init(state)
+        reps = h.step(state, int(round(2.0 / dt)))
+        E = np.array([r["E_tot"] for r in reps])
+        spans.append(np.ptp(E))
+        h.close()
+    ratio = spans[0] / spans[1]
+    assert 3.0 < ratio < 5.5, (spans, ratio)
 
 
 @pytest.mark.parametrize("n_atoms", [10, 50, 67])
