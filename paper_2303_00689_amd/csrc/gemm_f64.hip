@@ -58,43 +58,47 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
   const int kt_per = (n + BK - 1) / BK;
   const int ktiles = kt_per * p.nprod;
 
-  // register staging: 4 doubles of A and 4 of B per thread
-  double ra[4], rb[4];
   // A panel rows k (16) x cols m (64): thread -> (k = tid / 16, m = 4 * (tid % 16))
   const int la_k = tid >> 4, la_m = (tid & 15) * 4;
   // B panel, normal: same mapping; transposed: rows j (64) x 16 k: (j = tid / 4, k = 4 * (tid % 4))
   const int lbt_j = tid >> 2, lbt_k = (tid & 3) * 4;
 
+  // Unconditional loads from clamped in-bounds addresses (n % 4 == 0, so a
+  // group of four consecutive columns is either all in range or all out);
+  // the zeroing select happens in store(), after the MFMAs of the current
+  // panel, so that the loads of the next panel stay in flight during them.
+  typedef double dd2 __attribute__((ext_vector_type(2)));
+  dd2 ua[2], ub[2];
+  bool oka = true, okb = true;
   auto load = [&](int kt) {
     const int prod = kt / kt_per;
     const int k0 = (kt - prod * kt_per) * BK;
     const double *A = (const double *)p.A[prod];
     const double *B = (const double *)p.B[prod];
     {
-      const int k = k0 + la_k;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = i0 + la_m + q;
-        ra[q] = (k < n && m < n) ? A[(size_t)k * n + m] : 0.0;
-      }
+      const int k = k0 + la_k, m = i0 + la_m;
+      oka = k < n && m < n;
+      const double *src = A + (size_t)(k < n ? k : n - 1) * n + (m < n ? m : n - 4);
+      ua[0] = *(const dd2 *)src;
+      ua[1] = *(const dd2 *)(src + 2);
     }
     if (!p.btrans) {
-      const int k = k0 + la_k;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + la_m + q;
-        rb[q] = (k < n && j < n) ? B[(size_t)k * n + j] : 0.0;
-      }
+      const int k = k0 + la_k, j = j0 + la_m;
+      okb = k < n && j < n;
+      const double *src = B + (size_t)(k < n ? k : n - 1) * n + (j < n ? j : n - 4);
+      ub[0] = *(const dd2 *)src;
+      ub[1] = *(const dd2 *)(src + 2);
     } else {
-      const int j = j0 + lbt_j;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + lbt_k + q;
-        rb[q] = (k < n && j < n) ? B[(size_t)j * n + k] : 0.0;
-      }
+      const int j = j0 + lbt_j, k = k0 + lbt_k;
+      okb = k < n && j < n;
+      const double *src = B + (size_t)(j < n ? j : n - 1) * n + (k < n ? k : n - 4);
+      ub[0] = *(const dd2 *)src;
+      ub[1] = *(const dd2 *)(src + 2);
     }
   };
   auto store = [&](int buf) {
+    const double ra[4] = {oka ? ua[0][0] : 0.0, oka ? ua[0][1] : 0.0, oka ? ua[1][0] : 0.0, oka ? ua[1][1] : 0.0};
+    const double rb[4] = {okb ? ub[0][0] : 0.0, okb ? ub[0][1] : 0.0, okb ? ub[1][0] : 0.0, okb ? ub[1][1] : 0.0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) As[buf][la_k][la_m + q] = ra[q];
     if (!p.btrans) {

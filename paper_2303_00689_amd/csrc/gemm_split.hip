@@ -130,28 +130,42 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
   const int ktiles = kt_per * p.nprod;
   // loader: 128 rows x 32 floats per operand; thread -> row tid / 2, 16 floats at 16 * (tid % 2)
   const int lrow = tid >> 1, lk = (tid & 1) * 16;
-  float ra[16], rb[16];
+  // raw loaded rows and their validity; the zeroing select and the split
+  // happen in store(), after the MFMAs of the current panel, so the loads of
+  // the next panel stay in flight during them
+  f4 xa[4], xb[4];
+  bool vla = true, vlb = true, vk[4] = {true, true, true, true};
 
+  // Loads are unconditional (clamped in-bounds addresses), so no branch
+  // separates them and the compiler can keep all of them in flight.
   auto load = [&](int kt) {
     const int prod = kt / kt_per;
     const int k0 = (kt - prod * kt_per) * TK + lk;
     const float *A = (const float *)p.A[prod];
     const float *B = (const float *)p.B[prod];
     const int ia = i0 + lrow, jb = j0 + lrow;
+    vla = ia < n;
+    vlb = jb < n;
+    const size_t ra_off = (size_t)(vla ? ia : n - 1) * n;
+    const size_t rb_off = (size_t)(vlb ? jb : n - 1) * n;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = k0 + 4 * v;
-      f4 x = f4{0.f, 0.f, 0.f, 0.f}, y = f4{0.f, 0.f, 0.f, 0.f};
-      if (ia < n && k < n) x = *(const f4 *)(A + (size_t)ia * n + k);
-      if (jb < n && k < n) y = *(const f4 *)(B + (size_t)jb * n + k);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ra[4 * v + q] = x[q];
-        rb[4 * v + q] = y[q];
-      }
+      vk[v] = k < n;
+      const int kc = vk[v] ? k : n - 4;
+      xa[v] = *(const f4 *)(A + ra_off + kc);
+      xb[v] = *(const f4 *)(B + rb_off + kc);
     }
   };
   auto store = [&](int buf) {
+    float ra[16], rb[16];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[4 * v + q] = (vla && vk[v]) ? xa[v][q] : 0.0f;
+        rb[4 * v + q] = (vlb && vk[v]) ? xb[v][q] : 0.0f;
+      }
     unsigned short pa[P][16], pb[P][16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
