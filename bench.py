@@ -144,6 +144,8 @@ def main():
     prof = h.profile_read()
     h.profile(False)
     steps_per_s = args.steps / elapsed
+    # one more (untimed) step with the full report: shadow energy, chain depth
+    rep = h.step(state, 1, report=True)[0]
 
     # dominant kernel: the GEMM class with the larger share of the timed region
     split_kind = args.prec.split("_")[-1]
@@ -180,6 +182,7 @@ def main():
                      "share_of_step": g["ms"] * 1e-3 / elapsed},
         "other_gemm": {"fp64_ms_per_step": g64["ms"] / args.steps, "split_ms_per_step": gs["ms"] / args.steps,
                        "fp64_tflops": (g64["work"] / (g64["ms"] * 1e-3) / 1e12) if g64["ms"] > 0 else 0.0},
+        "step_report": {k: rep[k] for k in ("E_tot", "mu", "W0", "relres", "rank", "levels", "mu_passes")},
         "fock_roofline": {"bound": "hbm", "achieved": fock_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": fock_gbs / HBM_PEAK_GBS, "launches": fk["launches"],
                           "avg_launch_us": 1e3 * fk["ms"] / max(fk["launches"], 1)},

@@ -129,6 +129,8 @@ typedef struct {
   double relres;  /* relative residual of the rank-m kernel                   */
   int rank;       /* Krylov rank used                                          */
   int status;     /* XLBOMD_OK or the guard that tripped                       */
+  int levels;     /* recursion levels L of the Fermi chain                      */
+  int mu_passes;  /* exact chemical-potential shift passes (0: series shift)   */
 } xlbomd_report;
 
 /* Create a handle for one system; allocates all device workspace.  `stream`

@@ -56,7 +56,7 @@ class MDStateC(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("E_tot", "KE", "U", "TS", "T_ion", "mu", "W0", "relres")] + \
-               [("rank", C.c_int), ("status", C.c_int)]
+               [("rank", C.c_int), ("status", C.c_int), ("levels", C.c_int), ("mu_passes", C.c_int)]
 
 
 _lib = None

@@ -13,6 +13,7 @@
 
 #include "../../include/xlbomd.h"
 #include "common.h"
+#include "small_eig.h"
 
 using namespace xl;
 
@@ -22,20 +23,18 @@ constexpr int LMAX = 24;     // maximum number of recursion levels
 constexpr int MMAX = 32;     // maximum Krylov rank
 constexpr double KB = 8.617333262e-5;           // eV / K
 constexpr double ACC = 9.648533e-3;             // (eV / (Angstrom amu)) -> Angstrom / fs^2
+constexpr int LANCZOS_K = 32;                 // Lanczos steps for the spectral bounds
 constexpr double VMAX = 1.2;                    // bound on |v| at the start of the chain
-// odd Taylor coefficients of tanh(v) / v in powers of v^2 (degree-5 start)
-constexpr double TC0 = 1.0, TC1 = -1.0 / 3.0, TC2 = 2.0 / 15.0;
+// Taylor coefficients of tanh(v) / v in powers of v^2 (degree-9 start)
+constexpr double TC0 = 1.0, TC1 = -1.0 / 3.0, TC2 = 2.0 / 15.0, TC3 = -17.0 / 315.0,
+                 TC4 = 62.0 / 2835.0;
 
 // device scalar slots
 enum Slot {
   S_LOHI = 0,      // 2
   S_TAU = 4,       // 8: tau_0..tau_4
   S_MU1 = 16,      // 5: dmu, c, 2/(1+c), flag, 1-c
-  S_NEG1 = 24,     // -2/(1+c)
   S_T01 = 28,      // 2: Tr D1, Tr D1(I-D1)
-  S_MU2 = 32,      // 5
-  S_NEG2 = 40,
-  S_SQC = 44,      // sqrt(c c2)
   S_TRM = 48,      // Tr M
   S_TRR = 50,      // Tr R (response)
   S_CAN = 52,      // -Tr R / Tr M
@@ -50,17 +49,9 @@ enum Slot {
   S_KCOEF = 1184,  // 32
   S_KRES = 1216,   // 3: resid^2, ||W0||^2, singular
   S_ORTH = 1220,   // 33 orthogonalisation coefficients
-  S_TOTAL = 1280
+  S_LANC = 1280,   // 2 * LANCZOS_K: alpha_j, beta_j
+  S_TOTAL = 1344
 };
-
-__global__ void k_scal_misc(const double *mu1, const double *mu2, const double *trm, double *neg1,
-                            double *neg2, double *sqc) {
-  if (threadIdx.x) return;
-  if (neg1) *neg1 = -mu1[2];
-  if (neg2) *neg2 = -mu2[2];
-  if (sqc) *sqc = sqrt(mu1[1] * mu2[1]);
-  (void)trm;
-}
 
 __global__ void k_canon(const double *trR, const double *trM, double *out) {
   if (threadIdx.x) return;
@@ -171,18 +162,21 @@ struct xlbomd_ctx {
   float *noise_t = nullptr;
   double *pk = nullptr, *part = nullptr, *pk3 = nullptr, *fpart = nullptr, *epart = nullptr;
   double *dscal = nullptr, *red = nullptr, *frc = nullptr;
+  double *lq = nullptr, *lw = nullptr;  // Lanczos vectors ((K+1) x n) and product
   const double **dptr = nullptr;  // device pointer arrays (for lincomb / orth)
   // chain storage (chain element type)
   void *Yc[LMAX + 1] = {}, *Zc[LMAX] = {};
-  void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr;
+  void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr, *S2st = nullptr, *Bst = nullptr;
   void *D = nullptr, *M = nullptr, *Qs = nullptr;
   // response-precision copies of the cached chain (alias the above when the
   // two chains share a precision)
   void *Yr[LMAX + 1] = {}, *Zr[LMAX] = {};
-  void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *Mr = nullptr, *Qr = nullptr;
+  void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *S2r = nullptr, *Br = nullptr, *Mr = nullptr,
+       *Qr = nullptr;
   bool resp_copy = false;
   void *w[8] = {};
   int L = 0;
+  int mu_passes = 0;
   bool chain_valid = false;
   double mu_chain = 0.0;
   double mu_prev = NAN;   // chemical potential one MD step back (warm-start extrapolation)
@@ -328,9 +322,13 @@ xlbomd_status get_scalars(xlbomd_ctx *c, int slot, int cnt, double *out) {
   return XLBOMD_OK;
 }
 
+// Newton-Schulz stopping bound (a-priori error of each inverse).  In FP64 the
+// relative error of every level's inverse passes unamplified into Y for the
+// levels near mu, so L levels at 3e-12 keep D within ~1e-11 of the exact
+// Fermi matrix.
 double eps_for_prec(int prec) {
   switch (prec) {
-    case XLBOMD_FP64: return 1e-16;
+    case XLBOMD_FP64: return 3e-12;
     case XLBOMD_BF16X6: return 1e-8;
     case XLBOMD_FP16X3: return 1e-7;
     default: return 1e-6;
@@ -346,9 +344,72 @@ inline void split_prec(int prec, int &dm, int &rs) {
   }
 }
 
+// Lanczos start vector: fixed pseudo-random entries (a sine hash of the index),
+// normalised, written once into row 0 of the Lanczos buffer
+bool lanczos_start(xlbomd_ctx *c) {
+  std::vector<double> q(c->n);
+  double nrm = 0.0;
+  for (int i = 0; i < c->n; ++i) {
+    const double h = std::sin(i * 12.9898 + 78.233) * 43758.5453;
+    q[i] = h - std::floor(h) - 0.5;
+    nrm += q[i] * q[i];
+  }
+  for (auto &v : q) v /= std::sqrt(nrm);
+  return hipMemcpy(c->lq, q.data(), sizeof(double) * c->n, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Bounds [lo, hi] on the spectrum of the symmetric F.  K Lanczos steps give
+// Ritz values theta_min, theta_max and their residual norms
+// r = beta_K |s_K| (s the Ritz vector of the tridiagonal); the bounds are
+// theta -/+ (r + 1e-3 (theta_max - theta_min)), clipped to the Gershgorin
+// interval, which is rigorous but much wider for large clusters.  The chain
+// depth L grows with log2 of the bound, so each factor of two saved is one
+// recursion level less in the density matrix and in every response.
+xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
+  const int n = c->n;
+  gershgorin(n, F, c->dscal + S_LOHI, c->red, c->s);
+  const int K = std::min(LANCZOS_K, n);
+  lanczos(n, K, F, c->lq, c->lw, c->dscal + S_LANC, c->s);
+  double g[2], ab[2 * LANCZOS_K];
+  xlbomd_status st = get_scalars(c, S_LOHI, 2, g);
+  if (st) return st;
+  if (!std::isfinite(g[0]) || !std::isfinite(g[1]))
+    return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
+  if ((st = get_scalars(c, S_LANC, 2 * K, ab))) return st;
+  lohi[0] = g[0];
+  lohi[1] = g[1];
+  const double scale = std::max(std::fabs(g[0]), std::fabs(g[1]));
+  int k = K;
+  for (int j = 0; j < K; ++j) {
+    if (!std::isfinite(ab[2 * j]) || !std::isfinite(ab[2 * j + 1])) return XLBOMD_OK;  // keep Gershgorin
+    if (ab[2 * j + 1] <= 1e-12 * scale) {
+      k = j + 1;  // invariant subspace: the Ritz values are eigenvalues
+      break;
+    }
+  }
+  std::vector<double> T((size_t)k * k, 0.0), V, th;
+  for (int j = 0; j < k; ++j) {
+    T[(size_t)j * k + j] = ab[2 * j];
+    if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = ab[2 * j + 1];
+  }
+  if (!jacobi_eig(k, T, V, th)) return XLBOMD_OK;
+  int imin = 0, imax = 0;
+  for (int i = 1; i < k; ++i) {
+    if (th[i] < th[imin]) imin = i;
+    if (th[i] > th[imax]) imax = i;
+  }
+  const double bk = ab[2 * (k - 1) + 1];
+  const double rmin = bk * std::fabs(V[(size_t)(k - 1) * k + imin]);
+  const double rmax = bk * std::fabs(V[(size_t)(k - 1) * k + imax]);
+  const double margin = 1e-3 * (th[imax] - th[imin]) + 1e-12 * scale;
+  lohi[0] = std::max(g[0], th[imin] - rmin - margin);
+  lohi[1] = std::min(g[1], th[imax] + rmax + margin);
+  return XLBOMD_OK;
+}
+
 // ------------------------------------------------------------------ Fermi chain
 // D = (exp(beta (F - mu I)) + I)^-1 (one spin) by the centred tanh-doubling
-// recursion Y_{i+1} = 2 Y_i (I + 4 Y_i^2)^-1 started from a degree-5 Taylor
+// recursion Y_{i+1} = 2 Y_i (I + 4 Y_i^2)^-1 started from a degree-9 Taylor
 // polynomial of tanh at v = -beta (F - mu)/2^(L+1); D = I/2 + Y_L.  The inverse
 // of every level is a Newton-Schulz iteration started from the best linear
 // polynomial of T = I + 4 Y^2 on its spectral interval.
@@ -362,7 +423,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   c->L = L;
   const double vb = std::min(rho / std::ldexp(1.0, L), VMAX);
   const double sc = -beta / std::ldexp(1.0, L + 1);
-  void *V = c->Vst, *S = c->Sst, *P = c->Pst;
+  void *V = c->Vst, *S = c->Sst, *S2 = c->S2st, *B = c->Bst, *P = c->Pst;
   // V = sc (F - mu I), in chain precision
   if (c->is32) {
     convert((int)c->n2, F, 0, c->w[0], 1, c->s);
@@ -371,9 +432,12 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
     axpbyI_dev(n, nullptr, sc, F, nullptr, 0.0, nullptr, nullptr, -sc * mu, V, 0, c->s);
   }
   mm(c, V, V, S, 1.0, 1);                                   // S = V^2
-  mm(c, S, S, P, TC2, 1, S, TC1, nullptr, 0.0, TC0);        // P = c0 I + c1 S + c2 S^2
+  mm(c, S, S, S2, 1.0, 1);                                  // S2 = S^2
+  axpbyI_dev(n, nullptr, TC3, S, nullptr, TC4, S2, nullptr, TC2, B, c->is32, c->s);  // c2 + c3 S + c4 S2
+  mm(c, S2, B, P, 1.0, 1, S, TC1, nullptr, 0.0, TC0);       // P = c0 + c1 S + S2 B
   mm(c, V, P, c->Yc[0], 0.5, 1);                            // Y0 = V P / 2
-  double yb = 0.5 * vb * (TC0 + TC1 * vb * vb + TC2 * vb * vb * vb * vb);
+  const double vb2 = vb * vb;
+  double yb = 0.5 * vb * (TC0 + vb2 * (TC1 + vb2 * (TC2 + vb2 * (TC3 + vb2 * TC4))));
   const double eps = eps_for_prec(c->prec_dm);
   for (int i = 0; i < L; ++i) {
     void *Y = c->Yc[i];
@@ -437,53 +501,95 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     dots((int)c->n2, 3, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
   }
   mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->dscal + S_MU1, s);
-  // buffers: Qacc accumulates prod Q_k^-1 (unscaled) in c->Qs
+  // Each pass shifts D exactly to D(mu + dmu) = D Q^-1, Q = c I + (1 - c) D,
+  // c = exp(-beta dmu): pass 0 with dmu from the trace series, later passes
+  // with a (clamped) Newton step on Tr D.  Qs accumulates the product of the
+  // Q^-1.  The passes end with a step |1 - c| <= 1e-3, taken as the series
+  // Q^-1 = (I - r D + r^2 D^2 - r^3 D^3)/c, r = (1 - c)/c (error O(r^4)); the
+  // first-order trace correction applied afterwards then leaves O(r^4).
   double dmu_total = 0.0, cprod = 1.0;
   bool first = true, done = false;
+  c->mu_passes = 0;
   for (int pass = 0; pass < 8 && !done; ++pass) {
     double mres[5];
+    bool have_d3 = pass == 0;  // D2 = D^2 (and D3 = D^3 in pass 0) are current
     if (pass > 0) {
-      // Newton pass from Tr D and Tr D(I - D)
-      void *Dsq = c->w[0], *Mt = c->w[1];
-      mm(c, D, D, Dsq, 1.0, 1);
-      axpby((int)c->n2, 1.0, D, -1.0, Dsq, Mt, i32, s);
+      // Newton step from Tr D and Tr D(I - D)
+      void *Mt = c->w[1];
+      mm(c, D, D, D2, 1.0, 1);
+      axpby((int)c->n2, 1.0, D, -1.0, D2, Mt, i32, s);
       trace(n, D, c->dscal + S_T01, i32, c->red, s);
       trace(n, Mt, c->dscal + S_T01 + 1, i32, c->red, s);
       mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->dscal + S_MU1, s);
     }
     if ((st = get_scalars(c, S_MU1, 5, mres))) return st;
+    c->mu_passes = pass + 1;
     const bool clamped = mres[3] != 0.0;
     const double cc = mres[1];
-    // the passes end with one unclamped Newton step after the last clamped one
-    if (pass > 0 && !clamped) done = true;
-    hipLaunchKernelGGL(k_scal_misc, dim3(1), dim3(64), 0, s, c->dscal + S_MU1, c->dscal + S_MU1, nullptr,
-                       c->dscal + S_NEG1, nullptr, nullptr);
-    // Q = c I + (1 - c) D and its inverse by Newton-Schulz from Z0 = 2/(1+c) I
-    // (first iteration elementwise); e0 = |1-c|/(1+c) fixes the iteration count
-    void *Q = c->w[0], *E = c->w[1], *Za = c->w[2], *Zb = c->w[3];
-    axpbyI_dev(n, c->dscal + S_MU1 + 4, 0.0, D, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 1, 0.0, Q, i32, s);
-    axpbyI_dev(n, c->dscal + S_NEG1, 0.0, Q, nullptr, 0.0, nullptr, nullptr, 1.0, E, i32, s);
-    axpbyI_dev(n, c->dscal + S_MU1 + 2, 0.0, E, nullptr, 0.0, nullptr, c->dscal + S_MU1 + 2, 0.0, Za, i32, s);
-    double e = std::fabs(1.0 - cc) / (1.0 + cc);
-    e = e * e;
-    const double eps = eps_for_prec(c->prec_dm);
-    for (int it = 1; it < 6 && e > eps; ++it) {
-      mm(c, Q, Za, E, -1.0, 1, nullptr, 0.0, nullptr, 0.0, 1.0);
-      mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);
-      std::swap(Za, Zb);
-      e = e * e;
+    void *Qi;  // Q^-1 of this pass (unscaled)
+    if (!clamped && std::fabs(1.0 - cc) <= 1e-3) {
+      const double r = (1.0 - cc) / cc;
+      void *D4 = c->w[2];
+      if (!have_d3) mm(c, D, D2, D3, 1.0, 1);
+      mm(c, D2, D2, D4, 1.0, 1);
+      const void *Xs[4] = {D, D2, D3, D4};
+      const double aq[4] = {-r / cc, r * r / cc, -r * r * r / cc, 0.0};
+      const double ad[4] = {1.0 / cc, -r / cc, r * r / cc, -r * r * r / cc};
+      Qi = c->w[3];
+      poly_comb(n, Xs, aq, 1.0 / cc, Qi, i32, s);
+      poly_comb(n, Xs, ad, 0.0, D, i32, s);  // D <- D Q^-1 in place
+      done = true;
+    } else {
+      // inverse of Q (spectrum in [min(c,1), max(c,1)]) by Newton-Schulz from
+      // the Chebyshev-optimal linear start Z0 = z0 I + z1 D; the first step
+      // Z1 = Z0 (2I - Q Z0) is a cubic polynomial in D
+      const double lmin = std::min(cc, 1.0), kap = std::max(cc, 1.0) / lmin;
+      double ca, cb, e0;
+      cheb_lin(kap, ca, cb, e0);
+      const double z0 = ca / lmin + cb * cc / (lmin * lmin), z1 = cb * (1.0 - cc) / (lmin * lmin);
+      const double p0 = 2.0 - cc * z0, p1 = -((1.0 - cc) * z0 + cc * z1), p2 = -(1.0 - cc) * z1;
+      void *Za, *Zb, *E;
+      if (have_d3) {
+        const void *Xs[4] = {D, D2, D3, nullptr};
+        const double co[4] = {z0 * p1 + z1 * p0, z0 * p2 + z1 * p1, z1 * p2, 0.0};
+        Za = c->w[2];
+        Zb = c->w[3];
+        E = c->w[4];
+        poly_comb(n, Xs, co, z0 * p0, Za, i32, s);
+      } else {
+        void *Z0 = c->w[2], *Pp = c->w[1];
+        const void *X0s[4] = {D, nullptr, nullptr, nullptr};
+        const double c0[4] = {z1, 0.0, 0.0, 0.0};
+        poly_comb(n, X0s, c0, z0, Z0, i32, s);
+        const void *X1s[4] = {D, D2, nullptr, nullptr};
+        const double c1[4] = {p1, p2, 0.0, 0.0};
+        poly_comb(n, X1s, c1, p0, Pp, i32, s);  // 2I - Q Z0
+        mm(c, Z0, Pp, c->w[3], 1.0, 1);
+        Za = c->w[3];
+        Zb = c->w[2];
+        E = c->w[1];
+      }
+      double e = e0 * e0;
+      const double eps = eps_for_prec(c->prec_dm);
+      for (int it = 0; it < 8 && e > eps; ++it) {
+        mm(c, D, Za, E, -(1.0 - cc), 1, Za, -cc, nullptr, 0.0, 1.0);  // E = I - Q Z
+        mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);                            // Z <- Z + Z E
+        std::swap(Za, Zb);
+        e = e * e;
+      }
+      void *Dn = (Za == c->w[2]) ? c->w[3] : c->w[2];
+      mm(c, D, Za, Dn, 1.0, 1);
+      axpby((int)c->n2, 1.0, Dn, 0.0, nullptr, D, i32, s);
+      Qi = Za;
     }
-    // D <- D Q^-1 ; Qacc <- Qacc Q^-1
-    void *Dn = (Za == c->w[2]) ? c->w[3] : c->w[2];
-    mm(c, D, Za, Dn, 1.0, 1);
+    // Qs <- Qs Q^-1 (all factors are functions of F and commute)
     if (first) {
-      axpby((int)c->n2, 1.0, Za, 0.0, nullptr, c->Qs, i32, s);
+      axpby((int)c->n2, 1.0, Qi, 0.0, nullptr, c->Qs, i32, s);
       first = false;
     } else {
-      mm(c, c->Qs, Za, c->w[4], 1.0, 1);
+      mm(c, c->Qs, Qi, c->w[4], 1.0, 1);
       axpby((int)c->n2, 1.0, c->w[4], 0.0, nullptr, c->Qs, i32, s);
     }
-    axpby((int)c->n2, 1.0, Dn, 0.0, nullptr, D, i32, s);
     dmu_total += mres[0];
     cprod *= cc;
   }
@@ -506,6 +612,7 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   void *const *Yr = cp ? c->Yr : c->Yc;
   void *const *Zr = cp ? c->Zr : c->Zc;
   void *Vr = cp ? c->Vr : c->Vst, *Pr = cp ? c->Pr : c->Pst, *Sr = cp ? c->Sr : c->Sst;
+  void *S2r = cp ? c->S2r : c->S2st, *Br = cp ? c->Br : c->Bst;
   void *Mr = cp ? c->Mr : c->M, *Qr = cp ? c->Qr : c->Qs;
   const double sc = -c->beta / std::ldexp(1.0, L + 1);
   void *V1 = c->w[0], *dS = c->w[1], *dS2 = c->w[2], *Y1 = c->w[3], *G = c->w[4], *H = c->w[5],
@@ -518,8 +625,11 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   }
   mr(c, Vr, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, Vr);          // V V1 + V1 V
   mr(c, Sr, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, Sr);          // S dS + dS S
-  axpby((int)c->n2, TC1, dS, TC2, dS2, dS2, i32, s);                                      // dP
-  mr(c, V1, Pr, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Vr, dS2);         // (V1 P + V dP)/2
+  void *dB = c->w[7], *dP = G;
+  axpby((int)c->n2, TC3, dS, TC4, dS2, dB, i32, s);                                       // dB
+  // dP = c1 dS + dS2 B + S2 dB (symmetric as a sum: S2 B = B S2)
+  mr(c, dS2, Br, dP, 1.0, 1, dS, TC1, nullptr, 0.0, 0.0, 0, S2r, dB);
+  mr(c, V1, Pr, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Vr, dP);          // (V1 P + V dP)/2
   // level i: Y1 <- [2 Y1 - 4 Y_{i+1} (Y_i Y1 + Y1 Y_i)] Z_i, evaluated as the
   // (symmetric) transpose Z_i [2 Y1 - 4 Y_{i+1} G]^T so that every GEMM operand
   // is symmetric or explicitly transposed
@@ -549,12 +659,9 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
 
 xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
   const int n = c->n;
-  gershgorin(n, F, c->dscal + S_LOHI, c->red, c->s);
   double lohi[2];
-  xlbomd_status st = get_scalars(c, S_LOHI, 2, lohi);
+  xlbomd_status st = spectral_bounds(c, F, lohi);
   if (st) return st;
-  if (!std::isfinite(lohi[0]) || !std::isfinite(lohi[1]))
-    return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
   double mu = *mu_io;
   bool cold = !std::isfinite(mu);
   bool converged = false;
@@ -597,6 +704,8 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
     convert(n2, c->Vst, c->is32, c->Vr, 1, c->s);
     convert(n2, c->Pst, c->is32, c->Pr, 1, c->s);
     convert(n2, c->Sst, c->is32, c->Sr, 1, c->s);
+    convert(n2, c->S2st, c->is32, c->S2r, 1, c->s);
+    convert(n2, c->Bst, c->is32, c->Br, 1, c->s);
     convert(n2, c->Qs, c->is32, c->Qr, 1, c->s);
     convert(n2, c->M, c->is32, c->Mr, 1, c->s);
   }
@@ -789,11 +898,15 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   f(c->red);
   f(c->frc);
   f(c->dptr);
+  f(c->lq);
+  f(c->lw);
   for (auto &p : c->Yc) f(p);
   for (auto &p : c->Zc) f(p);
   f(c->Vst);
   f(c->Pst);
   f(c->Sst);
+  f(c->S2st);
+  f(c->Bst);
   f(c->D);
   f(c->M);
   f(c->Qs);
@@ -805,6 +918,8 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
     f(c->Vr);
     f(c->Pr);
     f(c->Sr);
+    f(c->S2r);
+    f(c->Br);
     f(c->Mr);
     f(c->Qr);
   }
@@ -863,12 +978,16 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   A((void **)&c->red, sizeof(double) * (reduce_partials_capacity() + 2 * (size_t)c->n));
   A((void **)&c->frc, sizeof(double) * 3 * N);
   A((void **)&c->dptr, sizeof(double *) * 64);
+  A((void **)&c->lq, sizeof(double) * (LANCZOS_K + 1) * (size_t)c->n);
+  A((void **)&c->lw, sizeof(double) * (size_t)c->n);
   const size_t mb = c->n2 * c->esz;
   for (auto &p : c->Yc) A(&p, mb);
   for (auto &p : c->Zc) A(&p, mb);
   A(&c->Vst, mb);
   A(&c->Pst, mb);
   A(&c->Sst, mb);
+  A(&c->S2st, mb);
+  A(&c->Bst, mb);
   A(&c->D, mb);
   A(&c->M, mb);
   A(&c->Qs, mb);
@@ -881,6 +1000,8 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
     A(&c->Vr, m4);
     A(&c->Pr, m4);
     A(&c->Sr, m4);
+    A(&c->S2r, m4);
+    A(&c->Br, m4);
     A(&c->Mr, m4);
     A(&c->Qr, m4);
   }
@@ -891,7 +1012,7 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   (void)ntp;
   if (hipMemcpy(c->onecenter, sys->onecenter, sizeof(double) * 5 * N, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->j55, sys->model.j55, sizeof(double) * 55, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess) {
+      hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess || !lanczos_start(c)) {
     xlbomd_destroy(c);
     return XLBOMD_E_HIP;
   }
@@ -1065,6 +1186,8 @@ xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlb
       r.relres = rel;
       r.rank = rank;
       r.status = XLBOMD_OK;
+      r.levels = c->L;
+      r.mu_passes = c->mu_passes;
     }
   }
   HIPCHK(c, hipStreamSynchronize(c->s));

@@ -13,6 +13,11 @@ namespace {
 
 constexpr int RED_BLOCKS = 1024;
 constexpr int MAXK = 16;
+// largest chemical-potential move of one Newton pass, in units of 1/beta, and
+// the bracket of the five-term series solve (the series in 1 - exp(-beta dmu)
+// is accurate only well inside its radius of convergence)
+constexpr double MU_STEP = 1.0;
+constexpr double SERIES_STEP = 0.3;
 
 template <typename T>
 __device__ inline double ld(const void *p, size_t i) {
@@ -42,6 +47,23 @@ __global__ void k_axpbyI(int n, const double *a_dev, double a, const void *x, co
     if (x) v += av * ld<T>(x, i);
     if (y) v += bv * ld<T>(y, i);
     if (i / n == i % n) v += gv;
+    ((T *)out)[i] = (T)v;
+  }
+}
+
+// out = sum_j a_j X_j + g I over four matrices (null X_j skipped); out may
+// alias any X_j (each element is read before it is written)
+template <typename T>
+__global__ void k_poly_comb(int n, const void *X0, const void *X1, const void *X2, const void *X3,
+                            double a0, double a1, double a2, double a3, double g, void *out) {
+  const size_t n2 = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double v = (i / n == i % n) ? g : 0.0;
+    if (X0) v += a0 * ld<T>(X0, i);
+    if (X1) v += a1 * ld<T>(X1, i);
+    if (X2) v += a2 * ld<T>(X2, i);
+    if (X3) v += a3 * ld<T>(X3, i);
     ((T *)out)[i] = (T)v;
   }
 }
@@ -152,6 +174,55 @@ __global__ __launch_bounds__(256) void k_trace_partial(int n, const void *M, dou
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
+// Lanczos recurrence for spectral bounds.  w = F q_j (one wavefront per row,
+// F symmetric, row-major), then one workgroup finishes the step:
+// alpha_j = w.q_j, w <- w - alpha_j q_j - beta_{j-1} q_{j-1}, beta_j = |w|,
+// q_{j+1} = w / beta_j.  Q holds the Lanczos vectors row by row; ab[2j] and
+// ab[2j+1] receive alpha_j and beta_j.
+__global__ __launch_bounds__(256) void k_symv(int n, const double *F, const double *q, double *w) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double *f = F + (size_t)row * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += f[j] * q[j];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) w[row] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_lanczos_step(int n, int j, double *Q, const double *w,
+                                                      double *ab) {
+  __shared__ double sh[4];
+  __shared__ double bc;
+  const double *qj = Q + (size_t)j * n;
+  const double *qp = j > 0 ? Q + (size_t)(j - 1) * n : nullptr;
+  double *qn = Q + (size_t)(j + 1) * n;
+  const double bprev = j > 0 ? ab[2 * j - 1] : 0.0;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += w[i] * qj[i];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) bc = a;
+  __syncthreads();
+  a = bc;
+  double b = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double v = w[i] - a * qj[i];
+    if (qp) v -= bprev * qp[i];
+    qn[i] = v;
+    b += v * v;
+  }
+  b = block_sum(b, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bc = sqrt(b);
+    ab[2 * j] = a;
+    ab[2 * j + 1] = bc;
+  }
+  __syncthreads();
+  const double inv = bc > 0.0 ? 1.0 / bc : 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) qn[i] *= inv;
+}
+
 // Gershgorin: one wavefront per row
 __global__ __launch_bounds__(256) void k_gersh_rows(int n, const double *F, double *lohi) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -206,7 +277,7 @@ __global__ void k_mu_series(const double *tau, double n_occ, double beta, double
     }
     return s - n_occ;
   };
-  double lo = -0.3 / beta, hi = 0.3 / beta;
+  double lo = -SERIES_STEP / beta, hi = SERIES_STEP / beta;
   double flag = 0.0;
   double dmu;
   if (g(lo) > 0.0) {
@@ -240,7 +311,7 @@ __global__ void k_mu_newton(const double *t01, double n_occ, double beta, double
   if (threadIdx.x != 0) return;
   const double t0 = t01[0], t1 = t01[1];
   double dmu = (t1 > 0.0) ? (n_occ - t0) / (beta * t1) : 0.0;
-  const double lim = 0.3 / beta;
+  const double lim = MU_STEP / beta;
   double flag = 0.0;
   if (dmu > lim) {
     dmu = lim;
@@ -419,6 +490,24 @@ void trace(int n, const void *M, double *res, int is32, double *partials, hipStr
 void gershgorin(int n, const double *F, double *res, double *partials, hipStream_t s) {
   hipLaunchKernelGGL(k_gersh_rows, dim3((n + 3) / 4), dim3(256), 0, s, n, F, partials);
   hipLaunchKernelGGL(k_gersh_final, dim3(1), dim3(256), 0, s, n, partials, res);
+}
+
+void poly_comb(int n, const void *const X[4], const double a[4], double g, void *out, int is32,
+               hipStream_t s) {
+  const size_t n2 = (size_t)n * n;
+  if (is32)
+    hipLaunchKernelGGL(k_poly_comb<float>, dim3(grid_for(n2)), dim3(256), 0, s, n, X[0], X[1], X[2], X[3],
+                       a[0], a[1], a[2], a[3], g, out);
+  else
+    hipLaunchKernelGGL(k_poly_comb<double>, dim3(grid_for(n2)), dim3(256), 0, s, n, X[0], X[1], X[2], X[3],
+                       a[0], a[1], a[2], a[3], g, out);
+}
+
+void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s) {
+  for (int j = 0; j < k; ++j) {
+    hipLaunchKernelGGL(k_symv, dim3((n + 3) / 4), dim3(256), 0, s, n, F, Q + (size_t)j * n, w);
+    hipLaunchKernelGGL(k_lanczos_step, dim3(1), dim3(256), 0, s, n, j, Q, w, ab);
+  }
 }
 
 void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s) {

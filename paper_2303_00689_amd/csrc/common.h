@@ -39,6 +39,9 @@ void axpby(int n2, double a, const void *x, double b, const void *y, void *out, 
 void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const double *b_dev, double b,
                 const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s);
 void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s);
+// out = sum_{j<4} a_j X_j + g I (null X_j skipped; out may alias an X_j)
+void poly_comb(int n, const void *const X[4], const double a[4], double g, void *out, int is32,
+               hipStream_t s);
 void symmetrize(int n, void *M, int is32, hipStream_t s);
 // out = sum_j coef[j] * M_j (coef on device), j < k <= 40, FP64
 void lincomb_dev(int n2, int k, const double *const *M, const double *coef, double *out, hipStream_t s);
@@ -51,6 +54,9 @@ void dots(int n2, int k, const void *const *X, const void *const *Y, double *res
 void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s);
 // Gershgorin bounds of a symmetric matrix: res[0] = min(F_ii - r_i), res[1] = max(F_ii + r_i)
 void gershgorin(int n, const double *F, double *res, double *partials, hipStream_t s);
+// k Lanczos steps on symmetric F from the unit vector in row 0 of Q
+// ((k + 1) x n); w: n scratch; ab: 2k device doubles (alpha_j, beta_j)
+void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s);
 int reduce_partials_capacity();
 
 // ------------------------------------------------------------- pair kernels
