@@ -148,16 +148,16 @@ int xlbomd_n_orb(xlbomd_handle h);
  * R only through the pair geometry). */
 xlbomd_status xlbomd_set_geometry(xlbomd_handle h, const double *R);
 
-/* a1: dense one-electron matrix h(R) into H (DEVICE n x n), eq. 6. */
+/* dense one-electron matrix h(R) into H (DEVICE n x n), eq. 6. */
 xlbomd_status xlbomd_hcore(xlbomd_handle h, double *H);
 
-/* a2: Fock build F = h + G(P) (eq. 6 / eq. 17 with S = I) for a spin-summed P,
+/* Fock build F = h + G(P) (eq. 6 / eq. 17 with S = I) for a spin-summed P,
  * G(P)_mn = sum_ls P_ls [(mn|ls) - 1/2 (ml|ns)] (eq. 3 at D = P/2) with NDDO
  * integrals.  include_h = 0 returns G(P) only (the F1 = G(V) of eq. 36).
  * P and F are DEVICE n x n and must not alias. */
 xlbomd_status xlbomd_fock(xlbomd_handle h, const double *P, double *F, int include_h);
 
-/* a3-a5: finite-temperature density matrix of eq. 19, P = 2 (exp(beta (F - mu0)) + 1)^-1,
+/* finite-temperature density matrix of eq. 19, P = 2 (exp(beta (F - mu0)) + 1)^-1,
  * with mu0 fixed by Tr P = N_e (eq. 8), by a recursive Fermi-operator GEMM chain in
  * the handle's precision and an exact chemical-potential shift.
  *   mu      host in/out: warm-start guess (NaN: none) / converged mu0
@@ -168,12 +168,12 @@ xlbomd_status xlbomd_fock(xlbomd_handle h, const double *P, double *F, int inclu
 xlbomd_status xlbomd_fermi_dm(xlbomd_handle h, const double *F, double *mu, double *P,
                               double *entropy);
 
-/* a6: canonical first-order response P1 = 2 dD/dlambda of D[F + lambda F1] at the
+/* canonical first-order response P1 = 2 dD/dlambda of D[F + lambda F1] at the
  * state of the last xlbomd_fermi_dm (eq. 36), with mu re-solved (Tr P1 = 0).
  * F1, P1: DEVICE n x n.  XLBOMD_E_STATE if no chain is cached. */
 xlbomd_status xlbomd_dm_response(xlbomd_handle h, const double *F1, double *P1);
 
-/* a7: rank-m Krylov approximation (eq. 34, K0 = I) of Y = J^-1 (P0 - X), with
+/* rank-m Krylov approximation (eq. 34, K0 = I) of Y = J^-1 (P0 - X), with
  * J V = P1[G(V)] - V the Jacobian of the residual (eq. 15).  Requires a
  * xlbomd_fermi_dm on F = h + G(X) just before (its chain is reused).
  *   m         requested rank (0 <= m <= 32); tol > 0 stops early once the
@@ -184,13 +184,13 @@ xlbomd_status xlbomd_dm_response(xlbomd_handle h, const double *F1, double *P1);
 xlbomd_status xlbomd_krylov_kernel(xlbomd_handle h, const double *X, const double *P0, int m,
                                    double tol, double *Y, int *rank, double *relres);
 
-/* a9: forces -dU/dR_A at fixed X (eq. 24, eq. 37 with S = I) into forces
+/* forces -dU/dR_A at fixed X (eq. 24, eq. 37 with S = I) into forces
  * (DEVICE n_atoms x 3, eV/Angstrom) and the parts of U (host, nullable, 4 values):
  *   [0] Tr[h P0], [1] Tr[(P0 - X/2) G(X)], [2] V_nn, [3] Tr[h P0] + Tr[(P0 - X/2)G(X)] + V_nn */
 xlbomd_status xlbomd_forces(xlbomd_handle h, const double *P0, const double *X,
                             double *forces, double *energy);
 
-/* a8: damped X-Verlet of eq. 35 on the ring st->X using st->Y, and the
+/* damped X-Verlet of eq. 35 on the ring st->X using st->Y, and the
  * leapfrog position update of eqs. 27-28 (positions and half-step velocities);
  * advances st->head.  Used by xlbomd_step; exposed for testing. */
 xlbomd_status xlbomd_integrate(xlbomd_handle h, xlbomd_md_state *st);

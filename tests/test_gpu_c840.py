@@ -1,0 +1,99 @@
+"""Parity at the full 840-atom size (n = 3360), through the C ABI, in the
+launch configuration the benchmark times.
+
+The FP64 oracle handles this size in seconds per call (one eigendecomposition
+of a 3360 x 3360 matrix, dense pair loops), so every element is compared, not
+a sample.  FP64 mode is held to 1e-10 relative per matrix; the mixed mode
+(FP64 density matrix, split-BF16 response chains) to the 1e-4 eV/Angstrom
+force target and to the split-response error budget.
+"""
+
+import numpy as np
+import pytest
+
+from synth import workload
+from oracle import model, density, dynamics
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+class Ref:
+    """Oracle results at one seeded state of the 840-atom cluster."""
+
+    def __init__(self):
+        s, w = workload("c840")
+        self.sys, self.w = s, w
+        self.beta = density.beta_of(w["T_e"])
+        n = s.n_orb
+        rng = np.random.default_rng(840)
+        X = np.eye(n) * s.n_elec / n + 0.01 * rng.standard_normal((n, n))
+        self.X = 0.5 * (X + X.T)
+        self.F = model.fock(self.X, s.R, s.onecenter, s.noise, s.params)
+        self.dm = density.density_matrix(self.F, s.n_elec, self.beta)
+        V = rng.standard_normal((n, n))
+        V = (V + V.T) / np.linalg.norm(V + V.T)
+        self.F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params)
+        self.P1 = density.response(self.F, self.F1, s.n_elec, self.beta, self.dm)
+        self.frc = dynamics.forces(s.R, self.dm["P"], self.X, s.params, s.noise)
+
+
+@pytest.fixture(scope="module")
+def ref():
+    return Ref()
+
+
+@pytest.fixture(scope="module")
+def binding():
+    from paper_2303_00689_amd import binding as b
+    return b
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _run(binding, ref, prec):
+    s = ref.sys
+    h = binding.handle_for(s, ref.w, prec=prec)
+    try:
+        h.set_geometry(_dev(s.R))
+        X = _dev(ref.X)
+        F = torch.empty_like(X)
+        h.fock(X, F, True)
+        P = torch.empty_like(X)
+        h.fermi_dm(F, P)
+        P1 = torch.empty_like(X)
+        h.dm_response(_dev(ref.F1), P1)
+        frc = torch.empty((s.n_atoms, 3), dtype=torch.float64, device="cuda:0")
+        h.forces(P, X, frc)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in dict(F=F, P=P, P1=P1, frc=frc).items()}
+    finally:
+        h.close()
+
+
+def test_fp64_step_parts_match_oracle(binding, ref):
+    out = _run(binding, ref, "fp64")
+    errs = {k: _rel(out[k], r) for k, r in (("F", ref.F), ("P", ref.dm["P"]), ("P1", ref.P1), ("frc", ref.frc))}
+    print("c840 fp64 relative errors:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+    assert abs(np.trace(out["P"]) - ref.sys.n_elec) <= 1e-11 * ref.sys.n_elec
+
+
+def test_mixed_precision_forces_meet_target(binding, ref):
+    out = _run(binding, ref, "dm64_bf16x3")
+    ferr = float(np.abs(out["frc"] - ref.frc).max())
+    perr = _rel(out["P"], ref.dm["P"])
+    p1err = _rel(out["P1"], ref.P1)
+    print(f"c840 dm64_bf16x3: P {perr:.2e}  P1 {p1err:.2e}  forces {ferr:.2e} eV/A")
+    assert perr <= TOL
+    assert ferr <= 1e-4
+    assert p1err <= 1e-2
