@@ -12,35 +12,22 @@
 // LDS panels are stored k-major (As[k][m], Bs[k][n]) so that both fragments
 // are read as 16 consecutive doubles per lane group.
 #include "common.h"
+#include "tile_map.h"
 
 namespace xl {
 namespace {
+
+constexpr int TILE_GROUP = 8;  // tile rows per L2-sharing group
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64;
 constexpr int BK = 16;
 
-__device__ inline void tri_index(int bid, int T, int &bi, int &bj) {
-  // row bi of the upper triangle holds T - bi tiles
-  int r = 0, start = 0;
-  while (start + (T - r) <= bid) {
-    start += T - r;
-    ++r;
-  }
-  bi = r;
-  bj = r + (bid - start);
-}
-
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
   const int n = p.n;
   int bi, bj;
-  if (p.sym) {
-    tri_index(blockIdx.x, T, bi, bj);
-  } else {
-    bi = blockIdx.x / T;
-    bj = blockIdx.x % T;
-  }
+  tile_of(blockIdx.x, T, p.sym, TILE_GROUP, bi, bj);
   const int i0 = bi * BM, j0 = bj * BM;
   __shared__ double As[2][BK][BM];
   __shared__ double Bs[2][BK][BM];

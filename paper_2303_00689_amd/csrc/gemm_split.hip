@@ -21,12 +21,15 @@
 // A operands of the chains, and op(B) = B^T, which is B for a symmetric B and
 // the requested transpose when btrans = 1.
 #include "common.h"
+#include "tile_map.h"
 
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
 namespace xl {
 namespace {
+
+constexpr int TILE_GROUP = 4;  // tile rows per L2-sharing group
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -81,28 +84,15 @@ __device__ inline f4 mfma(us8 a, us8 b, f4 c, bool f16) {
                                                  0, 0);
 }
 
-__device__ inline void tri_index(int bid, int T, int &bi, int &bj) {
-  int r = 0, start = 0;
-  while (start + (T - r) <= bid) {
-    start += T - r;
-    ++r;
-  }
-  bi = r;
-  bj = r + (bid - start);
-}
-
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
+// STAGES = 2 keeps the raw rows of two panels in registers (see below); it is
+// used where the register budget still allows two waves per SIMD.
+template <int MODE, int STAGES>
+__device__ __forceinline__ void gemm_split_body(GemmArgs p, int T) {
   constexpr int P = Parts<MODE>::P;
   constexpr bool F16 = (MODE == 2);
   const int n = p.n;
   int bi, bj;
-  if (p.sym) {
-    tri_index(blockIdx.x, T, bi, bj);
-  } else {
-    bi = blockIdx.x / T;
-    bj = blockIdx.x % T;
-  }
+  tile_of(blockIdx.x, T, p.sym, TILE_GROUP, bi, bj);
   const int i0 = bi * TM, j0 = bj * TM;
   // [buffer][part][row][k]
   __shared__ unsigned short As[2][P][TM][PITCH];
@@ -130,101 +120,129 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
   const int ktiles = kt_per * p.nprod;
   // loader: 128 rows x 32 floats per operand; thread -> row tid / 2, 16 floats at 16 * (tid % 2)
   const int lrow = tid >> 1, lk = (tid & 1) * 16;
-  // raw loaded rows and their validity; the zeroing select and the split
-  // happen in store(), after the MFMAs of the current panel, so the loads of
-  // the next panel stay in flight during them
-  f4 xa[4], xb[4];
-  bool vla = true, vlb = true, vk[4] = {true, true, true, true};
+  // Two register stages: the raw rows of panel kt + 2 are loaded while panel
+  // kt feeds the MFMAs and panel kt + 1 is split into LDS, so every global
+  // load has about two panels of MFMA work to arrive.  The zeroing select and
+  // the split happen in store(), after the loads of the later panel have been
+  // issued.
+  struct Stage {
+    f4 xa[4], xb[4];
+    bool vla, vlb, vk[4];
+  };
+  Stage s0, s1;
+  (void)s1;
 
   // Loads are unconditional (clamped in-bounds addresses), so no branch
   // separates them and the compiler can keep all of them in flight.
-  auto load = [&](int kt) {
+  auto load = [&](int kt, Stage &st) {
     const int prod = kt / kt_per;
     const int k0 = (kt - prod * kt_per) * TK + lk;
     const float *A = (const float *)p.A[prod];
     const float *B = (const float *)p.B[prod];
     const int ia = i0 + lrow, jb = j0 + lrow;
-    vla = ia < n;
-    vlb = jb < n;
-    const size_t ra_off = (size_t)(vla ? ia : n - 1) * n;
-    const size_t rb_off = (size_t)(vlb ? jb : n - 1) * n;
+    st.vla = ia < n;
+    st.vlb = jb < n;
+    const size_t ra_off = (size_t)(st.vla ? ia : n - 1) * n;
+    const size_t rb_off = (size_t)(st.vlb ? jb : n - 1) * n;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = k0 + 4 * v;
-      vk[v] = k < n;
-      const int kc = vk[v] ? k : n - 4;
-      xa[v] = *(const f4 *)(A + ra_off + kc);
-      xb[v] = *(const f4 *)(B + rb_off + kc);
+      st.vk[v] = k < n;
+      const int kc = st.vk[v] ? k : n - 4;
+      st.xa[v] = *(const f4 *)(A + ra_off + kc);
+      st.xb[v] = *(const f4 *)(B + rb_off + kc);
     }
   };
-  auto store = [&](int buf) {
-    float ra[16], rb[16];
+  auto store = [&](int buf, const Stage &st) {
+    // eight values at a time: select, split, one 16-byte LDS write per part
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int h = 0; h < 2; ++h) {
+      unsigned short pa[P][8], pb[P][8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ra[4 * v + q] = (vla && vk[v]) ? xa[v][q] : 0.0f;
-        rb[4 * v + q] = (vlb && vk[v]) ? xb[v][q] : 0.0f;
+      for (int e = 0; e < 8; ++e) {
+        const int v = 2 * h + e / 4, q4 = e % 4;
+        const float fa = (st.vla && st.vk[v]) ? st.xa[v][q4] : 0.0f;
+        const float fb = (st.vlb && st.vk[v]) ? st.xb[v][q4] : 0.0f;
+        unsigned short t[3];
+        split<MODE>(fa, t);
+#pragma unroll
+        for (int q = 0; q < P; ++q) pa[q][e] = t[q];
+        split<MODE>(fb, t);
+#pragma unroll
+        for (int q = 0; q < P; ++q) pb[q][e] = t[q];
       }
-    unsigned short pa[P][16], pb[P][16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      unsigned short t[3];
-      split<MODE>(ra[e], t);
-#pragma unroll
-      for (int q = 0; q < P; ++q) pa[q][e] = t[q];
-      split<MODE>(rb[e], t);
-#pragma unroll
-      for (int q = 0; q < P; ++q) pb[q][e] = t[q];
-    }
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      us8 *da = (us8 *)&As[buf][q][lrow][lk];
-      us8 *db = (us8 *)&Bs[buf][q][lrow][lk];
-      da[0] = us8{pa[q][0], pa[q][1], pa[q][2], pa[q][3], pa[q][4], pa[q][5], pa[q][6], pa[q][7]};
-      da[1] = us8{pa[q][8], pa[q][9], pa[q][10], pa[q][11], pa[q][12], pa[q][13], pa[q][14], pa[q][15]};
-      db[0] = us8{pb[q][0], pb[q][1], pb[q][2], pb[q][3], pb[q][4], pb[q][5], pb[q][6], pb[q][7]};
-      db[1] = us8{pb[q][8], pb[q][9], pb[q][10], pb[q][11], pb[q][12], pb[q][13], pb[q][14], pb[q][15]};
+      for (int q = 0; q < P; ++q) {
+        *(us8 *)&As[buf][q][lrow][lk + 8 * h] =
+            us8{pa[q][0], pa[q][1], pa[q][2], pa[q][3], pa[q][4], pa[q][5], pa[q][6], pa[q][7]};
+        *(us8 *)&Bs[buf][q][lrow][lk + 8 * h] =
+            us8{pb[q][0], pb[q][1], pb[q][2], pb[q][3], pb[q][4], pb[q][5], pb[q][6], pb[q][7]};
+      }
     }
   };
-
-  load(0);
-  store(0);
-  __syncthreads();
   const int fr = lane & 15, fk = 8 * (lane >> 4);
-  for (int kt = 0; kt < ktiles; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < ktiles) load(kt + 1);
-    us8 a[P][4], b[P][4];
+  auto compute = [&](int buf) {
+    // B fragments for the four column blocks, then one row block of A at a time
+    us8 b[P][4];
 #pragma unroll
     for (int q = 0; q < P; ++q)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[q][r] = *(const us8 *)&As[buf][q][wm + 16 * r + fr][fk];
-        b[q][r] = *(const us8 *)&Bs[buf][q][wn + 16 * r + fr][fk];
-      }
+      for (int c = 0; c < 4; ++c) b[q][c] = *(const us8 *)&Bs[buf][q][wn + 16 * c + fr][fk];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      us8 a[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) a[q] = *(const us8 *)&As[buf][q][wm + 16 * r + fr][fk];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         if (MODE == 2) {
-          acc[r][c] = mfma(a[0][r], b[0][c], acc[r][c], true);
-          acc2[r][c] = mfma(a[0][r], b[1][c], acc2[r][c], true);
-          acc2[r][c] = mfma(a[1][r], b[0][c], acc2[r][c], true);
+          acc[r][c] = mfma(a[0], b[0][c], acc[r][c], true);
+          acc2[r][c] = mfma(a[0], b[1][c], acc2[r][c], true);
+          acc2[r][c] = mfma(a[1], b[0][c], acc2[r][c], true);
         } else {
           // small terms first
           if (MODE == 1) {
-            acc[r][c] = mfma(a[1][r], b[1][c], acc[r][c], false);
-            acc[r][c] = mfma(a[0][r], b[2][c], acc[r][c], false);
-            acc[r][c] = mfma(a[2][r], b[0][c], acc[r][c], false);
+            acc[r][c] = mfma(a[1], b[1][c], acc[r][c], false);
+            acc[r][c] = mfma(a[0], b[2][c], acc[r][c], false);
+            acc[r][c] = mfma(a[2], b[0][c], acc[r][c], false);
           }
-          acc[r][c] = mfma(a[0][r], b[1][c], acc[r][c], false);
-          acc[r][c] = mfma(a[1][r], b[0][c], acc[r][c], false);
-          acc[r][c] = mfma(a[0][r], b[0][c], acc[r][c], false);
+          acc[r][c] = mfma(a[0], b[1][c], acc[r][c], false);
+          acc[r][c] = mfma(a[1], b[0][c], acc[r][c], false);
+          acc[r][c] = mfma(a[0], b[0][c], acc[r][c], false);
         }
       }
-    if (kt + 1 < ktiles) store(buf ^ 1);
+    }
+  };
+
+  if constexpr (STAGES == 2) {
+    load(0, s0);
+    if (ktiles > 1) load(1, s1);
+    store(0, s0);
     __syncthreads();
+    for (int kt = 0; kt < ktiles; kt += 2) {
+      // panel kt from buffer 0; stage 0 is free again
+      if (kt + 2 < ktiles) load(kt + 2, s0);
+      compute(0);
+      if (kt + 1 < ktiles) store(1, s1);
+      __syncthreads();
+      if (kt + 1 >= ktiles) break;
+      // panel kt + 1 from buffer 1; stage 1 is free again
+      if (kt + 3 < ktiles) load(kt + 3, s1);
+      compute(1);
+      if (kt + 2 < ktiles) store(0, s0);
+      __syncthreads();
+    }
+  } else {
+    load(0, s0);
+    store(0, s0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < ktiles) load(kt + 1, s0);
+      compute(buf);
+      if (kt + 1 < ktiles) store(buf ^ 1, s0);
+      __syncthreads();
+    }
   }
 
   const float *C1 = (const float *)p.C1;
@@ -262,6 +280,18 @@ __global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
+  gemm_split_body<MODE, 1>(p, T);
+}
+
+// BF16x3, the response-chain mode of the mixed-precision step: two register
+// stages at two waves per SIMD
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_split_bf16x3(GemmArgs p,
+                                                                                                  int T) {
+  gemm_split_body<0, 2>(p, T);
+}
+
 }  // namespace
 
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
@@ -270,7 +300,7 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   switch (prec) {
     case 2: hipLaunchKernelGGL(k_gemm_split<1>, dim3(blocks), dim3(256), 0, s, a, T); break;
     case 3: hipLaunchKernelGGL(k_gemm_split<2>, dim3(blocks), dim3(256), 0, s, a, T); break;
-    default: hipLaunchKernelGGL(k_gemm_split<0>, dim3(blocks), dim3(256), 0, s, a, T); break;
+    default: hipLaunchKernelGGL(k_gemm_split_bf16x3, dim3(blocks), dim3(256), 0, s, a, T); break;
   }
 }
 
