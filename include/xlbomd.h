@@ -224,10 +224,10 @@ xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, d
  * earlier records. */
 xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
 /* Sums over the recorded launches, 4 classes x {launches, milliseconds,
- * algorithmic work}: [0..2] FP64 GEMM and [3..5] split-precision GEMM (work =
- * flops of the products the method needs: 2n^3 per product, n^3 for a product
- * with symmetric output, not counting the extra split products), [6..8] Fock
- * build and [9..11] forces (work = HBM bytes: 220 per atom pair plus 16 n^2). */
+ * work}: [0..2] FP64 GEMM and [3..5] split-precision GEMM (work = executed
+ * MFMA flops: 2n^3 per product, n^3 for a product with symmetric output, times
+ * the 3 or 6 MFMA products a split product runs), [6..8] Fock build and
+ * [9..11] forces (work = algorithmic HBM bytes: 220 per atom pair plus 16 n^2). */
 xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
 
 #ifdef __cplusplus

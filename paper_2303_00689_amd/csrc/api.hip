@@ -259,8 +259,10 @@ void mm_p(xlbomd_ctx *c, int prec, const void *A, const void *B, void *out, doub
     gemm_f64(g, c->s);
   else
     gemm_split(g, prec, c->s);
+  // profiled work: executed MFMA flops (a split product runs 3 or 6 MFMA products)
   const double n = (double)c->n;
-  prof_end(c, e, prec == XLBOMD_FP64 ? PC_GEMM64 : PC_GEMMS, g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
+  const double parts = prec == XLBOMD_FP64 ? 1.0 : (prec == XLBOMD_BF16X6 ? 6.0 : 3.0);
+  prof_end(c, e, prec == XLBOMD_FP64 ? PC_GEMM64 : PC_GEMMS, parts * g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
   ++c->n_gemm;
 }
 
@@ -439,6 +441,8 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   const double vb2 = vb * vb;
   double yb = 0.5 * vb * (TC0 + vb2 * (TC1 + vb2 * (TC2 + vb2 * (TC3 + vb2 * TC4))));
   const double eps = eps_for_prec(c->prec_dm);
+  const bool mixed = c->prec_dm == XLBOMD_FP64 && c->resp_copy;
+  const int n2i = (int)c->n2;
   for (int i = 0; i < L; ++i) {
     void *Y = c->Yc[i];
     void *Si = c->w[1], *E = c->w[2], *Za = c->w[3], *Zb = c->w[4];
@@ -451,14 +455,45 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       e = e * e;
       ++k;
     }
-    // E0 = I - a T - b T^2 with T = I + 4S, T^2 = I + 8S + 16 S^2
-    mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
-    // Z1 = Z0 (I + E0), Z0 = (a + b) I + 4 b S
-    mm(c, Si, E, Za, 4.0 * b, 1, Si, 4.0 * b, E, a + b, a + b);
-    for (int it = 1; it < k; ++it) {
-      mm(c, Si, Za, E, -4.0, 1, Za, -1.0, nullptr, 0.0, 1.0);   // E = I - T Z
-      mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);                        // Z <- Z + Z E
+    if (mixed) {
+      // FP64-accurate inverse with split-precision Newton-Schulz steps: the
+      // iteration corrects itself, so only the last residual E = I - T Z
+      // (a cancellation) needs FP64; the start and the early steps run in
+      // BF16x3 / BF16x6, and the last correction Z E (of size ~e) in BF16x6.
+      const size_t half = c->n2 * 4;
+      void *S32 = c->w[5], *E32 = (char *)c->w[5] + half, *Za32 = c->w[6], *Zb32 = (char *)c->w[6] + half,
+           *C32 = c->w[7];
+      convert(n2i, Si, 0, S32, 1, c->s);
+      mm_p(c, XLBOMD_BF16X3, S32, S32, E32, -16.0 * b, 1, S32, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
+      mm_p(c, XLBOMD_BF16X3, S32, E32, Za32, 4.0 * b, 1, S32, 4.0 * b, E32, a + b, a + b);
+      double el = e0 * e0 + 2e-5;  // + BF16x3 rounding
+      for (int it = 0; it < 8 && el > std::sqrt(eps); ++it) {
+        mm_p(c, XLBOMD_BF16X6, S32, Za32, E32, -4.0, 1, Za32, -1.0, nullptr, 0.0, 1.0);
+        mm_p(c, XLBOMD_BF16X6, Za32, E32, Zb32, 1.0, 1, Za32, 1.0);
+        std::swap(Za32, Zb32);
+        el = el * el + 1e-7;
+      }
+      // Z is a function of the FP32-rounded S, so T Z is symmetric only to
+      // ~1e-7 and E is not symmetric: the FP64 residual is formed in full, and
+      // the split GEMM (which takes its second operand transposed) gets E^T.
+      // Z E carries the asymmetry of Z and is formed in full as well.
+      convert(n2i, Za32, 1, Za, 0, c->s);
+      mm(c, Si, Za, E, -4.0, 0, Za, -1.0, nullptr, 0.0, 1.0);  // E = I - T Z in FP64
+      convert_t(n, (const double *)E, (float *)E32, c->s);
+      mm_p(c, XLBOMD_BF16X6, Za32, E32, C32, 1.0, 0);           // Z E
+      convert(n2i, C32, 1, E, 0, c->s);
+      axpby(n2i, 1.0, Za, 1.0, E, Zb, 0, c->s);                // Z + Z E
       std::swap(Za, Zb);
+    } else {
+      // E0 = I - a T - b T^2 with T = I + 4S, T^2 = I + 8S + 16 S^2
+      mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
+      // Z1 = Z0 (I + E0), Z0 = (a + b) I + 4 b S
+      mm(c, Si, E, Za, 4.0 * b, 1, Si, 4.0 * b, E, a + b, a + b);
+      for (int it = 1; it < k; ++it) {
+        mm(c, Si, Za, E, -4.0, 1, Za, -1.0, nullptr, 0.0, 1.0);   // E = I - T Z
+        mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);                        // Z <- Z + Z E
+        std::swap(Za, Zb);
+      }
     }
     // keep Z_i in the cache
     if (Za != c->w[3]) std::swap(c->w[3], c->w[4]);

@@ -68,6 +68,22 @@ __global__ void k_poly_comb(int n, const void *X0, const void *X1, const void *X
   }
 }
 
+// out = in^T, FP64 -> FP32, by 32 x 32 tiles staged in LDS (coalesced both ways)
+__global__ __launch_bounds__(256) void k_convert_t(int n, const double *in, float *out) {
+  __shared__ float t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    if (i < n && j < n) t[r][tx] = (float)in[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + r, j = by + tx;
+    if (i < n && j < n) out[(size_t)i * n + j] = t[tx][r];
+  }
+}
+
 template <typename TI, typename TO>
 __global__ void k_convert(size_t n2, const void *in, void *out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
@@ -501,6 +517,11 @@ void poly_comb(int n, const void *const X[4], const double a[4], double g, void 
   else
     hipLaunchKernelGGL(k_poly_comb<double>, dim3(grid_for(n2)), dim3(256), 0, s, n, X[0], X[1], X[2], X[3],
                        a[0], a[1], a[2], a[3], g, out);
+}
+
+void convert_t(int n, const double *in, float *out, hipStream_t s) {
+  const int g = (n + 31) / 32;
+  hipLaunchKernelGGL(k_convert_t, dim3(g, g), dim3(256), 0, s, n, in, out);
 }
 
 void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s) {

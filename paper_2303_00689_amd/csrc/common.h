@@ -39,6 +39,8 @@ void axpby(int n2, double a, const void *x, double b, const void *y, void *out, 
 void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const double *b_dev, double b,
                 const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s);
 void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s);
+// out = in^T (n x n, FP64 in, FP32 out)
+void convert_t(int n, const double *in, float *out, hipStream_t s);
 // out = sum_{j<4} a_j X_j + g I (null X_j skipped; out may alias an X_j)
 void poly_comb(int n, const void *const X[4], const double a[4], double g, void *out, int is32,
                hipStream_t s);
