@@ -280,9 +280,209 @@ __device__ __forceinline__ void gemm_split_body(GemmArgs p, int T) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split GEMM with direct-to-LDS operand panels (gfx950 global_load_lds).
+//
+// The FP32 panels (128 rows x 32 k of A and of B) stream into LDS without
+// passing through registers, two stages deep, so the loads of panel kt + 1
+// are in flight while panel kt feeds the MFMAs.  Every wave splits the FP32
+// values of its own fragments into BF16/FP16 parts right before the MFMAs.
+// Within an LDS row (eight 16-byte chunks) chunk kc sits at position
+// kc ^ (r & 7) ^ ((r >> 3) & 1), which puts the 16 rows a fragment read
+// touches on distinct bank groups.  A direct load writes lane i's 16 bytes at
+// (wave-uniform base) + 16 i, so each load instruction fills eight rows.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+constexpr int LROW = 32;                 // floats per LDS row (one k panel)
+constexpr int LSTAGE = 2 * TM * LROW;     // floats per stage (A then B)
+
+__device__ inline int swz(int r, int kc) { return kc ^ (r & 7) ^ ((r >> 3) & 1); }
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_split(GemmArgs p, int T) {
-  gemm_split_body<MODE, 1>(p, T);
+__device__ inline void split8(const float (&x)[8], us8 (&o)[3]) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    unsigned short t[3];
+    split<MODE>(x[v], t);
+    o[0][v] = t[0];
+    o[1][v] = t[1];
+    if (MODE == 1) o[2][v] = t[2];
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void gemm_split_lds_body(GemmArgs p, int T) {
+  constexpr int P = Parts<MODE>::P;
+  constexpr bool F16 = (MODE == 2);
+  const int n = p.n;
+  int bi, bj;
+  tile_of(blockIdx.x, T, p.sym, TILE_GROUP, bi, bj);
+  const int i0 = bi * TM, j0 = bj * TM;
+  __shared__ float stage[2][LSTAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;          // waves 0..3 compute, wave 4 loads
+  const bool producer = wave == 4;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f4 acc[4][4];
+  f4 acc2[F16 ? 4 : 1][F16 ? 4 : 1];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+  if (F16) {
+#pragma unroll
+    for (int r = 0; r < (F16 ? 4 : 1); ++r)
+#pragma unroll
+      for (int c = 0; c < (F16 ? 4 : 1); ++c) acc2[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  const int kt_per = (n + TK - 1) / TK;
+  const int ktiles = kt_per * p.nprod;
+  const bool edge_rows = (i0 + TM > n) || (j0 + TM > n);
+
+  // producer: 16 load instructions per operand fill the 128 rows of a panel;
+  // lane -> row 8 j + lane / 8, physical chunk lane % 8
+  const int lr = lane >> 3, lpc = lane & 7;
+  auto issue = [&](int kt, int st) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * TK;
+    const float *A = (const float *)p.A[prod];
+    const float *B = (const float *)p.B[prod];
+#pragma unroll 4
+    for (int j = 0; j < TM / 8; ++j) {
+      const int r = 8 * j + lr;
+      const int kc = swz(r, lpc);
+      int k = k0 + 4 * kc;
+      k = k < n ? k : n - 4;
+      const int ia = i0 + r < n ? i0 + r : n - 1;
+      const int jb = j0 + r < n ? j0 + r : n - 1;
+      __builtin_amdgcn_global_load_lds((gbl_void_t *)(A + (size_t)ia * n + k),
+                                       (lds_void_t *)&stage[st][8 * j * LROW], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gbl_void_t *)(B + (size_t)jb * n + k),
+                                       (lds_void_t *)&stage[st][TM * LROW + 8 * j * LROW], 16, 0, 0);
+    }
+  };
+
+  const int fr = lane & 15, fq = lane >> 4;  // fragment row, k group (8 values)
+  // eight FP32 values row r, k 8 fq .. 8 fq + 7 of a stage operand, zeroed
+  // outside the matrix on edge tiles and on a partial last k panel
+  auto fetch = [&](const float *base, int r, int rlim, int klim, bool edge, float (&x)[8]) {
+    const f4 lo = *(const f4 *)(base + r * LROW + 4 * swz(r, 2 * fq));
+    const f4 hi = *(const f4 *)(base + r * LROW + 4 * swz(r, 2 * fq + 1));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = lo[v];
+      x[4 + v] = hi[v];
+    }
+    if (edge) {
+      const bool rv = r < rlim;
+      const bool k0v = 8 * fq < klim, k1v = 8 * fq + 4 < klim;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x[v] = (rv && k0v) ? x[v] : 0.0f;
+        x[4 + v] = (rv && k1v) ? x[4 + v] : 0.0f;
+      }
+    }
+  };
+  auto compute = [&](int st, int kt) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * TK;
+    const int klim = n - k0;  // valid k of this panel: [0, klim)
+    const bool edge = edge_rows || klim < TK;
+    const float *sa = &stage[st][0];
+    const float *sb = &stage[st][TM * LROW];
+    us8 b[4][3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float x[8];
+      fetch(sb, wn + 16 * c + fr, n - j0, klim, edge, x);
+      split8<MODE>(x, b[c]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float x[8];
+      us8 a[3];
+      fetch(sa, wm + 16 * r + fr, n - i0, klim, edge, x);
+      split8<MODE>(x, a);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (MODE == 2) {
+          acc[r][c] = mfma(a[0], b[c][0], acc[r][c], true);
+          acc2[r][c] = mfma(a[0], b[c][1], acc2[r][c], true);
+          acc2[r][c] = mfma(a[1], b[c][0], acc2[r][c], true);
+        } else {
+          if (MODE == 1) {
+            acc[r][c] = mfma(a[1], b[c][1], acc[r][c], false);
+            acc[r][c] = mfma(a[0], b[c][2], acc[r][c], false);
+            acc[r][c] = mfma(a[2], b[c][0], acc[r][c], false);
+          }
+          acc[r][c] = mfma(a[0], b[c][1], acc[r][c], false);
+          acc[r][c] = mfma(a[1], b[c][0], acc[r][c], false);
+          acc[r][c] = mfma(a[0], b[c][0], acc[r][c], false);
+        }
+      }
+    }
+  };
+
+  // The producer wave loads panel kt + 1 into the other stage (and waits for
+  // its own loads) while the four compute waves work on panel kt; the one
+  // barrier per panel hands the stages over.  Only the producer ever has
+  // loads in flight, so no wait for them lands in the compute waves.
+  if (producer) {
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  }
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    if (producer) {
+      if (kt + 1 < ktiles) issue(kt + 1, (kt + 1) & 1);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    } else {
+      compute(kt & 1, kt);
+    }
+    __syncthreads();
+  }
+  if (producer) return;
+
+  const float *C1 = (const float *)p.C1;
+  const float *C2 = (const float *)p.C2;
+  float *out = (float *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+  const float alpha = (float)p.alpha, b1 = (float)p.beta1, b2 = (float)p.beta2, gam = (float)p.gamma;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + wn + 16 * c + fr;
+      const int ib = i0 + wm + 16 * r + 4 * (lane >> 4);
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ib + q;
+        float accv = acc[r][c][q];
+        if (MODE == 2) accv += acc2[r][c][q] * (1.0f / 2048.0f);
+        float x = alpha * accv;
+        if (i < n && j < n) {
+          const size_t off = (size_t)i * n + j;
+          if (C1) x += b1 * C1[off];
+          if (C2) x += b2 * C2[off];
+          if (i == j) x += gam;
+          out[off] = x;
+        }
+        v[q] = x;
+      }
+      if (mirror && j < n && ib < n) *(f4 *)(out + (size_t)j * n + ib) = f4{v[0], v[1], v[2], v[3]};
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(320) void k_gemm_split_lds(GemmArgs p, int T) {
+  gemm_split_lds_body<MODE>(p, T);
 }
 
 // BF16x3, the response-chain mode of the mixed-precision step: two register
@@ -298,8 +498,11 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   const int T = (a.n + TM - 1) / TM;
   const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
   switch (prec) {
-    case 2: hipLaunchKernelGGL(k_gemm_split<1>, dim3(blocks), dim3(256), 0, s, a, T); break;
-    case 3: hipLaunchKernelGGL(k_gemm_split<2>, dim3(blocks), dim3(256), 0, s, a, T); break;
+    // the three-part split (and the FP16 split with its second accumulator)
+    // run the direct-to-LDS kernel; BF16x3 the register-staged one, whose
+    // single split per element is cheaper than splitting on every read
+    case 2: hipLaunchKernelGGL(k_gemm_split_lds<1>, dim3(blocks), dim3(320), 0, s, a, T); break;
+    case 3: hipLaunchKernelGGL(k_gemm_split_lds<2>, dim3(blocks), dim3(320), 0, s, a, T); break;
     default: hipLaunchKernelGGL(k_gemm_split_bf16x3, dim3(blocks), dim3(256), 0, s, a, T); break;
   }
 }
