@@ -103,13 +103,21 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
   for (int kt = 0; kt < ktiles; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < ktiles) load(kt + 1);
+    // fragments of k-step kk + 4 are read while the MFMAs of step kk run
+    double fa0, fa1, fb0, fb1;
+    auto frags = [&](int kk) {
+      const int kr = kk + (lane >> 4);
+      fa0 = As[buf][kr][wm + (lane & 15)];
+      fa1 = As[buf][kr][wm + 16 + (lane & 15)];
+      fb0 = Bs[buf][kr][wn + (lane & 15)];
+      fb1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+    };
+    frags(0);
+    __builtin_amdgcn_iglp_opt(0);  // interleave the LDS reads with the MFMAs
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a0 = As[buf][kr][wm + (lane & 15)];
-      double a1 = As[buf][kr][wm + 16 + (lane & 15)];
-      double b0 = Bs[buf][kr][wn + (lane & 15)];
-      double b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+      const double a0 = fa0, a1 = fa1, b0 = fb0, b1 = fb1;
+      if (kk + 4 < BK) frags(kk + 4);
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
