@@ -50,7 +50,8 @@ enum Slot {
   S_KRES = 1216,   // 3: resid^2, ||W0||^2, singular
   S_ORTH = 1220,   // 33 orthogonalisation coefficients
   S_LANC = 1280,   // 2 * LANCZOS_K: alpha_j, beta_j
-  S_TOTAL = 1344
+  S_KCTL = 1344,   // Krylov control: |v|^2, |source|^2, scale, breakdown rank (-1: none)
+  S_TOTAL = 1352
 };
 
 __global__ void k_canon(const double *trR, const double *trM, double *out) {
@@ -114,14 +115,41 @@ __global__ void k_orth(size_t n2, int k, const double *v, const double *const *V
   }
 }
 
-// copy the dots results into row k of O and rhs
-__global__ void k_store_orow(int k, const double *d, double *O, double *rhs) {
+// copy the dots results into row k of O and rhs; <W_k, W_k> is the squared
+// norm of the next Krylov source
+__global__ void k_store_orow(int k, const double *d, double *O, double *rhs, double *src_sq) {
   if (threadIdx.x) return;
   for (int j = 0; j <= k; ++j) {
     O[k * 32 + j] = d[j];
     O[j * 32 + k] = d[j];
   }
   rhs[k] = d[k + 1];
+  *src_sq = d[k];
+}
+
+// normalisation of Krylov direction k on the device: scale = 1/|v| unless
+// |v| <= 1e-12 |source| (breakdown: the rank is recorded, later directions get
+// scale 0 and the solve uses the leading basis only)
+__global__ void k_kscale(int k, double *ctl) {
+  if (threadIdx.x) return;
+  if (ctl[3] >= 0.0) {
+    ctl[2] = 0.0;
+    return;
+  }
+  const double nv = sqrt(ctl[0]);
+  if (nv > 1e-12 * sqrt(ctl[1])) {
+    ctl[2] = 1.0 / nv;
+  } else {
+    ctl[2] = 0.0;
+    ctl[3] = k;
+  }
+}
+__global__ void k_kinit(double *ctl, double w0sq) {
+  if (threadIdx.x) return;
+  ctl[0] = 0.0;
+  ctl[1] = w0sq;
+  ctl[2] = 0.0;
+  ctl[3] = -1.0;
 }
 
 inline void cheb_lin(double lmax, double &a, double &b, double &e0) {
@@ -775,6 +803,11 @@ xlbomd_status ensure_krylov(xlbomd_ctx *c, int m) {
     if (!dev_alloc((void **)&c->Vk[k], c->n2 * 8) || !dev_alloc((void **)&c->Wk[k], c->n2 * 8))
       return fail(c, XLBOMD_E_NOMEM, "Krylov workspace allocation failed");
     ++c->kalloc;
+    // the basis pointers live on the device for k_orth / lincomb; uploading
+    // them once here keeps pageable copies out of the step
+    if (c->kalloc == m &&
+        hipMemcpy(c->dptr, c->Vk, sizeof(double *) * c->kalloc, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, XLBOMD_E_HIP, "Krylov pointer upload failed");
   }
   return XLBOMD_OK;
 }
@@ -803,10 +836,16 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
     if (rel_out) *rel_out = (m == 0 && nw0sq > 0.0) ? 1.0 : 0.0;
     return XLBOMD_OK;
   }
+  // The basis is built without host round trips: normalisation and the
+  // breakdown test run on the device (k_kscale), and the host reads the
+  // residual once at the end (per direction only when tol > 0 asks for an
+  // early stop).
+  double *ctl = c->dscal + S_KCTL;
+  hipLaunchKernelGGL(k_kinit, dim3(1), dim3(64), 0, s, ctl, nw0sq);
   const double *src = W0;
-  double nsrc = std::sqrt(nw0sq);
   int k = 0;
   double rel = 1.0;
+  double kres[3] = {0.0, 0.0, 0.0};
   for (; k < m;) {
     // classical Gram-Schmidt applied twice
     HIPCHK(c, hipMemcpyAsync(v, src, c->n2 * 8, hipMemcpyDeviceToDevice, s));
@@ -818,19 +857,15 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
       }
       for (int j0 = 0; j0 < k; j0 += 16)
         dots(n2, std::min(16, k - j0), xs + j0, ys + j0, c->dscal + S_ORTH + j0, 0, c->red, s);
-      HIPCHK(c, hipMemcpyAsync(c->dptr, c->Vk, sizeof(double *) * k, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_orth, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
       std::swap(v, tmp);
     }
     {
       const void *a[1] = {v};
-      dots(n2, 1, a, a, c->dscal + S_DOTS, 0, c->red, s);
+      dots(n2, 1, a, a, ctl, 0, c->red, s);
     }
-    double nv2;
-    if ((st = get_scalars(c, S_DOTS, 1, &nv2))) return st;
-    const double nv = std::sqrt(nv2);
-    if (!(nv > 1e-12 * nsrc)) break;  // breakdown: rank k
-    axpby(n2, 1.0 / nv, v, 0.0, nullptr, c->Vk[k], 0, s);
+    hipLaunchKernelGGL(k_kscale, dim3(1), dim3(64), 0, s, k, ctl);
+    axpbyI_dev(c->n, ctl + 2, 0.0, v, nullptr, 0.0, nullptr, nullptr, 0.0, c->Vk[k], 0, s);
     // W_k = J V_k = P1[G(V_k)] - V_k
     fock_t(c, c->Vk[k], F1, 0);
     if ((st = response(c, F1, P1))) return st;
@@ -848,23 +883,27 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
         dots(n2, std::min(16, tot - j0), xs + j0, ys + j0, c->dscal + S_DOTS + j0, 0, c->red, s);
     }
     hipLaunchKernelGGL(k_store_orow, dim3(1), dim3(64), 0, s, k, c->dscal + S_DOTS, c->dscal + S_KO,
-                       c->dscal + S_KRHS);
+                       c->dscal + S_KRHS, ctl + 1);
     ++k;
-    krylov_solve(k, c->dscal + S_KO, c->dscal + S_KRHS, c->dscal + S_KCOEF, c->dscal + S_KRES, s);
-    double kres[3];
-    if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
-    rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
-    if (tol > 0.0 && rel < tol) break;
-    double okk;
-    if ((st = get_scalars(c, S_DOTS + k - 1, 1, &okk))) return st;
+    krylov_solve(k, c->dscal + S_KO, c->dscal + S_KRHS, c->dscal + S_KCOEF, c->dscal + S_KRES, ctl + 3, s);
     src = c->Wk[k - 1];
-    nsrc = std::sqrt(okk);
+    if (tol > 0.0) {
+      double kc[4];
+      if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
+      if ((st = get_scalars(c, S_KCTL, 4, kc))) return st;
+      rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
+      if (rel < tol || kc[3] >= 0.0) break;
+    }
   }
+  double kc[4];
+  if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
+  if ((st = get_scalars(c, S_KCTL, 4, kc))) return st;
+  rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
+  const int rank = kc[3] >= 0.0 ? std::min(k, (int)kc[3]) : k;
   if (k > 0) {
-    HIPCHK(c, hipMemcpyAsync(c->dptr, c->Vk, sizeof(double *) * k, hipMemcpyHostToDevice, s));
     lincomb_dev(n2, k, c->dptr, c->dscal + S_KCOEF, Y, s);
   }
-  if (rank_out) *rank_out = k;
+  if (rank_out) *rank_out = rank;
   if (rel_out) *rel_out = rel;
   return XLBOMD_OK;
 }

@@ -348,9 +348,13 @@ __global__ void k_mu_newton(const double *t01, double n_occ, double beta, double
 // Krylov: solve O coef = rhs (k x k, FP64, Gaussian elimination with partial
 // pivoting) and resid2 = ||sum W_i c_i - W0||^2 = c^T O c - 2 c^T rhs + ||W0||^2
 // (the last term is read from resid2[1] on entry).
-__global__ void k_krylov_solve(int k, const double *O, const double *rhs, double *coef,
-                               double *resid2) {
+// k_rank (device, may be null): a basis that broke down at rank r >= 0 solves
+// only the leading r x r system (the remaining coefficients are zero)
+__global__ void k_krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
+                               const double *k_rank) {
   if (threadIdx.x != 0) return;
+  const int kfull = k;
+  if (k_rank && *k_rank >= 0.0 && (int)*k_rank < k) k = (int)*k_rank;
   double a[32][33];
   for (int i = 0; i < k; ++i) {
     for (int j = 0; j < k; ++j) a[i][j] = O[i * 32 + j];
@@ -386,6 +390,7 @@ __global__ void k_krylov_solve(int k, const double *O, const double *rhs, double
     x[i] = s;
   }
   double q = 0.0, l = 0.0;
+  for (int i = k; i < kfull; ++i) coef[i] = 0.0;
   for (int i = 0; i < k; ++i) {
     coef[i] = x[i];
     l += x[i] * rhs[i];
@@ -540,8 +545,8 @@ void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStr
 }
 
 void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_krylov_solve, dim3(1), dim3(64), 0, s, k, O, rhs, coef, resid2);
+                  const double *k_rank, hipStream_t s) {
+  hipLaunchKernelGGL(k_krylov_solve, dim3(1), dim3(64), 0, s, k, O, rhs, coef, resid2, k_rank);
 }
 
 void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, double alpha,

@@ -89,7 +89,7 @@ size_t energy_partial_doubles(int n_atoms);
 void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s);
 void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStream_t s);
 void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
-                  hipStream_t s);
+                  const double *k_rank, hipStream_t s);
 
 // ------------------------------------------------------------- MD kernels
 void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, double alpha,
