@@ -10,6 +10,12 @@
 // each part rounded to nearest-even, and the products accumulate in FP32 on
 // v_mfma_f32_16x16x32_{bf16,f16}.
 //
+// Three kernels share these conventions:
+//  * k_gemm_split_bf16x3 (BF16x3) and k_gemm_split_lds (BF16x6, FP16x3):
+//    128 x 128 tiles, any n with n % 4 == 0;
+//  * k_gemm_split_big (BF16x3 full outputs and BF16x6 at n >= 2048,
+//    n % 32 == 0): 224 x 224 tiles with 112 x 112 wave tiles.
+//
 // Tile 128 x 128 per workgroup of 256 threads (2 x 2 wavefronts of 64 x 64,
 // i.e. 4 x 4 MFMA blocks of 16 x 16 each).  K advances by 32 through
 // double-buffered LDS panels.  Both panels are stored k-fastest (row-major
@@ -485,6 +491,274 @@ __global__ __launch_bounds__(320) void k_gemm_split_lds(GemmArgs p, int T) {
   gemm_split_lds_body<MODE>(p, T);
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile split GEMM: 224 x 224 output tiles, four waves of 112 x 112
+// (7 x 7 MFMA blocks each), one workgroup per compute unit; n % 32 == 0.
+//
+// The larger wave tile halves the LDS bytes read per MFMA against 64 x 64
+// waves, and 224 divides the 3360 orbitals of the 840-atom cluster exactly.
+// All four waves stream the FP32 panels (224 A rows and 224 B rows x 32 k)
+// into LDS with global_load_lds, two stages deep.  The stages are separate
+// LDS arrays, so the loads into one stage carry no wait for the reads of the
+// other, and the one barrier per panel is also where the next stage's loads
+// are complete.  Each wave splits its fragments into BF16/FP16 parts on read.
+// BF16 parts of eight FP32 values, two at a time: v_cvt_pk_bf16_f32 rounds a
+// pair to nearest even, and each rounded part goes back to FP32 by a shift
+// or a mask of its half of the packed word.
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+__device__ inline unsigned cvt_pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f2){a, b}, bf2));
+}
+template <int MODE>
+__device__ inline void split8_pk(const float (&x)[8], us8 (&o)[3]) {
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  u4 h, l, l2;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const float a = x[2 * v], b = x[2 * v + 1];
+    const unsigned hp = cvt_pk_bf16(a, b);
+    const float ra = a - __builtin_bit_cast(float, hp << 16);
+    const float rb = b - __builtin_bit_cast(float, hp & 0xffff0000u);
+    const unsigned lp = cvt_pk_bf16(ra, rb);
+    h[v] = hp;
+    l[v] = lp;
+    if (MODE == 1) {
+      const float sa = ra - __builtin_bit_cast(float, lp << 16);
+      const float sb = rb - __builtin_bit_cast(float, lp & 0xffff0000u);
+      l2[v] = cvt_pk_bf16(sa, sb);
+    }
+  }
+  o[0] = __builtin_bit_cast(us8, h);
+  o[1] = __builtin_bit_cast(us8, l);
+  if (MODE == 1) o[2] = __builtin_bit_cast(us8, l2);
+}
+
+constexpr int BT = 224;               // tile edge
+constexpr int BW = 112;               // wave tile edge
+constexpr int BNB = BW / 16;          // MFMA blocks per wave tile edge
+constexpr int BSTAGE = 2 * BT * LROW;  // floats per stage (A rows, then B rows)
+constexpr int BIG_GROUP = 3;          // tile rows per L2-sharing group
+constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor word 3 (32-bit data format)
+
+template <int MODE>
+__device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
+  // BF16 splits only: the FP16 split's second accumulator does not fit
+  static_assert(MODE == 0 || MODE == 1, "large-tile kernel: BF16 splits only");
+  const int n = p.n;
+  int bi, bj;
+  tile_of(blockIdx.x, T, p.sym, BIG_GROUP, bi, bj);
+  const int i0 = bi * BT, j0 = bj * BT;
+  __shared__ float st0[BSTAGE];
+  __shared__ float st1[BSTAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int wm = (wave >> 1) * BW, wn = (wave & 1) * BW;
+
+  f4 acc[BNB][BNB];
+#pragma unroll
+  for (int r = 0; r < BNB; ++r)
+#pragma unroll
+    for (int c = 0; c < BNB; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // n is a multiple of 32, so every k panel is full.  Rows past n are read
+  // clamped to row n - 1: they only reach output rows and columns past n,
+  // which are not stored.
+  const int kt_per = n / TK;
+  const int ktiles = kt_per * p.nprod;
+
+  // loads: wave w fills stage rows [112 w, 112 w + 112) (waves 0, 1: A rows,
+  // 2, 3: B rows), eight rows per instruction; lane -> row lane / 8,
+  // physical chunk lane % 8
+  const int lr = lane >> 3, lpc = lane & 7;
+  const bool ldA = wave < 2;
+  const int g0 = (ldA ? i0 : j0) + (wave & 1) * BW;
+  // Buffer loads to LDS: the lane's byte offset of each load row is computed
+  // once (n^2 FP32 values fit in 32 bits for n <= 32767) and the k panel is
+  // the scalar offset.  Stage row 112 w + 8 j + lr has swizzle
+  // lpc ^ lr ^ (j & 1).
+  unsigned roff[BW / 8];
+#pragma unroll
+  for (int j = 0; j < BW / 8; ++j) {
+    int g = g0 + 8 * j + lr;
+    g = g < n ? g : n - 1;
+    roff[j] = 4u * ((unsigned)g * (unsigned)n + 4u * (unsigned)(lpc ^ lr ^ (j & 1)));
+  }
+  const int nbytes = (int)(4u * (unsigned)n * (unsigned)n);  // buffer range (n <= 32767)
+  auto issue = [&](int kt, float *stg) {
+    const int prod = kt / kt_per;
+    const unsigned kb = 4u * (unsigned)((kt - prod * kt_per) * TK);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(ldA ? p.A[prod] : p.B[prod]), (short)0, nbytes, BUF_DWORD3);
+#pragma unroll
+    for (int j = 0; j < BW / 8; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&stg[(wave * BW + 8 * j) * LROW], 16, roff[j], kb,
+                                               0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  const int fr = lane & 15, fq = lane >> 4;
+  // eight FP32 values of stage row r, k 8 fq .. 8 fq + 7
+  auto fetch = [&](const float *stg, int r, float (&x)[8]) {
+    const f4 lo = *(const f4 *)(stg + r * LROW + 4 * swz(r, 2 * fq));
+    const f4 hi = *(const f4 *)(stg + r * LROW + 4 * swz(r, 2 * fq + 1));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = lo[v];
+      x[4 + v] = hi[v];
+    }
+  };
+  // the product terms of row block r and column block c, small terms first
+  auto mma = [&](int r, int c, const us8 (&a)[3], const us8 (&bc)[3]) {
+    if (MODE == 1) {
+      acc[r][c] = mfma(a[1], bc[1], acc[r][c], false);
+      acc[r][c] = mfma(a[0], bc[2], acc[r][c], false);
+      acc[r][c] = mfma(a[2], bc[0], acc[r][c], false);
+    }
+    acc[r][c] = mfma(a[0], bc[1], acc[r][c], false);
+    acc[r][c] = mfma(a[1], bc[0], acc[r][c], false);
+    acc[r][c] = mfma(a[0], bc[0], acc[r][c], false);
+  };
+  constexpr int TERMS = (MODE == 1) ? 6 : 3;
+  constexpr int RM = BNB * TERMS;  // MFMAs per row block
+
+  // Software pipeline over k panels.  Within a panel the A fragment of row
+  // block r + 1 is split, and that of r + 2 read, under the MFMAs of block r.
+  // The one barrier per panel sits after row block 4, whose reads are the
+  // panel's last: past it the next panel's loads have landed (each wave waits
+  // for its own), so rows 5 and 6 read and split the next panel's B
+  // fragments and first A fragments under their MFMAs, and the loads of the
+  // panel after next go into the stage just read.  Group barriers interleave
+  // the MFMAs with that VALU and LDS work.
+  us8 b[BNB][3], a[3];
+  float xn[8];
+  issue(0, st0);
+  if (ktiles > 1) issue(1, st1);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  __syncthreads();
+  {
+    float x[8];
+#pragma unroll
+    for (int c = 0; c < BNB; ++c) {
+      fetch(st0, BT + wn + 16 * c + fr, x);
+      split8_pk<MODE>(x, b[c]);
+    }
+    fetch(st0, wm + fr, x);
+    split8_pk<MODE>(x, a);
+    fetch(st0, wm + 16 + fr, xn);
+  }
+  for (int kt = 0; kt < ktiles; ++kt) {
+    float *cur = (kt & 1) ? st1 : st0;
+    float *nxt = (kt & 1) ? st0 : st1;
+    us8 an[3];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      split8_pk<MODE>(xn, an);
+      fetch(cur, wm + 16 * (r + 2) + fr, xn);
+#pragma unroll
+      for (int c = 0; c < BNB; ++c) mma(r, c, a, b[c]);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // DS read
+#pragma unroll
+      for (int i = 0; i < RM; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) a[q] = an[q];
+    }
+    // the LDS writes of this wave's buffer loads are done once vmcnt drains
+    // (the compiler does not wait for them here by itself)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (kt + 2 < ktiles) issue(kt + 2, cur);
+    us8 bn[BNB][3];
+    // row block 5: split A block 6; read and split B blocks 0..3 of the next panel
+    split8_pk<MODE>(xn, an);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float x[8];
+      fetch(nxt, BT + wn + 16 * c + fr, x);
+      split8_pk<MODE>(x, bn[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < BNB; ++c) mma(5, c, a, b[c]);
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // row block 6: B blocks 4..6 and A blocks 0, 1 of the next panel
+#pragma unroll
+    for (int c = 4; c < BNB; ++c) {
+      float x[8];
+      fetch(nxt, BT + wn + 16 * c + fr, x);
+      split8_pk<MODE>(x, bn[c]);
+    }
+    us8 a0[3];
+    {
+      float x[8];
+      fetch(nxt, wm + fr, x);
+      split8_pk<MODE>(x, a0);
+    }
+#pragma unroll
+    for (int c = 0; c < BNB; ++c) mma(6, c, an, b[c]);
+    fetch(nxt, wm + 16 + fr, xn);
+    __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < BNB; ++c)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[c][q] = bn[c][q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a[q] = a0[q];
+  }
+
+  const float *C1 = (const float *)p.C1;
+  const float *C2 = (const float *)p.C2;
+  float *out = (float *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+  const float alpha = (float)p.alpha, b1 = (float)p.beta1, b2 = (float)p.beta2, gam = (float)p.gamma;
+#pragma unroll
+  for (int r = 0; r < BNB; ++r) {
+#pragma unroll
+    for (int c = 0; c < BNB; ++c) {
+      const int j = j0 + wn + 16 * c + fr;
+      const int ib = i0 + wm + 16 * r + 4 * fq;
+      float v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = ib + q;
+        float x = alpha * acc[r][c][q];
+        if (i < n && j < n) {
+          const size_t off = (size_t)i * n + j;
+          if (C1) x += b1 * C1[off];
+          if (C2) x += b2 * C2[off];
+          if (i == j) x += gam;
+          out[off] = x;
+        }
+        v[q] = x;
+      }
+      if (mirror && j < n && ib < n) *(f4 *)(out + (size_t)j * n + ib) = f4{v[0], v[1], v[2], v[3]};
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split_big(GemmArgs p,
+                                                                                                   int T) {
+  gemm_split_big_body<MODE>(p, T);
+}
+
 // BF16x3, the response-chain mode of the mixed-precision step: two register
 // stages at two waves per SIMD
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm_split_bf16x3(GemmArgs p,
@@ -495,6 +769,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }  // namespace
 
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
+  // the 224-tile kernel needs n % 32 == 0 and enough tiles to fill the chip;
+  // for the two-part split it only pays on full (non-symmetric) outputs
+  const bool big = (a.n % 32 == 0) && a.n >= 2048 && a.n <= 32767;
+  if (big && (prec == 2 || (prec == 1 && !a.sym))) {
+    const int T = (a.n + BT - 1) / BT;
+    const int blocks = tile_count(T, a.sym);
+    if (prec == 2)
+      hipLaunchKernelGGL(k_gemm_split_big<1>, dim3(blocks), dim3(256), 0, s, a, T);
+    else
+      hipLaunchKernelGGL(k_gemm_split_big<0>, dim3(blocks), dim3(256), 0, s, a, T);
+    return;
+  }
   const int T = (a.n + TM - 1) / TM;
   const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
   switch (prec) {

@@ -72,6 +72,38 @@ def test_split_matmul(binding, mode, n_atoms, sym):
     h.close()
 
 
+@pytest.mark.parametrize("mode", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("n_atoms", [560, 584])
+@pytest.mark.parametrize("sym", [0, 1])
+def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
+    """n = 2240 (ten 224-row tiles) and n = 2336 (a ragged last tile): the
+    sizes at which the two-part split's full products and the three-part
+    split run the 224 x 224-tile kernel."""
+    s = carbon_cluster(n_atoms, 2)
+    h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
+    n = s.n_orb
+    rng = np.random.default_rng(n_atoms + 11)
+    A = rng.uniform(-0.5, 0.5, (n, n))
+    A = 0.5 * (A + A.T)
+    B = A @ A / n + np.eye(n) if sym else 0.5 * (lambda M: M + M.T)(rng.uniform(-0.5, 0.5, (n, n)))
+    dev = torch.device("cuda:0")
+    C = torch.empty((n, n), dtype=torch.float64, device=dev)
+    h.matmul(torch.tensor(A, device=dev), torch.tensor(B, device=dev), C, sym_out=bool(sym))
+    torch.cuda.synchronize()
+    A32 = A.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    Cg = C.cpu().numpy()
+    ref = A32 @ B32
+    err = _rel(Cg, ref)
+    # FP32 accumulation over n terms adds ~sqrt(n) u32 of the absolute partial
+    # sums (|A| |B|); with a factor 4 of headroom this joins the split budget
+    S = float((np.abs(A32) @ np.abs(B32)).max())
+    acc = 4.0 * np.sqrt(n) * 2.0**-24 * S / np.abs(ref).max()
+    print(f"{mode} n={n} sym={sym} matmul rel err {err:.3e} (accumulation budget {acc:.1e})")
+    assert err <= BOUND[mode]["mm"] + acc
+    h.close()
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name", ["c10", "c100"])
 def test_split_density_response_forces(binding, mode, name):
