@@ -13,8 +13,8 @@
 // Three kernels share these conventions:
 //  * k_gemm_split_bf16x3 (BF16x3) and k_gemm_split_lds (BF16x6, FP16x3):
 //    128 x 128 tiles, any n with n % 4 == 0;
-//  * k_gemm_split_big (BF16x3 full outputs and BF16x6 at n >= 2048,
-//    n % 32 == 0): 224 x 224 tiles with 112 x 112 wave tiles.
+//  * k_gemm_split_big (BF16x3 and BF16x6, n % 32 == 0, large n): 224 x 224
+//    tiles for full outputs, 160 x 160 for symmetric ones.
 //
 // Tile 128 x 128 per workgroup of 256 threads (2 x 2 wavefronts of 64 x 64,
 // i.e. 4 x 4 MFMA blocks of 16 x 16 each).  K advances by 32 through
@@ -492,16 +492,18 @@ __global__ __launch_bounds__(320) void k_gemm_split_lds(GemmArgs p, int T) {
 }
 
 // ---------------------------------------------------------------------------
-// Large-tile split GEMM: 224 x 224 output tiles, four waves of 112 x 112
-// (7 x 7 MFMA blocks each), one workgroup per compute unit; n % 32 == 0.
+// Large-tile split GEMM (BF16 splits, n % 32 == 0): 2 x 2 waves of BNB x BNB
+// MFMA blocks of 16, one workgroup per compute unit.  BNB = 7 gives 224 x 224
+// tiles (full outputs: 225 tiles at the 3360 orbitals of the 840-atom
+// cluster), BNB = 5 gives 160 x 160 tiles (symmetric outputs: 231 upper
+// tiles there), so either fills the 256 compute units in one round.
 //
-// The larger wave tile halves the LDS bytes read per MFMA against 64 x 64
-// waves, and 224 divides the 3360 orbitals of the 840-atom cluster exactly.
-// All four waves stream the FP32 panels (224 A rows and 224 B rows x 32 k)
-// into LDS with global_load_lds, two stages deep.  The stages are separate
-// LDS arrays, so the loads into one stage carry no wait for the reads of the
+// The larger wave tiles cut the LDS bytes read per MFMA against 64 x 64
+// waves.  All four waves stream the FP32 panels (A rows and B rows x 32 k)
+// into LDS with buffer loads, two stages deep.  The stages are separate LDS
+// arrays, so the loads into one stage carry no wait for the reads of the
 // other, and the one barrier per panel is also where the next stage's loads
-// are complete.  Each wave splits its fragments into BF16/FP16 parts on read.
+// are complete.  Each wave splits its fragments into BF16 parts on read.
 // BF16 parts of eight FP32 values, two at a time: v_cvt_pk_bf16_f32 rounds a
 // pair to nearest even, and each rounded part goes back to FP32 by a shift
 // or a mask of its half of the packed word.
@@ -534,17 +536,19 @@ __device__ inline void split8_pk(const float (&x)[8], us8 (&o)[3]) {
   if (MODE == 1) o[2] = __builtin_bit_cast(us8, l2);
 }
 
-constexpr int BT = 224;               // tile edge
-constexpr int BW = 112;               // wave tile edge
-constexpr int BNB = BW / 16;          // MFMA blocks per wave tile edge
-constexpr int BSTAGE = 2 * BT * LROW;  // floats per stage (A rows, then B rows)
 constexpr int BIG_GROUP = 3;          // tile rows per L2-sharing group
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor word 3 (32-bit data format)
 
-template <int MODE>
+// BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles) or 5 (160)
+template <int MODE, int BNB>
 __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   // BF16 splits only: the FP16 split's second accumulator does not fit
   static_assert(MODE == 0 || MODE == 1, "large-tile kernel: BF16 splits only");
+  constexpr int BW = 16 * BNB;           // wave tile edge
+  constexpr int BT = 2 * BW;             // tile edge
+  constexpr int BSTAGE = 2 * BT * LROW;  // floats per stage (A rows, then B rows)
+  // the load swizzle below takes stage rows 8 j + lr of a wave's BW rows
+  static_assert((BW / 8) % 2 == 0, "wave row count must be a multiple of 16");
   const int n = p.n;
   int bi, bj;
   tile_of(blockIdx.x, T, p.sym, BIG_GROUP, bi, bj);
@@ -626,12 +630,12 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
 
   // Software pipeline over k panels.  Within a panel the A fragment of row
   // block r + 1 is split, and that of r + 2 read, under the MFMAs of block r.
-  // The one barrier per panel sits after row block 4, whose reads are the
-  // panel's last: past it the next panel's loads have landed (each wave waits
-  // for its own), so rows 5 and 6 read and split the next panel's B
-  // fragments and first A fragments under their MFMAs, and the loads of the
-  // panel after next go into the stage just read.  Group barriers interleave
-  // the MFMAs with that VALU and LDS work.
+  // The one barrier per panel sits after row block BNB - 3, whose reads are
+  // the panel's last: past it the next panel's loads have landed (each wave
+  // waits for its own), so the last two row blocks read and split the next
+  // panel's B fragments and first A fragments under their MFMAs, and the
+  // loads of the panel after next go into the stage just read.  Group
+  // barriers interleave the MFMAs with that VALU and LDS work.
   us8 b[BNB][3], a[3];
   float xn[8];
   issue(0, st0);
@@ -654,7 +658,7 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
     float *nxt = (kt & 1) ? st0 : st1;
     us8 an[3];
 #pragma unroll
-    for (int r = 0; r < 5; ++r) {
+    for (int r = 0; r < BNB - 2; ++r) {
       split8_pk<MODE>(xn, an);
       fetch(cur, wm + 16 * (r + 2) + fr, xn);
 #pragma unroll
@@ -675,26 +679,27 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
     __syncthreads();
     if (kt + 2 < ktiles) issue(kt + 2, cur);
     us8 bn[BNB][3];
-    // row block 5: split A block 6; read and split B blocks 0..3 of the next panel
+    constexpr int H = (BNB + 1) / 2;  // next-panel B blocks split under row block BNB - 2
+    // row block BNB - 2: split its successor's A block; B blocks 0 .. H - 1 of the next panel
     split8_pk<MODE>(xn, an);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < H; ++c) {
       float x[8];
       fetch(nxt, BT + wn + 16 * c + fr, x);
       split8_pk<MODE>(x, bn[c]);
     }
 #pragma unroll
-    for (int c = 0; c < BNB; ++c) mma(5, c, a, b[c]);
-    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+    for (int c = 0; c < BNB; ++c) mma(BNB - 2, c, a, b[c]);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * H, 0);
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // row block 6: B blocks 4..6 and A blocks 0, 1 of the next panel
+    // row block BNB - 1: B blocks H .. BNB - 1 and A blocks 0, 1 of the next panel
 #pragma unroll
-    for (int c = 4; c < BNB; ++c) {
+    for (int c = H; c < BNB; ++c) {
       float x[8];
       fetch(nxt, BT + wn + 16 * c + fr, x);
       split8_pk<MODE>(x, bn[c]);
@@ -706,9 +711,9 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
       split8_pk<MODE>(x, a0);
     }
 #pragma unroll
-    for (int c = 0; c < BNB; ++c) mma(6, c, an, b[c]);
+    for (int c = 0; c < BNB; ++c) mma(BNB - 1, c, an, b[c]);
     fetch(nxt, wm + 16 + fr, xn);
-    __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * (BNB - H) + 4, 0);
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -753,10 +758,10 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   }
 }
 
-template <int MODE>
+template <int MODE, int BNB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split_big(GemmArgs p,
                                                                                                    int T) {
-  gemm_split_big_body<MODE>(p, T);
+  gemm_split_big_body<MODE, BNB>(p, T);
 }
 
 // BF16x3, the response-chain mode of the mixed-precision step: two register
@@ -769,27 +774,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }  // namespace
 
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
-  // the 224-tile kernel needs n % 32 == 0 and enough tiles to fill the chip;
-  // for the two-part split it only pays on full (non-symmetric) outputs
-  const bool big = (a.n % 32 == 0) && a.n >= 2048 && a.n <= 32767;
-  if (big && (prec == 2 || (prec == 1 && !a.sym))) {
-    const int T = (a.n + BT - 1) / BT;
-    const int blocks = tile_count(T, a.sym);
-    if (prec == 2)
-      hipLaunchKernelGGL(k_gemm_split_big<1>, dim3(blocks), dim3(256), 0, s, a, T);
-    else
-      hipLaunchKernelGGL(k_gemm_split_big<0>, dim3(blocks), dim3(256), 0, s, a, T);
+  // large tiles (224 rows for full outputs, 160 for symmetric ones) need
+  // n % 32 == 0 and pay once they give at least 3/4 of a workgroup per
+  // compute unit (192 of the 256); below that the 128-row tiles fill the chip
+  // better
+  const int edge = a.sym ? 160 : 224;
+  const int T = (a.n + edge - 1) / edge;
+  const int blocks = tile_count(T, a.sym);
+  const bool big = (a.n % 32 == 0) && a.n <= 32767 && blocks >= 192;
+  if (big && (prec == 1 || prec == 2)) {
+    if (a.sym) {
+      if (prec == 2)
+        hipLaunchKernelGGL((k_gemm_split_big<1, 5>), dim3(blocks), dim3(256), 0, s, a, T);
+      else
+        hipLaunchKernelGGL((k_gemm_split_big<0, 5>), dim3(blocks), dim3(256), 0, s, a, T);
+    } else {
+      if (prec == 2)
+        hipLaunchKernelGGL((k_gemm_split_big<1, 7>), dim3(blocks), dim3(256), 0, s, a, T);
+      else
+        hipLaunchKernelGGL((k_gemm_split_big<0, 7>), dim3(blocks), dim3(256), 0, s, a, T);
+    }
     return;
   }
-  const int T = (a.n + TM - 1) / TM;
-  const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
+  const int Ts = (a.n + TM - 1) / TM;
+  const int nb = a.sym ? Ts * (Ts + 1) / 2 : Ts * Ts;
   switch (prec) {
     // the three-part split (and the FP16 split with its second accumulator)
     // run the direct-to-LDS kernel; BF16x3 the register-staged one, whose
     // single split per element is cheaper than splitting on every read
-    case 2: hipLaunchKernelGGL(k_gemm_split_lds<1>, dim3(blocks), dim3(320), 0, s, a, T); break;
-    case 3: hipLaunchKernelGGL(k_gemm_split_lds<2>, dim3(blocks), dim3(320), 0, s, a, T); break;
-    default: hipLaunchKernelGGL(k_gemm_split_bf16x3, dim3(blocks), dim3(256), 0, s, a, T); break;
+    case 2: hipLaunchKernelGGL(k_gemm_split_lds<1>, dim3(nb), dim3(320), 0, s, a, Ts); break;
+    case 3: hipLaunchKernelGGL(k_gemm_split_lds<2>, dim3(nb), dim3(320), 0, s, a, Ts); break;
+    default: hipLaunchKernelGGL(k_gemm_split_bf16x3, dim3(nb), dim3(256), 0, s, a, Ts); break;
   }
 }
 

@@ -73,12 +73,12 @@ def test_split_matmul(binding, mode, n_atoms, sym):
 
 
 @pytest.mark.parametrize("mode", ["bf16x3", "bf16x6"])
-@pytest.mark.parametrize("n_atoms", [560, 584])
+@pytest.mark.parametrize("n_atoms", [840, 848])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
-    """n = 2240 (ten 224-row tiles) and n = 2336 (a ragged last tile): the
-    sizes at which the two-part split's full products and the three-part
-    split run the 224 x 224-tile kernel."""
+    """n = 3360 (15 tiles of 224 rows, 21 of 160) and n = 3392 (ragged last
+    tiles): sizes at which the BF16 splits run the large-tile kernels, 224-row
+    tiles for full outputs and 160-row tiles for symmetric ones."""
     s = carbon_cluster(n_atoms, 2)
     h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
     n = s.n_orb
