@@ -103,6 +103,8 @@ typedef struct {
   double kappa;       /* eq. 35 kappa = dt^2 omega^2                                     */
   double alpha;       /* eq. 29/35 damping alpha                                         */
   double c[7];        /* eq. 29/35 damping c_k, k = 0..6                                 */
+  double kernel_c;    /* m = 0: the original XL-BOMD kernel K = -c I (scaled identity,   */
+                      /* Results, low-gap fullerene test: c = 1, or 0.9 tuned), c > 0    */
 } xlbomd_params;
 
 /* MD state of xlbomd_step, all DEVICE pointers owned by the caller.  The X
@@ -177,7 +179,9 @@ xlbomd_status xlbomd_dm_response(xlbomd_handle h, const double *F1, double *P1);
  * J V = P1[G(V)] - V the Jacobian of the residual (eq. 15).  Requires a
  * xlbomd_fermi_dm on F = h + G(X) just before (its chain is reused).
  *   m         requested rank (0 <= m <= 32); tol > 0 stops early once the
- *             relative residual falls below tol
+ *             relative residual falls below tol.  m = 0 is the original
+ *             XL-BOMD kernel K = -c I: Y = -kernel_c (P0 - X), rank 0,
+ *             relres 1 (no Jacobian is applied)
  *   Y         DEVICE n x n output
  *   rank      host out: rank used (breakdown is reported here, not as an error)
  *   relres    host out: ||sum W_i M_ij <W_j, W0> - W0|| / ||W0||  */
@@ -200,6 +204,20 @@ xlbomd_status xlbomd_integrate(xlbomd_handle h, xlbomd_md_state *st);
  * closing half kick.  rep: host array of n_steps reports (nullable). */
 xlbomd_status xlbomd_step(xlbomd_handle h, xlbomd_md_state *st, int n_steps,
                           xlbomd_report *rep);
+
+/* Langevin (NVT) variant of xlbomd_step, the thermostat of the paper's
+ * Results runs (the paper does not give its scheme): the nuclei follow the
+ * BAOAB splitting (Leimkuhler and Matthews 2013): half kick, half drift,
+ * v <- c1 v + c2 xi with c1 = exp(-gamma dt), c2 = sqrt(k_B T_ion / M
+ * (1 - c1^2)), half drift, forces, half kick; the electronic update (eq. 35)
+ * is that of xlbomd_step.
+ *   gamma   friction, 1/fs (>= 0; 0 reproduces xlbomd_step exactly)
+ *   T_ion   bath temperature, K (>= 0)
+ *   xi      DEVICE, n_steps x n_atoms x 3 independent standard normal
+ *           numbers drawn by the caller; step k reads xi + 3 n_atoms k
+ * E_tot in the reports is not a constant of motion here. */
+xlbomd_status xlbomd_step_langevin(xlbomd_handle h, xlbomd_md_state *st, int n_steps, double gamma,
+                                   double T_ion, const double *xi, xlbomd_report *rep);
 
 /* Initial state for xlbomd_step: evaluates P0, Y and the accelerations at
  * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5). */

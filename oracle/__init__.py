@@ -27,6 +27,10 @@ Parity status per function:
   krylov.krylov_kernel                                       pinned (full rank = exact inverse Jacobian)
   dynamics.energy_forces                                     pinned (finite differences of U)
   dynamics.md_step / dynamics.scf                            pinned (dt^2 scaling, reversibility, residual)
+  dynamics.evaluate with m = 0 (K = -c I)                    pinned (closed form; equals the full-rank
+                                                             kernel when J = -I; unstable where KSA is not)
+  dynamics.ou_coefficients / dynamics.langevin_step          pinned (Maxwell-Boltzmann variance; gamma = 0
+                                                             is md_step; thermalisation to the bath T)
 """
 
 from . import model, density, krylov, dynamics  # noqa: F401

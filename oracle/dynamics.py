@@ -101,6 +101,9 @@ class Settings:
     alpha: float = XL_ALPHA
     c: tuple = XL_C
     krylov_tol: float = 0.0
+    # m = 0: the kernel of the original XL-BOMD, the scaled identity K = -c I
+    # (Results, low-gap fullerene test: c = 1, or c = 0.9 tuned for stability)
+    kernel_c: float = 1.0
 
     @property
     def beta(self) -> float:
@@ -129,7 +132,13 @@ def evaluate(R, X, sys_, st: Settings, with_kernel: bool = True) -> dict:
         def jac(V):
             F1 = model.two_electron(V, R, sys_.onecenter, sys_.noise, p)
             return density.response(F, F1, sys_.n_elec, beta, dm) - V
-        Y, rank, rel = krylov.krylov_kernel(X, P0, jac, st.m, st.krylov_tol)
+        if st.m == 0:
+            # original XL-BOMD: eq. 35's kernel term with K = -c I in place of
+            # the Krylov sum; no Jacobian is applied, the residual is reported as 1
+            W0 = P0 - X
+            Y, rank, rel = -st.kernel_c * W0, 0, (1.0 if np.any(W0) else 0.0)
+        else:
+            Y, rank, rel = krylov.krylov_kernel(X, P0, jac, st.m, st.krylov_tol)
         out.update(Y=Y, rank=rank, relres=rel)
     return out
 
@@ -221,3 +230,39 @@ def md_step(state: MDState, sys_, st: Settings):
                T_ion=2.0 * KE / (dof * density.KB_EV_PER_K), mu=ev["mu"],
                W0=float(np.linalg.norm(ev["P0"] - Xn)), relres=ev["relres"], rank=ev["rank"])
     return new, rep
+def ou_coefficients(gamma: float, T_ion: float, dt: float, mass: float):
+    """Exact Ornstein-Uhlenbeck velocity update over dt: v <- c1 v + c2 xi,
+    xi ~ N(0, 1), c1 = exp(-gamma dt), c2 = sqrt(k_B T / M (1 - c1^2)) in
+    Angstrom/fs; it leaves the Maxwell-Boltzmann distribution at T unchanged."""
+    c1 = float(np.exp(-gamma * dt))
+    c2 = float(np.sqrt(density.KB_EV_PER_K * T_ion / mass * EV_PER_AMU_TO_A2_PER_FS2 * (1.0 - c1 * c1)))
+    return c1, c2
+
+
+def langevin_step(state: MDState, sys_, st: Settings, gamma: float, T_ion: float, xi: np.ndarray):
+    """One NVT step with a Langevin thermostat on the nuclei (the paper's
+    Results runs use one without giving the scheme; this is the BAOAB
+    splitting of Leimkuhler and Matthews 2013: half kick, half drift, exact
+    Ornstein-Uhlenbeck velocity update with the caller's standard normals xi
+    (n_atoms x 3), half drift, forces, half kick).  The electronic degrees of
+    freedom follow eq. 35 as in md_step.  Returns (state, report)."""
+    dt = st.dt
+    mass = sys_.params.mass
+    c1, c2 = ou_coefficients(gamma, T_ion, dt, mass)
+    Vh = state.V + 0.5 * dt * state.A
+    Rh = state.R + 0.5 * dt * Vh
+    Vo = c1 * Vh + c2 * np.asarray(xi, dtype=np.float64).reshape(Vh.shape)
+    Rn = Rh + 0.5 * dt * Vo
+    Xn = integrate_x(state.Xhist, state.Y, st)
+    ev = evaluate(Rn, Xn, sys_, st)
+    An = ev["forces"] / mass * EV_PER_AMU_TO_A2_PER_FS2
+    Vn = Vo + 0.5 * dt * An
+    new = MDState(R=Rn, V=Vn, A=An, Xhist=[Xn] + state.Xhist[:-1], Y=ev["Y"], mu=ev["mu"],
+                  U=ev["U"], step=state.step + 1)
+    KE = kinetic_energy(Vn, mass)
+    dof = max(3 * sys_.n_atoms - 3, 1)
+    rep = dict(E_tot=KE + ev["U"], KE=KE, U=ev["U"], TS=2.0 * ev["S"] / st.beta,
+               T_ion=2.0 * KE / (dof * density.KB_EV_PER_K), mu=ev["mu"],
+               W0=float(np.linalg.norm(ev["P0"] - Xn)), relres=ev["relres"], rank=ev["rank"])
+    return new, rep
+

@@ -27,7 +27,7 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
 SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
            "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm",
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
-           "xlbomd_step", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul",
+           "xlbomd_step", "xlbomd_step_langevin", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul",
            "xlbomd_profile", "xlbomd_profile_read"]
 
 
@@ -46,7 +46,7 @@ class System(C.Structure):
 class Params(C.Structure):
     _fields_ = [("prec", C.c_int), ("T_e", C.c_double), ("m", C.c_int), ("krylov_tol", C.c_double),
                 ("dt", C.c_double), ("kappa", C.c_double), ("alpha", C.c_double),
-                ("c", C.c_double * 7)]
+                ("c", C.c_double * 7), ("kernel_c", C.c_double)]
 
 
 class MDStateC(C.Structure):
@@ -88,6 +88,7 @@ def load():
     lib.xlbomd_forces.argtypes = [vp, vp, vp, vp, pd]
     lib.xlbomd_integrate.argtypes = [vp, C.POINTER(MDStateC)]
     lib.xlbomd_step.argtypes = [vp, C.POINTER(MDStateC), i, C.POINTER(Report)]
+    lib.xlbomd_step_langevin.argtypes = [vp, C.POINTER(MDStateC), i, d, d, vp, C.POINTER(Report)]
     lib.xlbomd_md_init.argtypes = [vp, C.POINTER(MDStateC)]
     lib.xlbomd_scf.argtypes = [vp, vp, i, d, i, pd]
     lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
@@ -140,7 +141,7 @@ class Handle:
 
     def __init__(self, n_atoms, n_elec, onecenter, noise55, model, *, prec="fp64", T_e=3000.0,
                  m=4, dt=0.5, kappa=1.84, alpha=0.0055,
-                 c=(-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0), krylov_tol=0.0, stream=None):
+                 c=(-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0), krylov_tol=0.0, kernel_c=1.0, stream=None):
         self.lib = load()
         self.n_atoms = int(n_atoms)
         self.n = 4 * self.n_atoms
@@ -160,7 +161,8 @@ class Handle:
         sysc = System(self.n_atoms, float(n_elec), self._oc.ctypes.data_as(C.POINTER(C.c_double)),
                       self._noise.ctypes.data_as(C.POINTER(C.c_float)), mdl)
         prm = Params(PREC[prec] if isinstance(prec, str) else int(prec), float(T_e), int(m),
-                     float(krylov_tol), float(dt), float(kappa), float(alpha), (C.c_double * 7)(*c))
+                     float(krylov_tol), float(dt), float(kappa), float(alpha), (C.c_double * 7)(*c),
+                     float(kernel_c))
         self.prec = prec
         self.m = int(m)
         h = C.c_void_p()
@@ -238,6 +240,21 @@ class Handle:
         sc = state._c(self)
         reps = (Report * max(n_steps, 1))() if report else None
         self._check(self.lib.xlbomd_step(self.h, C.byref(sc), int(n_steps), reps), "step")
+        state.head, state.mu = sc.head, sc.mu
+        if not report:
+            return None
+        return [{k: getattr(r, k) for k, _ in Report._fields_} for r in reps[:n_steps]]
+
+    def step_langevin(self, state: MDState, xi, gamma, T_ion, report=True):
+        """len(xi) / (3 n_atoms) Langevin steps; xi: device float64 standard normals."""
+        import torch
+        if xi.dtype != torch.float64 or not xi.is_contiguous() or xi.numel() % (3 * self.n_atoms):
+            raise XLBOMDError("xi must be a contiguous float64 tensor of n_steps x n_atoms x 3")
+        n_steps = xi.numel() // (3 * self.n_atoms)
+        sc = state._c(self)
+        reps = (Report * max(n_steps, 1))() if report else None
+        self._check(self.lib.xlbomd_step_langevin(self.h, C.byref(sc), int(n_steps), float(gamma), float(T_ion),
+                                                  C.c_void_p(xi.data_ptr()), reps), "step_langevin")
         state.head, state.mu = sc.head, sc.mu
         if not report:
             return None

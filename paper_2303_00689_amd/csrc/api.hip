@@ -829,13 +829,16 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
   double nw0sq;
   if ((st = get_scalars(c, S_KRES + 1, 1, &nw0sq))) return st;
   if (w0_out) *w0_out = std::sqrt(nw0sq);
-  axpby(n2, 0.0, W0, 0.0, nullptr, Y, 0, s);
   if (rank_out) *rank_out = 0;
   if (rel_out) *rel_out = 0.0;
-  if (!(nw0sq > 0.0) || m == 0) {
-    if (rel_out) *rel_out = (m == 0 && nw0sq > 0.0) ? 1.0 : 0.0;
+  if (m == 0) {
+    // original XL-BOMD: the scaled-identity kernel K = -c I
+    axpby(n2, -c->prm.kernel_c, W0, 0.0, nullptr, Y, 0, s);
+    if (rel_out) *rel_out = nw0sq > 0.0 ? 1.0 : 0.0;
     return XLBOMD_OK;
   }
+  axpby(n2, 0.0, W0, 0.0, nullptr, Y, 0, s);
+  if (!(nw0sq > 0.0)) return XLBOMD_OK;
   // The basis is built without host round trips: normalisation and the
   // breakdown test run on the device (k_kscale), and the host reads the
   // residual once at the end (per direction only when tol > 0 asks for an
@@ -1017,7 +1020,8 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   if (sys->n_atoms < 1 || !sys->onecenter || (sys->n_atoms > 1 && !sys->noise55)) return XLBOMD_E_ARG;
   const double n = 4.0 * sys->n_atoms;
   if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
-  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6)
+  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6 ||
+      !(prm->kernel_c > 0.0) || !std::isfinite(prm->kernel_c))
     return XLBOMD_E_ARG;
   xlbomd_ctx *c = new xlbomd_ctx();
   c->N = sys->n_atoms;
@@ -1230,11 +1234,23 @@ xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
   return evaluate_state(c, st, e, &rank, &rel, &w0);
 }
 
-xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep) {
-  if (!c || !st || n_steps < 0) return XLBOMD_E_ARG;
+// the steps of xlbomd_step and xlbomd_step_langevin (xi == nullptr: NVE)
+static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep,
+                              double c1, double c2, const double *xi) {
   for (int k = 0; k < n_steps; ++k) {
     xlbomd_status s;
-    if ((s = xlbomd_integrate(c, st))) return s;
+    if (xi) {
+      if (!st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+      const double *Xk[7];
+      for (int j = 0; j < 7; ++j) Xk[j] = st->X + (size_t)((st->head + j) % 7) * c->n2;
+      const int nh = (st->head + 6) % 7;
+      x_verlet((int)c->n2, Xk, st->Y, c->prm.kappa, c->prm.alpha, c->prm.c, st->X + (size_t)nh * c->n2, c->s);
+      st->head = nh;
+      baoab_pre(3 * c->N, st->R, st->V, st->A, c->prm.dt, c1, c2, xi + (size_t)3 * c->N * k, c->s);
+      HIPCHK(c, hipGetLastError());
+    } else if ((s = xlbomd_integrate(c, st))) {
+      return s;
+    }
     double e[3];
     int rank = 0;
     double rel = 0, w0 = 0, S = 0.0;
@@ -1266,6 +1282,21 @@ xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlb
   }
   HIPCHK(c, hipStreamSynchronize(c->s));
   return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep) {
+  if (!c || !st || n_steps < 0) return XLBOMD_E_ARG;
+  return md_steps(c, st, n_steps, rep, 1.0, 0.0, nullptr);
+}
+
+xlbomd_status xlbomd_step_langevin(xlbomd_handle c, xlbomd_md_state *st, int n_steps, double gamma,
+                                   double T_ion, const double *xi, xlbomd_report *rep) {
+  if (!c || !st || n_steps < 0 || !(gamma >= 0.0) || !(T_ion >= 0.0) || !std::isfinite(gamma) ||
+      !std::isfinite(T_ion) || (n_steps > 0 && !xi))
+    return XLBOMD_E_ARG;
+  const double c1 = std::exp(-gamma * c->prm.dt);
+  const double c2 = std::sqrt(KB * T_ion * ACC / c->model.mass * (1.0 - c1 * c1));
+  return md_steps(c, st, n_steps, rep, c1, c2, xi);
 }
 
 xlbomd_status xlbomd_scf(xlbomd_handle c, double *X, int m, double tol, int max_iter, double *residual) {

@@ -421,6 +421,17 @@ __global__ void k_kick_drift(int n3, double *R, double *V, const double *A, doub
   if (drift) R[i] += dt * v;
 }
 
+__global__ void k_baoab_pre(int n3, double *R, double *V, const double *A, double dt, double c1, double c2,
+                            const double *xi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  double v = V[i] + 0.5 * dt * A[i];
+  double r = R[i] + 0.5 * dt * v;
+  v = c1 * v + c2 * xi[i];
+  R[i] = r + 0.5 * dt * v;
+  V[i] = v;
+}
+
 __global__ void k_accel(int n3, const double *f, double s, double *A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n3) A[i] = f[i] * s;
@@ -559,6 +570,11 @@ void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, do
 void kick_drift(int n3, double *R, double *V, const double *A, double dt, int drift,
                 hipStream_t s) {
   hipLaunchKernelGGL(k_kick_drift, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, R, V, A, dt, drift);
+}
+
+void baoab_pre(int n3, double *R, double *V, const double *A, double dt, double c1, double c2,
+               const double *xi, hipStream_t s) {
+  hipLaunchKernelGGL(k_baoab_pre, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, R, V, A, dt, c1, c2, xi);
 }
 
 void accel(int n3, const double *frc, double sc, double *A, hipStream_t s) {

@@ -94,6 +94,10 @@ void krylov_solve(int k, const double *O, const double *rhs, double *coef, doubl
 // ------------------------------------------------------------- MD kernels
 void x_verlet(int n2, const double *const *Xk, const double *Y, double kappa, double alpha,
               const double *c, double *out, hipStream_t s);
+// BAOAB (Leimkuhler-Matthews) before the force evaluation: half kick, half
+// drift, V <- c1 V + c2 xi, half drift
+void baoab_pre(int n3, double *R, double *V, const double *A, double dt, double c1, double c2,
+               const double *xi, hipStream_t s);
 void kick_drift(int n3, double *R, double *V, const double *A, double dt, int drift,
                 hipStream_t s);
 void accel(int n3, const double *frc, double inv_mass_conv, double *A, hipStream_t s);

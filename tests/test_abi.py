@@ -49,3 +49,37 @@ def test_library_loads_without_gpu(built):
     lib = binding.load()
     assert lib.xlbomd_n_orb(None) == 0
     assert lib.xlbomd_destroy(None) == -1
+
+
+# binding struct -> C struct name
+_STRUCTS = {"Model": "xlbomd_model", "System": "xlbomd_system", "Params": "xlbomd_params",
+            "MDStateC": "xlbomd_md_state", "Report": "xlbomd_report"}
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets the C
+    compiler gives the header's struct (a mismatch would pass wrong values
+    through the ABI without any error)."""
+    from paper_2303_00689_amd import binding
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "xlbomd.h"', 'int main(void) {']
+    for py, cname in _STRUCTS.items():
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(binding, py)._fields_:
+            lines.append(f'  printf("{py} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-x", "c", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        py, field, value = line.split()
+        cls = getattr(binding, py)
+        got = C_sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), (py, field, got, value)
+
+
+def C_sizeof(cls):
+    import ctypes
+    return ctypes.sizeof(cls)

@@ -170,6 +170,52 @@ def test_md_step_matches_oracle(case, lib):
     assert reps[0]["E_tot"] == pytest.approx(rep["E_tot"], rel=1e-10)
 
 
+def test_original_xlbomd_step_matches_oracle(case, lib):
+    # m = 0: the scaled-identity kernel K = -c I of the original XL-BOMD
+    s = case.sys
+    st = dynamics.Settings(T_e=case.w["T_e"], m=0, dt=case.w["dt"], kernel_c=0.9)
+    h = lib.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, T_e=st.T_e, m=0, dt=st.dt,
+                   kernel_c=0.9)
+    try:
+        o = dynamics.init_state(s, st, case.X)
+        n = s.n_orb
+        Xr = torch.zeros((7, n, n), dtype=torch.float64, device=case.dev)
+        for k in range(7):
+            Xr[k] = case.t(o.Xhist[k])
+        state = lib.MDState(R=case.t(o.R), V=case.t(o.V), A=case.t(o.A), X=Xr, Y=case.t(o.Y), head=0, mu=o.mu)
+        reps = h.step(state, 2)
+        for _ in range(2):
+            o, rep = dynamics.md_step(o, s, st)
+        assert np.abs(case.np(state.x_current()) - o.Xhist[0]).max() <= TOL * np.abs(o.Xhist[0]).max()
+        assert np.abs(case.np(state.Y) - o.Y).max() <= TOL * np.abs(o.Y).max()
+        assert reps[-1]["rank"] == 0 and reps[-1]["relres"] == 1.0
+        assert reps[-1]["E_tot"] == pytest.approx(rep["E_tot"], rel=1e-10)
+    finally:
+        h.close()
+
+
+def test_langevin_step_matches_oracle(case, lib):
+    # BAOAB on the nuclei with the same standard normals on both sides
+    s = case.sys
+    st = dynamics.Settings(T_e=case.w["T_e"], m=case.w["m"], dt=case.w["dt"])
+    o = dynamics.init_state(s, st, case.X)
+    o.V = 0.005 * case.rng.standard_normal(o.R.shape)
+    n = s.n_orb
+    Xr = torch.zeros((7, n, n), dtype=torch.float64, device=case.dev)
+    for k in range(7):
+        Xr[k] = case.t(o.Xhist[k])
+    state = lib.MDState(R=case.t(o.R), V=case.t(o.V), A=case.t(o.A), X=Xr, Y=case.t(o.Y), head=0, mu=o.mu)
+    xi = case.rng.standard_normal((2, s.n_atoms, 3))
+    reps = case.h.step_langevin(state, case.t(xi), gamma=0.05, T_ion=300.0)
+    for k in range(2):
+        o, rep = dynamics.langevin_step(o, s, st, 0.05, 300.0, xi[k])
+    assert np.abs(case.np(state.R) - o.R).max() <= 1e-12 * np.abs(o.R).max()
+    assert np.abs(case.np(state.V) - o.V).max() <= 1e-9 * np.abs(o.V).max()
+    assert np.abs(case.np(state.x_current()) - o.Xhist[0]).max() <= TOL * np.abs(o.Xhist[0]).max()
+    assert reps[-1]["KE"] == pytest.approx(rep["KE"], rel=1e-9)
+    assert reps[-1]["U"] == pytest.approx(rep["U"], rel=1e-10)
+
+
 def test_nve_energy_fluctuation_scales_as_dt_squared(lib):
     # the GPU trajectory from a converged 6-atom state: the spread of the
     # constant of motion (eq. 26) over 2 fs shrinks ~4x when dt is halved

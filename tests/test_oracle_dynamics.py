@@ -156,3 +156,92 @@ def test_scf_reaches_fixed_point():
     F = model.fock(X, sys_.R, sys_.onecenter, sys_.noise, sys_.params)
     P = density.density_matrix(F, sys_.n_elec, st.beta)["P"]
     assert np.linalg.norm(P - X) < 1e-9
+
+
+def test_original_kernel_is_scaled_identity():
+    # m = 0 is the original XL-BOMD kernel K = -c I: eq. 35's kernel term
+    # becomes -c (P0 - X).  Its sign convention is the Krylov kernel's: with
+    # a vanishing response (J = -I) the full-rank Krylov kernel J^-1 W0 is
+    # exactly the c = 1 scaled identity.
+    sys_ = carbon_cluster(4, 21)
+    rng = np.random.default_rng(21)
+    X = _start_density(sys_, rng)
+    st = dynamics.Settings(T_e=3000.0, m=0, dt=0.5, kernel_c=0.9)
+    ev = dynamics.evaluate(sys_.R, X, sys_, st)
+    W0 = ev["P0"] - X
+    np.testing.assert_array_equal(ev["Y"], -0.9 * W0)
+    assert ev["rank"] == 0 and ev["relres"] == 1.0
+    Y, rank, rel = krylov.krylov_kernel(X, ev["P0"], lambda V: -V, 3)
+    assert rank == 1 and rel < 1e-14
+    np.testing.assert_allclose(Y, -W0, rtol=0, atol=1e-14 * np.abs(W0).max())
+
+
+def test_original_xlbomd_unstable_where_ksa_is_stable():
+    # Results, low-gap fullerene test: with strong charge response the
+    # scaled-identity kernel (c = 1) lets the electronic residual grow without
+    # bound, a smaller c keeps it bounded but less tight, and the rank-3 KSA
+    # kernel stays stable and tight.  Here on the 6-atom cluster, 20 steps of
+    # 0.1 fs from the ground state.
+    import dataclasses
+    sys_ = carbon_cluster(6, 13)
+    st0 = dynamics.Settings(T_e=3000.0, m=3, dt=0.1)
+    Xmin = dynamics.scf(sys_, st0, m=30)
+    res = {}
+    for m, c in ((3, 1.0), (0, 1.0), (0, 0.5)):
+        st = dataclasses.replace(st0, m=m, kernel_c=c)
+        s = dynamics.init_state(sys_, st, Xmin)
+        E, W = [], []
+        for _ in range(20):
+            s, rep = dynamics.md_step(s, sys_, st)
+            E.append(rep["E_tot"])
+            W.append(rep["W0"])
+        res[(m, c)] = (np.ptp(E), max(W))
+    ksa, xl1, xl05 = res[(3, 1.0)], res[(0, 1.0)], res[(0, 0.5)]
+    assert ksa[0] < 1e-2 and ksa[1] < 2e-3
+    assert xl1[1] > 100 * ksa[1] and xl1[0] > 1.0
+    assert xl05[1] < 1e-2 and xl05[1] > ksa[1]
+
+
+def test_langevin_without_friction_is_the_nve_step():
+    # gamma = 0: the Ornstein-Uhlenbeck update is the identity and BAOAB's two
+    # half drifts make the leapfrog drift of md_step
+    sys_ = carbon_cluster(5, 14)
+    st = dynamics.Settings(T_e=3000.0, m=3, dt=0.2)
+    rng = np.random.default_rng(3)
+    s0 = dynamics.init_state(sys_, st, _start_density(sys_, rng))
+    s0.V = 0.01 * rng.standard_normal(s0.R.shape)
+    a, ra = dynamics.md_step(s0, sys_, st)
+    b, rb = dynamics.langevin_step(s0, sys_, st, 0.0, 300.0, rng.standard_normal(s0.R.shape))
+    np.testing.assert_allclose(b.R, a.R, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(b.V, a.V, rtol=0, atol=1e-13)
+    np.testing.assert_array_equal(b.Xhist[0], a.Xhist[0])
+    assert rb["E_tot"] == pytest.approx(ra["E_tot"], rel=1e-13)
+
+
+def test_ou_update_keeps_the_maxwell_boltzmann_variance():
+    # equipartition: (1/2) M <v^2> = (1/2) k_B T per Cartesian component, and
+    # the exact Ornstein-Uhlenbeck step maps that distribution onto itself
+    mass, T, dt = 12.011, 300.0, 0.5
+    var = density.KB_EV_PER_K * T / mass * dynamics.EV_PER_AMU_TO_A2_PER_FS2
+    rng = np.random.default_rng(11)
+    v = np.sqrt(var) * rng.standard_normal(400_000)
+    for gamma in (0.01, 0.2, 5.0):
+        c1, c2 = dynamics.ou_coefficients(gamma, T, dt, mass)
+        w = c1 * v + c2 * rng.standard_normal(v.size)
+        assert abs(w.var() / var - 1.0) < 0.012
+        assert abs(w.mean()) < 0.01 * np.sqrt(var)
+
+
+def test_langevin_thermalises_to_the_bath_temperature():
+    # a 4-atom cluster started far from equilibrium: after the transient the
+    # mean kinetic energy is (3N/2) k_B T (statistical error ~6% here)
+    sys_ = carbon_cluster(4, 31)
+    st = dynamics.Settings(T_e=3000.0, m=2, dt=0.25)
+    s = dynamics.init_state(sys_, st, dynamics.scf(sys_, st, m=20))
+    rng = np.random.default_rng(5)
+    KE = []
+    for _ in range(1600):
+        s, rep = dynamics.langevin_step(s, sys_, st, 0.1, 300.0, rng.standard_normal((sys_.n_atoms, 3)))
+        KE.append(rep["KE"])
+    ratio = np.mean(KE[400:]) / (1.5 * sys_.n_atoms * density.KB_EV_PER_K * 300.0)
+    assert abs(ratio - 1.0) < 0.15, ratio
