@@ -153,9 +153,191 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile FP64 GEMM: 128 x 128 tiles, four waves of 64 x 64 (4 x 4 blocks
+// of v_mfma_f64_16x16x4f64), two workgroups per compute unit.  Against the
+// 64 x 64 kernel the workgroup reads half the operand bytes per flop from L2.
+//
+// K advances by 16.  The panels stream into LDS by buffer loads, two stages
+// in separate LDS arrays, so the loads of panel k + 1 need no wait before the
+// reads of panel k; the one barrier per panel is where a panel's loads are
+// complete and the stage read before it is free.
+//   A panel (and B when not transposed): 16 k rows of 128 doubles, each row
+//     one 1 KB load instruction, rows padded to 1152 bytes so that the four
+//     k rows one fragment read touches fall on different banks;
+//   B transposed: 128 rows j of 16 k values (128 bytes), eight rows per load
+//     instruction, 16-byte chunk c of row j at position c ^ (j & 7) ^ ((j >> 3) & 1).
+// n % 16 == 0 is required (every k panel full); rows and columns past n are
+// read clamped and never stored.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+constexpr int FT = 128;                 // tile edge
+constexpr int FK = 16;                  // k panel
+constexpr int FROW = 144;               // doubles per padded k row (1152 bytes)
+constexpr int FSTAGE = 2 * FK * FROW;   // doubles per stage (A rows, then B rows): 36 KB
+constexpr int F_GROUP = 4;              // tile rows per L2-sharing group
+constexpr int F_BUF_WORD3 = 0x00020000;  // raw buffer descriptor word 3
+
+__device__ inline int swz8(int r, int c) { return c ^ (r & 7) ^ ((r >> 3) & 1); }
+
+template <int BTRANS>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
+  const int n = p.n;
+  int bi, bj;
+  tile_of(blockIdx.x, T, p.sym, F_GROUP, bi, bj);
+  const int i0 = bi * FT, j0 = bj * FT;
+  __shared__ double sa[FSTAGE];
+  __shared__ double sb[FSTAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int kt_per = n / FK;
+  const int ktiles = kt_per * p.nprod;
+  const int nbytes = (int)(8u * (unsigned)n * (unsigned)n);  // buffer range (n <= 23170)
+
+  // Loads.  A (and normal B): wave w loads k rows 4 w .. 4 w + 3 of A and of
+  // B, lane -> 16 bytes at column 2 lane of the tile (clamped to n - 2).
+  // Transposed B: wave w loads tile rows j = 32 w .. 32 w + 31, eight per
+  // instruction, lane -> row lane / 8, physical chunk lane % 8.
+  int colA = i0 + 2 * lane;
+  colA = colA < n ? colA : n - 2;
+  int colB = j0 + 2 * lane;
+  colB = colB < n ? colB : n - 2;
+  const int lr = lane >> 3, lpc = lane & 7;
+  unsigned toff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int j = j0 + 32 * wave + 8 * q + lr;
+    j = j < n ? j : n - 1;
+    // stage row 32 w + 8 q + lr: logical chunk lpc ^ lr ^ (q & 1) (2 doubles)
+    toff[q] = 8u * ((unsigned)j * (unsigned)n + 2u * (unsigned)(lpc ^ lr ^ (q & 1)));
+  }
+  auto issue = [&](int kt, double *st) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * FK;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p.A[prod]), (short)0, nbytes, F_BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p.B[prod]), (short)0, nbytes, F_BUF_WORD3);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + 4 * wave + q;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t *)&st[(4 * wave + q) * FROW], 16,
+                                               8u * ((unsigned)k * (unsigned)n + (unsigned)colA), 0, 0, 0);
+    }
+    if (!BTRANS) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 4 * wave + q;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[(FK + 4 * wave + q) * FROW], 16,
+                                                 8u * ((unsigned)k * (unsigned)n + (unsigned)colB), 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[FK * FROW + (32 * wave + 8 * q) * 16], 16,
+                                                 toff[q], 8u * (unsigned)k0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  const int fl = lane & 15, fk = lane >> 4;
+  // fragments of k step kk: A[kk + fk][wm + 16 r + fl], B[kk + fk][wn + 16 c + fl]
+  auto frags = [&](const double *st, int kk, double (&a)[4], double (&b)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = st[(kk + fk) * FROW + wm + 16 * r + fl];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (!BTRANS) {
+        b[c] = st[(FK + kk + fk) * FROW + wn + 16 * c + fl];
+      } else {
+        const int j = wn + 16 * c + fl, k = kk + fk;
+        b[c] = st[FK * FROW + j * 16 + 2 * swz8(j, k >> 1) + (k & 1)];
+      }
+    }
+  };
+  auto panel = [&](const double *st) {
+    double a[4], b[4];
+    frags(st, 0, a, b);
+#pragma unroll
+    for (int kk = 0; kk < FK; kk += 4) {
+      double an[4], bn[4];
+      if (kk + 4 < FK) frags(st, kk + 4, an, bn);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+      if (kk + 4 < FK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = an[q];
+          b[q] = bn[q];
+        }
+      }
+    }
+  };
+
+  // Panel kt + 1 loads into one stage while panel kt is read from the other.
+  // At the top of each panel: this wave's loads of panel kt are complete once
+  // vmcnt drains (the compiler does not wait for them by itself), and the
+  // barrier makes every wave's part visible and frees the stage of panel
+  // kt - 1 for the loads of panel kt + 1.
+  issue(0, sa);
+  for (int kt = 0; kt < ktiles; ++kt) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (kt + 1 < ktiles) issue(kt + 1, (kt & 1) ? sa : sb);
+    panel((kt & 1) ? sb : sa);
+  }
+
+  const double *C1 = (const double *)p.C1;
+  const double *C2 = (const double *)p.C2;
+  double *out = (double *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + wn + c * 16 + fl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wm + r * 16 + fk + 4 * q;
+        if (i < n && j < n) {
+          const size_t off = (size_t)i * n + j;
+          double x = p.alpha * acc[r][c][q];
+          if (C1) x += p.beta1 * C1[off];
+          if (C2) x += p.beta2 * C2[off];
+          if (i == j) x += p.gamma;
+          out[off] = x;
+          if (mirror) out[(size_t)j * n + i] = x;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void gemm_f64(const GemmArgs &a, hipStream_t s) {
+  // 128-row tiles from n = 1024 on (n % 16 == 0; the buffer range limits n to 23170)
+  if (a.n % 16 == 0 && a.n >= 1024 && a.n <= 23170) {
+    const int T = (a.n + FT - 1) / FT;
+    const int blocks = tile_count(T, a.sym);
+    if (a.btrans)
+      hipLaunchKernelGGL(k_gemm_f64_big<1>, dim3(blocks), dim3(256), 0, s, a, T);
+    else
+      hipLaunchKernelGGL(k_gemm_f64_big<0>, dim3(blocks), dim3(256), 0, s, a, T);
+    return;
+  }
   const int T = (a.n + BM - 1) / BM;
   const int blocks = a.sym ? T * (T + 1) / 2 : T * T;
   hipLaunchKernelGGL(k_gemm_f64, dim3(blocks), dim3(256), 0, s, a, T);
