@@ -180,45 +180,59 @@ constexpr int F_BUF_WORD3 = 0x00020000;  // raw buffer descriptor word 3
 
 __device__ inline int swz8(int r, int c) { return c ^ (r & 7) ^ ((r >> 3) & 1); }
 
-template <int BTRANS>
-__global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
+// TN = 128: square tiles (tile_of; symmetric outputs mirror off-diagonal
+// tiles).  TN = 64: 128 x 64 tiles for symmetric outputs, enumerated by
+// tile_of_rect_sym; each entry with j >= i is written and, for j > i,
+// mirrored, so every entry is written once.  TI, TJ: tile rows, columns.
+template <int BTRANS, int TN>
+__device__ __forceinline__ void gemm_f64_big_body(GemmArgs p, int TI, int TJ) {
+  constexpr int WNC = TN / 2;   // wave tile columns
+  constexpr int NCB = WNC / 16;  // 16-column blocks per wave
   const int n = p.n;
   int bi, bj;
-  tile_of(blockIdx.x, T, p.sym, F_GROUP, bi, bj);
-  const int i0 = bi * FT, j0 = bj * FT;
+  if (TN == FT)
+    tile_of(blockIdx.x, TI, p.sym, F_GROUP, bi, bj);
+  else
+    tile_of_rect_sym(blockIdx.x, TI, TJ, bi, bj);
+  const int i0 = bi * FT, j0 = bj * TN;
   __shared__ double sa[FSTAGE];
   __shared__ double sb[FSTAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * WNC;
 
-  d4 acc[4][4];
+  d4 acc[4][NCB];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NCB; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int kt_per = n / FK;
   const int ktiles = kt_per * p.nprod;
   const int nbytes = (int)(8u * (unsigned)n * (unsigned)n);  // buffer range (n <= 23170)
 
-  // Loads.  A (and normal B): wave w loads k rows 4 w .. 4 w + 3 of A and of
-  // B, lane -> 16 bytes at column 2 lane of the tile (clamped to n - 2).
-  // Transposed B: wave w loads tile rows j = 32 w .. 32 w + 31, eight per
+  // Loads.  A (and normal B when TN = 128): wave w loads k rows 4 w .. 4 w + 3,
+  // lane -> 16 bytes at column 2 lane of the tile (clamped to n - 2).
+  // Normal B when TN = 64: 64-double k rows, two per instruction (wave w:
+  // rows 4 w .. 4 w + 3), lane -> row lane / 32 of the pair, physical 16-byte
+  // chunk lane % 32, which holds logical chunk (lane % 32) ^ (8 (row & 1)).
+  // Transposed B: wave w loads tile rows j = (TN / 4) w .., eight per
   // instruction, lane -> row lane / 8, physical chunk lane % 8.
   int colA = i0 + 2 * lane;
   colA = colA < n ? colA : n - 2;
   int colB = j0 + 2 * lane;
+  if (TN == 64) colB = j0 + 2 * ((lane & 31) ^ (8 * ((lane >> 5) & 1)));
   colB = colB < n ? colB : n - 2;
   const int lr = lane >> 3, lpc = lane & 7;
-  unsigned toff[4];
+  constexpr int TQ = TN / 32;  // transposed-B load instructions per wave
+  unsigned toff[TQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int j = j0 + 32 * wave + 8 * q + lr;
+  for (int q = 0; q < TQ; ++q) {
+    int j = j0 + (TN / 4) * wave + 8 * q + lr;
     j = j < n ? j : n - 1;
-    // stage row 32 w + 8 q + lr: logical chunk lpc ^ lr ^ (q & 1) (2 doubles)
+    // stage row (TN / 4) w + 8 q + lr: logical chunk lpc ^ lr ^ (q & 1) (2 doubles)
     toff[q] = 8u * ((unsigned)j * (unsigned)n + 2u * (unsigned)(lpc ^ lr ^ (q & 1)));
   }
   auto issue = [&](int kt, double *st) {
@@ -234,31 +248,41 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t *)&st[(4 * wave + q) * FROW], 16,
                                                8u * ((unsigned)k * (unsigned)n + (unsigned)colA), 0, 0, 0);
     }
-    if (!BTRANS) {
+    if (!BTRANS && TN == FT) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + 4 * wave + q;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[(FK + 4 * wave + q) * FROW], 16,
                                                  8u * ((unsigned)k * (unsigned)n + (unsigned)colB), 0, 0, 0);
       }
+    } else if (!BTRANS) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = k0 + 4 * wave + 2 * q + (lane >> 5);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[FK * FROW + (4 * wave + 2 * q) * 64], 16,
+                                                 8u * ((unsigned)k * (unsigned)n + (unsigned)colB), 0, 0, 0);
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[FK * FROW + (32 * wave + 8 * q) * 16], 16,
-                                                 toff[q], 8u * (unsigned)k0, 0, 0);
+      for (int q = 0; q < TQ; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)&st[FK * FROW + ((TN / 4) * wave + 8 * q) * 16],
+                                                 16, toff[q], 8u * (unsigned)k0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
 
   const int fl = lane & 15, fk = lane >> 4;
   // fragments of k step kk: A[kk + fk][wm + 16 r + fl], B[kk + fk][wn + 16 c + fl]
-  auto frags = [&](const double *st, int kk, double (&a)[4], double (&b)[4]) {
+  auto frags = [&](const double *st, int kk, double (&a)[4], double (&b)[NCB]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) a[r] = st[(kk + fk) * FROW + wm + 16 * r + fl];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (!BTRANS) {
+    for (int c = 0; c < NCB; ++c) {
+      if (!BTRANS && TN == FT) {
         b[c] = st[(FK + kk + fk) * FROW + wn + 16 * c + fl];
+      } else if (!BTRANS) {
+        const int row = kk + fk, col = wn + 16 * c + fl;
+        b[c] = st[FK * FROW + row * 64 + 2 * ((col >> 1) ^ (8 * (row & 1))) + (col & 1)];
       } else {
         const int j = wn + 16 * c + fl, k = kk + fk;
         b[c] = st[FK * FROW + j * 16 + 2 * swz8(j, k >> 1) + (k & 1)];
@@ -266,22 +290,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
     }
   };
   auto panel = [&](const double *st) {
-    double a[4], b[4];
+    double a[4], b[NCB];
     frags(st, 0, a, b);
 #pragma unroll
     for (int kk = 0; kk < FK; kk += 4) {
-      double an[4], bn[4];
+      double an[4], bn[NCB];
       if (kk + 4 < FK) frags(st, kk + 4, an, bn);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
+        for (int c = 0; c < NCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], b[c], acc[r][c], 0, 0, 0);
       if (kk + 4 < FK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = an[q];
-          b[q] = bn[q];
-        }
+        for (int q = 0; q < 4; ++q) a[q] = an[q];
+#pragma unroll
+        for (int q = 0; q < NCB; ++q) b[q] = bn[q];
       }
     }
   };
@@ -306,23 +330,28 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCB; ++c) {
       const int j = j0 + wn + c * 16 + fl;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wm + r * 16 + fk + 4 * q;
-        if (i < n && j < n) {
+        if (i < n && j < n && (TN == FT || j >= i)) {
           const size_t off = (size_t)i * n + j;
           double x = p.alpha * acc[r][c][q];
           if (C1) x += p.beta1 * C1[off];
           if (C2) x += p.beta2 * C2[off];
           if (i == j) x += p.gamma;
           out[off] = x;
-          if (mirror) out[(size_t)j * n + i] = x;
+          if (TN == FT ? mirror : j > i) out[(size_t)j * n + i] = x;
         }
       }
     }
   }
+}
+
+template <int BTRANS, int TN>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int TI, int TJ) {
+  gemm_f64_big_body<BTRANS, TN>(p, TI, TJ);
 }
 
 }  // namespace
@@ -330,12 +359,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int T) {
 void gemm_f64(const GemmArgs &a, hipStream_t s) {
   // 128-row tiles from n = 1024 on (n % 16 == 0; the buffer range limits n to 23170)
   if (a.n % 16 == 0 && a.n >= 1024 && a.n <= 23170) {
-    const int T = (a.n + FT - 1) / FT;
-    const int blocks = tile_count(T, a.sym);
-    if (a.btrans)
-      hipLaunchKernelGGL(k_gemm_f64_big<1>, dim3(blocks), dim3(256), 0, s, a, T);
-    else
-      hipLaunchKernelGGL(k_gemm_f64_big<0>, dim3(blocks), dim3(256), 0, s, a, T);
+    const int TI = (a.n + FT - 1) / FT;
+    if (a.sym) {
+      // symmetric outputs: 128 x 64 tiles, twice as many for an even load over the CUs
+      const int TJ = (a.n + 63) / 64;
+      const int blocks = tile_count_rect_sym(TI, TJ);
+      if (a.btrans)
+        hipLaunchKernelGGL((k_gemm_f64_big<1, 64>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
+      else
+        hipLaunchKernelGGL((k_gemm_f64_big<0, 64>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
+    } else {
+      const int blocks = tile_count(TI, 0);
+      if (a.btrans)
+        hipLaunchKernelGGL((k_gemm_f64_big<1, 128>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
+      else
+        hipLaunchKernelGGL((k_gemm_f64_big<0, 128>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
+    }
     return;
   }
   const int T = (a.n + BM - 1) / BM;

@@ -52,4 +52,31 @@ __host__ __device__ inline void tile_of(int w, int T, int sym, int G, int &bi, i
   }
 }
 
+// Symmetric outputs on rectangular tiles of 2h x h (TI tile rows of 2h, TJ
+// tile columns of h): tile (I, J) holds entries with j >= i exactly when
+// J >= 2 I, so those are the tiles enumerated, row by row, after the same
+// XCD-contiguous remap as tile_of.
+__host__ __device__ inline int tile_count_rect_sym(int TI, int TJ) {
+  int c = 0;
+  for (int I = 0; I < TI; ++I) c += TJ - 2 * I > 0 ? TJ - 2 * I : 0;
+  return c;
+}
+
+__host__ __device__ inline void tile_of_rect_sym(int w, int TI, int TJ, int &bi, int &bj) {
+  const int B = tile_count_rect_sym(TI, TJ);
+  const int q = B / NXCD, r = B % NXCD;
+  const int x = w % NXCD, k = w / NXCD;
+  int l = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+  for (int I = 0; I < TI; ++I) {
+    const int cnt = TJ - 2 * I > 0 ? TJ - 2 * I : 0;
+    if (l < cnt) {
+      bi = I;
+      bj = 2 * I + l;
+      return;
+    }
+    l -= cnt;
+  }
+  bi = bj = 0;  // not reached for w < tile_count_rect_sym
+}
+
 }  // namespace xl
