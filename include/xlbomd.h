@@ -219,6 +219,19 @@ xlbomd_status xlbomd_step(xlbomd_handle h, xlbomd_md_state *st, int n_steps,
 xlbomd_status xlbomd_step_langevin(xlbomd_handle h, xlbomd_md_state *st, int n_steps, double gamma,
                                    double T_ion, const double *xi, xlbomd_report *rep);
 
+/* Steps of an ensemble of independent trajectories (systems of uneven
+ * sizes): member i advances h[i] with st[i] by n_steps exactly as
+ * xlbomd_step does, and the members run concurrently, each from a host
+ * thread of its own (at most 16 threads) on its handle's stream.  Create the
+ * handles on distinct streams so that their GPU work overlaps.
+ *   h, st   host arrays of count distinct handles and their states
+ *   rep     host, count x n_steps reports, member-major (nullable)
+ * Returns XLBOMD_E_ARG for a repeated handle; otherwise the status of the
+ * first failing member (its message in that handle's last_error), after
+ * every member has run. */
+xlbomd_status xlbomd_ensemble_step(xlbomd_handle *h, xlbomd_md_state *st, int count, int n_steps,
+                                   xlbomd_report *rep);
+
 /* Initial state for xlbomd_step: evaluates P0, Y and the accelerations at
  * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5). */
 xlbomd_status xlbomd_md_init(xlbomd_handle h, xlbomd_md_state *st);

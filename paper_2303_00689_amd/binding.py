@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
 SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
            "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm",
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
-           "xlbomd_step", "xlbomd_step_langevin", "xlbomd_md_init", "xlbomd_scf", "xlbomd_matmul",
+           "xlbomd_step", "xlbomd_step_langevin", "xlbomd_ensemble_step", "xlbomd_md_init", "xlbomd_scf",
+           "xlbomd_matmul",
            "xlbomd_profile", "xlbomd_profile_read"]
 
 
@@ -89,6 +90,7 @@ def load():
     lib.xlbomd_integrate.argtypes = [vp, C.POINTER(MDStateC)]
     lib.xlbomd_step.argtypes = [vp, C.POINTER(MDStateC), i, C.POINTER(Report)]
     lib.xlbomd_step_langevin.argtypes = [vp, C.POINTER(MDStateC), i, d, d, vp, C.POINTER(Report)]
+    lib.xlbomd_ensemble_step.argtypes = [C.POINTER(vp), C.POINTER(MDStateC), i, i, C.POINTER(Report)]
     lib.xlbomd_md_init.argtypes = [vp, C.POINTER(MDStateC)]
     lib.xlbomd_scf.argtypes = [vp, vp, i, d, i, pd]
     lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
@@ -282,6 +284,31 @@ class Handle:
         if not (allow_noconv and st == -3):
             self._check(st, "scf")
         return res.value
+
+
+def ensemble_step(handles, states, n_steps=1, report=True):
+    """Advance every (handle, state) pair by n_steps concurrently
+    (xlbomd_ensemble_step); returns one list of reports per member."""
+    count = len(handles)
+    if len(states) != count:
+        raise XLBOMDError("one state per handle")
+    if count == 0:
+        return []
+    lib = handles[0].lib
+    hs = (C.c_void_p * count)(*[h.h for h in handles])
+    scs = (MDStateC * count)(*[s._c(h) for h, s in zip(handles, states)])
+    reps = (Report * max(count * n_steps, 1))() if report else None
+    st = lib.xlbomd_ensemble_step(hs, scs, int(count), int(n_steps), reps)
+    for k, (h, s) in enumerate(zip(handles, states)):
+        s.head, s.mu = scs[k].head, scs[k].mu
+    if st != 0:
+        msgs = "; ".join(f"member {k}: {h.lib.xlbomd_last_error(h.h).decode()}" for k, h in enumerate(handles)
+                         if h.lib.xlbomd_last_error(h.h))
+        raise XLBOMDError(f"ensemble_step failed: {STATUS.get(st, st)} ({msgs})")
+    if not report:
+        return None
+    return [[{k: getattr(reps[m * n_steps + j], k) for k, _ in Report._fields_} for j in range(n_steps)]
+            for m in range(count)]
 
 
 def handle_for(system, settings: dict, prec="fp64", stream=None) -> Handle:

@@ -2,11 +2,13 @@
 // hot path.  Every arithmetic step runs in the kernels of gemm_*.hip,
 // blas1.hip and pairs.hip; this file only sequences them, keeps the chain
 // cache and moves a few scalars between host and device.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include <hipsolver/hipsolver.h>
@@ -179,6 +181,7 @@ struct xlbomd_ctx {
   xlbomd_params prm{};
   xlbomd_model model{};
   hipStream_t s = nullptr;
+  int device = 0;               // the device current at create
   int prec = 0;                 // precision as requested at create
   int prec_dm = 0, prec_rs = 0; // Fermi chain + mu shift / response chains
   int is32 = 0, rs32 = 0;       // FP32 storage of the Fermi-chain / response-chain matrices
@@ -1032,6 +1035,10 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   c->prm = *prm;
   c->model = sys->model;
   c->s = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return XLBOMD_E_HIP;
+  }
   c->beta = 1.0 / (KB * prm->T_e);
   c->prec = prm->prec;
   split_prec(prm->prec, c->prec_dm, c->prec_rs);
@@ -1287,6 +1294,37 @@ static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, x
 xlbomd_status xlbomd_step(xlbomd_handle c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep) {
   if (!c || !st || n_steps < 0) return XLBOMD_E_ARG;
   return md_steps(c, st, n_steps, rep, 1.0, 0.0, nullptr);
+}
+
+xlbomd_status xlbomd_ensemble_step(xlbomd_handle *h, xlbomd_md_state *st, int count, int n_steps,
+                                   xlbomd_report *rep) {
+  if (!h || !st || count < 0 || n_steps < 0) return XLBOMD_E_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!h[i]) return XLBOMD_E_ARG;
+    for (int j = 0; j < i; ++j)
+      if (h[j] == h[i]) return XLBOMD_E_ARG;  // a handle's workspace serves one member
+  }
+  // members are taken in index order by up to 16 host threads; each runs
+  // xlbomd_step on its own handle (and so its own stream and workspace)
+  std::vector<xlbomd_status> status(count, XLBOMD_OK);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    for (int i = next++; i < count; i = next++) {
+      if (hipSetDevice(h[i]->device) != hipSuccess) {
+        status[i] = XLBOMD_E_HIP;
+        continue;
+      }
+      status[i] = xlbomd_step(h[i], &st[i], n_steps, rep ? rep + (size_t)i * n_steps : nullptr);
+    }
+  };
+  const int nt = std::min(count, 16);
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  if (nt > 0) worker();
+  for (auto &t : pool) t.join();
+  for (int i = 0; i < count; ++i)
+    if (status[i] != XLBOMD_OK) return status[i];
+  return XLBOMD_OK;
 }
 
 xlbomd_status xlbomd_step_langevin(xlbomd_handle c, xlbomd_md_state *st, int n_steps, double gamma,

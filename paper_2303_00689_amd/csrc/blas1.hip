@@ -155,18 +155,34 @@ struct PtrPack {
   const void *y[MAXK];
 };
 
+// All k dot products in one pass over the elements.  Pairs that repeat the
+// previous pair's x (or y) matrix reuse the loaded value, so a matrix shared
+// by consecutive pairs (the new direction in Gram-Schmidt, W_k in a row of
+// the overlap matrix) is read once.  Each thread sums its elements in the
+// same order as a pass per pair would.
 template <typename T>
 __global__ __launch_bounds__(256) void k_dots_partial(size_t n2, int k, PtrPack pp, double *part) {
   __shared__ double sh[4];
-  for (int a = 0; a < k; ++a) {
-    double v = 0.0;
-    const T *x = (const T *)pp.x[a];
-    const T *y = (const T *)pp.y[a];
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
-         i += (size_t)gridDim.x * blockDim.x)
-      v += (double)x[i] * (double)y[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) part[(size_t)a * gridDim.x + blockIdx.x] = v;
+  double v[MAXK];
+#pragma unroll
+  for (int a = 0; a < MAXK; ++a) v[a] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x) {
+    double xv = 0.0, yv = 0.0;
+#pragma unroll
+    for (int a = 0; a < MAXK; ++a) {
+      if (a < k) {
+        if (a == 0 || pp.x[a] != pp.x[a - 1]) xv = (double)((const T *)pp.x[a])[i];
+        if (a == 0 || pp.y[a] != pp.y[a - 1]) yv = (double)((const T *)pp.y[a])[i];
+        v[a] += xv * yv;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < MAXK; ++a) {
+    if (a < k) {
+      const double t = block_sum(v[a], sh);
+      if (threadIdx.x == 0) part[(size_t)a * gridDim.x + blockIdx.x] = t;
+    }
   }
 }
 

@@ -1,5 +1,7 @@
 """Parity at the full 840-atom size (n = 3360), through the C ABI, in the
-launch configuration the benchmark times.
+launch configuration the benchmark times: the benchmark cluster (5000 K,
+rank 6) and the low-gap cluster (hopping x0.6, s-p split 4 eV, 10000 K,
+rank 8).
 
 The FP64 oracle handles this size in seconds per call (one eigendecomposition
 of a 3360 x 3360 matrix, dense pair loops), so every element is compared, not
@@ -25,10 +27,10 @@ def _rel(a, b):
 
 
 class Ref:
-    """Oracle results at one seeded state of the 840-atom cluster."""
+    """Oracle results at one seeded state of an 840-atom cluster."""
 
-    def __init__(self):
-        s, w = workload("c840")
+    def __init__(self, name="c840"):
+        s, w = workload(name)
         self.sys, self.w = s, w
         self.beta = density.beta_of(w["T_e"])
         n = s.n_orb
@@ -44,9 +46,9 @@ class Ref:
         self.frc = dynamics.forces(s.R, self.dm["P"], self.X, s.params, s.noise)
 
 
-@pytest.fixture(scope="module")
-def ref():
-    return Ref()
+@pytest.fixture(scope="module", params=["c840", "c840_lowgap"])
+def ref(request):
+    return Ref(request.param)
 
 
 @pytest.fixture(scope="module")
@@ -82,18 +84,19 @@ def _run(binding, ref, prec):
 def test_fp64_step_parts_match_oracle(binding, ref):
     out = _run(binding, ref, "fp64")
     errs = {k: _rel(out[k], r) for k, r in (("F", ref.F), ("P", ref.dm["P"]), ("P1", ref.P1), ("frc", ref.frc))}
-    print("c840 fp64 relative errors:", {k: f"{v:.2e}" for k, v in errs.items()})
+    print(f"T_e {ref.w['T_e']} fp64 relative errors:", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= TOL, (k, v)
     assert abs(np.trace(out["P"]) - ref.sys.n_elec) <= 1e-11 * ref.sys.n_elec
 
 
-def test_mixed_precision_forces_meet_target(binding, ref):
-    out = _run(binding, ref, "dm64_bf16x3")
+@pytest.mark.parametrize("prec", ["dm64_bf16x3", "dm64_fp16x3"])
+def test_mixed_precision_forces_meet_target(binding, ref, prec):
+    out = _run(binding, ref, prec)
     ferr = float(np.abs(out["frc"] - ref.frc).max())
     perr = _rel(out["P"], ref.dm["P"])
     p1err = _rel(out["P1"], ref.P1)
-    print(f"c840 dm64_bf16x3: P {perr:.2e}  P1 {p1err:.2e}  forces {ferr:.2e} eV/A")
+    print(f"{ref.w['n_atoms']} atoms, T_e {ref.w['T_e']}: {prec}: P {perr:.2e}  P1 {p1err:.2e}  forces {ferr:.2e} eV/A")
     assert perr <= TOL
     assert ferr <= 1e-4
     assert p1err <= 1e-2
