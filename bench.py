@@ -101,6 +101,71 @@ def kernel_traffic(kclass):
     return rec["hbm_bytes_per_launch"]
 
 
+def run_ensemble(args, binding, torch, dev):
+    """Batch steps/s of a ragged ensemble: member i is the cluster of
+    ensemble_sizes()[i] atoms from seed 4000 + i, on a stream of its own;
+    every timed step restarts each member from its prepared state."""
+    from synth import carbon_cluster, ensemble_sizes
+    sizes = ensemble_sizes(args.ensemble)
+    w = {"T_e": 3000.0, "m": 4, "dt": 0.5}
+    t = time.perf_counter()
+    hs, states, snaps, streams = [], [], [], []
+    for i, na in enumerate(sizes):
+        sys_ = carbon_cluster(int(na), 4000 + i)
+        n = sys_.n_orb
+        R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
+        hi = binding.handle_for(sys_, w, prec="fp16x3")
+        hi.set_geometry(R0)
+        X0 = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
+        hi.scf(X0, m=8, tol=1e-12, max_iter=0, allow_noconv=True)   # 50 mixing steps
+        hi.close()
+        strm = torch.cuda.Stream()
+        h = binding.Handle(sys_.n_atoms, sys_.n_elec, sys_.onecenter, sys_.noise, sys_.params, prec=args.prec,
+                           T_e=w["T_e"], m=w["m"], dt=w["dt"], stream=strm.cuda_stream)
+        st = make_state(binding, torch, sys_, X0, dev)
+        torch.cuda.synchronize()
+        h.md_init(st)
+        torch.cuda.synchronize()
+        hs.append(h)
+        states.append(st)
+        streams.append(strm)
+        snaps.append((st.R.clone(), st.V.clone(), st.A.clone(), st.X.clone(), st.Y.clone(), st.head, st.mu))
+    log(f"ensemble of {len(hs)} prepared ({time.perf_counter() - t:.1f} s)")
+
+    def restore():
+        for st, sn in zip(states, snaps):
+            for dst, src in zip((st.R, st.V, st.A, st.X, st.Y), sn[:5]):
+                dst.copy_(src)
+            st.head, st.mu = sn[5], sn[6]
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        tot = 0.0
+        for k in range(args.warmup + args.steps):
+            restore()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                tot += time.perf_counter() - t0
+        return tot / args.steps
+
+    t_ens = timed(lambda: binding.ensemble_step(hs, states, 1, report=False))
+    log("ensemble steps done")
+    t_seq = timed(lambda: [h.step(st, 1, report=False) for h, st in zip(hs, states)])
+    log("sequential steps done")
+    for h in hs:
+        h.close()
+    print(json.dumps({
+        "metric": "ensemble batch steps/s (ragged carbon clusters, one step of every member per batch step)",
+        "value": 1.0 / t_ens, "unit": "batch steps/s", "ms_per_batch_step": 1e3 * t_ens,
+        "sequential_ms_per_batch_step": 1e3 * t_seq, "members": len(hs),
+        "atoms": int(sum(sizes)), "sizes": [int(x) for x in sizes], "dtype": DTYPE[args.prec],
+        "config": {"workload": f"{len(hs)} clusters of 20-300 atoms (seed 4000 + i), T_e 3000 K, rank 4, "
+                               f"dt 0.5 fs", "precision": args.prec},
+        "steps": args.steps, "warmup": args.warmup, "data": "synthetic"}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +180,10 @@ def main():
     ap.add_argument("--trajectory", choices=["reset", "free"], default="reset",
                     help="reset: every step starts from the prepared MD state (default); "
                          "free: one continuous NVE trajectory")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="instead: the ragged ensemble of this many clusters (20-300 atoms, 3000 K, "
+                         "rank 4) through xlbomd_ensemble_step, against the same members stepped one "
+                         "after another")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -140,6 +209,9 @@ def main():
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_bytes, "launches": 5}))
+        return
+    if args.ensemble:
+        run_ensemble(args, binding, torch, dev)
         return
     sys_, w = workload(args.workload)
     n = sys_.n_orb
