@@ -200,11 +200,12 @@ struct xlbomd_ctx {
   void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr, *S2st = nullptr, *Bst = nullptr;
   void *D = nullptr, *M = nullptr, *Qs = nullptr;
   // response-precision copies of the cached chain (alias the above when the
-  // two chains share a precision)
-  void *Yr[LMAX + 1] = {}, *Zr[LMAX] = {};
-  void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *S2r = nullptr, *Br = nullptr, *Mr = nullptr,
-       *Qr = nullptr;
+  // two chains share a precision), made on the first response after a chain
+  void *Yr[LMAX] = {};
+  void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *S2r = nullptr, *Br = nullptr, *Mr = nullptr;
+  void *Wr = nullptr;  // W = 2^(L/2) Qs prod_i Z_i, response precision
   bool resp_copy = false;
+  bool resp_ready = false;
   void *w[8] = {};
   int L = 0;
   int mu_passes = 0;
@@ -448,6 +449,7 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
 // polynomial of T = I + 4 Y^2 on its spectral interval.
 xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, double hi) {
   const int n = c->n;
+  c->resp_ready = false;
   const double beta = c->beta;
   const double rho = beta * std::max(hi - mu, mu - lo) / 2.0;
   int L = (int)std::ceil(std::log2(std::max(rho / VMAX, 1.0)));
@@ -548,6 +550,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
 // Returns XLBOMD_E_NOCONV (without changing mu) if the passes run out.
 xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   const int n = c->n, i32 = c->is32;
+  c->resp_ready = false;
   hipStream_t s = c->s;
   xlbomd_status st;
   void *D = c->D, *D2 = c->w[0], *D3 = c->w[1], *Mx = c->w[2], *Nx = c->w[3], *N2 = c->w[4],
@@ -669,17 +672,55 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   return XLBOMD_OK;
 }
 
+// Response-side factors of the cached chain, made once per chain on its first
+// response.  In the eigenbasis of F, level i of the tanh-doubling recursion maps
+// a response entry (a, b) by the divided difference of y -> 2y / (1 + 4y^2):
+//   2 z_a z_b (1 - 4 y_a y_b),   z = 1 / (1 + 4 y^2),  y = eigenvalues of Y_i,
+// and the chemical-potential shift D Q^-1 maps it by qs_a qs_b (qs the
+// eigenvalues of Qs).  These are Hadamard factors, so they commute: the z-parts
+// and qs collect into W = 2^(L/2) Qs Z_0 ... Z_(L-1) (L products, once per chain)
+// and each level keeps only K -> K - 4 Y_i K Y_i (two products per response).
+void prepare_response(xlbomd_ctx *c) {
+  const int n2 = (int)c->n2, L = c->L;
+  hipStream_t s = c->s;
+  const void *Q = c->Qs;
+  if (c->resp_copy) {
+    for (int i = 0; i < L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, s);
+    convert(n2, c->Vst, c->is32, c->Vr, 1, s);
+    convert(n2, c->Pst, c->is32, c->Pr, 1, s);
+    convert(n2, c->Sst, c->is32, c->Sr, 1, s);
+    convert(n2, c->S2st, c->is32, c->S2r, 1, s);
+    convert(n2, c->Bst, c->is32, c->Br, 1, s);
+    convert(n2, c->M, c->is32, c->Mr, 1, s);
+    convert(n2, c->Qs, c->is32, c->w[0], 1, s);
+    Q = c->w[0];
+  }
+  // W <- sqrt(2) Z_i W for i < L (commuting symmetric factors: symmetric products)
+  const void *Wa = Q;
+  for (int i = 0; i < L; ++i) {
+    const void *Zi = c->Zc[i];
+    if (c->resp_copy) {
+      convert(n2, c->Zc[i], c->is32, c->w[1], 1, s);
+      Zi = c->w[1];
+    }
+    void *dst = i == L - 1 ? c->Wr : (Wa == c->w[2] ? c->w[3] : c->w[2]);
+    mr(c, Zi, Wa, dst, std::sqrt(2.0), 1);
+    Wa = dst;
+  }
+  c->resp_ready = true;
+}
+
 // canonical response of the cached chain to F1 (FP64, spin-summed F1): P1 = 2 D1
 xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   const int n = c->n, i32 = c->rs32, L = c->L;
   hipStream_t s = c->s;
   // the Fermi-chain cache itself, or its response-precision copy
+  if (!c->resp_ready) prepare_response(c);
   const bool cp = c->resp_copy;
   void *const *Yr = cp ? c->Yr : c->Yc;
-  void *const *Zr = cp ? c->Zr : c->Zc;
   void *Vr = cp ? c->Vr : c->Vst, *Pr = cp ? c->Pr : c->Pst, *Sr = cp ? c->Sr : c->Sst;
   void *S2r = cp ? c->S2r : c->S2st, *Br = cp ? c->Br : c->Bst;
-  void *Mr = cp ? c->Mr : c->M, *Qr = cp ? c->Qr : c->Qs;
+  void *Mr = cp ? c->Mr : c->M, *Wr = c->Wr;
   const double sc = -c->beta / std::ldexp(1.0, L + 1);
   void *V1 = c->w[0], *dS = c->w[1], *dS2 = c->w[2], *Y1 = c->w[3], *G = c->w[4], *H = c->w[5],
        *Y1b = c->w[6];
@@ -696,19 +737,16 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   // dP = c1 dS + dS2 B + S2 dB (symmetric as a sum: S2 B = B S2)
   mr(c, dS2, Br, dP, 1.0, 1, dS, TC1, nullptr, 0.0, 0.0, 0, S2r, dB);
   mr(c, V1, Pr, Y1, 0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Vr, dP);          // (V1 P + V dP)/2
-  // level i: Y1 <- [2 Y1 - 4 Y_{i+1} (Y_i Y1 + Y1 Y_i)] Z_i, evaluated as the
-  // (symmetric) transpose Z_i [2 Y1 - 4 Y_{i+1} G]^T so that every GEMM operand
-  // is symmetric or explicitly transposed
+  // Level i maps a response K to K - 4 Y_i K Y_i (its z-part is in W): G = Y_i K,
+  // then Y_i G^T = Y_i K Y_i, symmetric, with K added in the epilogue.
   for (int i = 0; i < L; ++i) {
-    mr(c, Yr[i], Y1, G, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, Y1, Yr[i]);      // G = Y Y1 + Y1 Y
-    mr(c, Yr[i + 1], G, H, 1.0, 0);                                                     // H = Y_{i+1} G
-    axpby((int)c->n2, 2.0, Y1, -4.0, H, H, i32, s);                                       // 2 Y1 - 4 H
-    mr(c, Zr[i], H, Y1b, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);                  // Z_i (..)^T
+    mr(c, Yr[i], Y1, G, 1.0, 0);                                                         // G = Y_i K
+    mr(c, Yr[i], G, Y1b, -4.0, 1, Y1, 1.0, nullptr, 0.0, 0.0, 1);                        // K - 4 Y_i K Y_i
     std::swap(Y1, Y1b);
   }
-  // chemical-potential shift map: Qs Y1 Qs
-  mr(c, Qr, Y1, G, 1.0, 0);
-  mr(c, Qr, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+  // the z-parts of all levels and the chemical-potential shift: W K W
+  mr(c, Wr, Y1, G, 1.0, 0);
+  mr(c, Wr, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
   // canonical projection: R - (Tr R / Tr M) M
   trace(n, H, c->dscal + S_TRR, i32, c->red, s);
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
@@ -763,18 +801,7 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   }
   if (!converged) return fail(c, XLBOMD_E_NOCONV, "chemical potential search did not converge");
   c->chain_valid = true;
-  if (c->resp_copy) {
-    const int n2 = (int)c->n2;
-    for (int i = 0; i <= c->L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, c->s);
-    for (int i = 0; i < c->L; ++i) convert(n2, c->Zc[i], c->is32, c->Zr[i], 1, c->s);
-    convert(n2, c->Vst, c->is32, c->Vr, 1, c->s);
-    convert(n2, c->Pst, c->is32, c->Pr, 1, c->s);
-    convert(n2, c->Sst, c->is32, c->Sr, 1, c->s);
-    convert(n2, c->S2st, c->is32, c->S2r, 1, c->s);
-    convert(n2, c->Bst, c->is32, c->Br, 1, c->s);
-    convert(n2, c->Qs, c->is32, c->Qr, 1, c->s);
-    convert(n2, c->M, c->is32, c->Mr, 1, c->s);
-  }
+  c->resp_ready = false;
   hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, c->s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
                      c->dscal + S_FIX);
   {
@@ -994,15 +1021,14 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   for (auto &p : c->f64) f(p);
   if (c->resp_copy) {
     for (auto &p : c->Yr) f(p);
-    for (auto &p : c->Zr) f(p);
     f(c->Vr);
     f(c->Pr);
     f(c->Sr);
     f(c->S2r);
     f(c->Br);
     f(c->Mr);
-    f(c->Qr);
   }
+  f(c->Wr);
   for (int k = 0; k < c->kalloc; ++k) {
     f(c->Vk[k]);
     f(c->Wk[k]);
@@ -1081,15 +1107,14 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   if (c->resp_copy) {
     const size_t m4 = c->n2 * 4;
     for (auto &p : c->Yr) A(&p, m4);
-    for (auto &p : c->Zr) A(&p, m4);
     A(&c->Vr, m4);
     A(&c->Pr, m4);
     A(&c->Sr, m4);
     A(&c->S2r, m4);
     A(&c->Br, m4);
     A(&c->Mr, m4);
-    A(&c->Qr, m4);
   }
+  A(&c->Wr, c->resp_copy ? c->n2 * 4 : mb);
   if (!ok) {
     xlbomd_destroy(c);
     return XLBOMD_E_NOMEM;
