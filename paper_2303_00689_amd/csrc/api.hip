@@ -34,14 +34,14 @@ constexpr double TC0 = 1.0, TC1 = -1.0 / 3.0, TC2 = 2.0 / 15.0, TC3 = -17.0 / 31
 // device scalar slots
 enum Slot {
   S_LOHI = 0,      // 2
-  S_TAU = 4,       // 8: tau_0..tau_4
+  S_TAU = 4,       // 8: tau_0..tau_5
   S_MU1 = 16,      // 5: dmu, c, 2/(1+c), flag, 1-c
   S_T01 = 28,      // 2: Tr D1, Tr D1(I-D1)
   S_TRM = 48,      // Tr M
   S_TRR = 50,      // Tr R (response)
   S_CAN = 52,      // -Tr R / Tr M
   S_TRD = 54,      // final trace of D
-  S_FIX = 56,      // first-order trace correction coefficient
+  S_FIX = 56,      // first-order trace correction coefficient (+1: mu_shift's own step)
   S_ENT = 59,      // entropy S/k_B
   S_TRP = 58,      // trace of the returned P
   S_ENER = 60,     // 3 energies
@@ -198,12 +198,14 @@ struct xlbomd_ctx {
   // chain storage (chain element type)
   void *Yc[LMAX + 1] = {}, *Zc[LMAX] = {};
   void *Vst = nullptr, *Pst = nullptr, *Sst = nullptr, *S2st = nullptr, *Bst = nullptr;
-  void *D = nullptr, *M = nullptr, *Qs = nullptr;
+  void *D = nullptr, *M = nullptr;
+  double shift_c = 1.0;  // prod c_k of the last chemical-potential shift
+  bool fix_pending = false;  // mu_shift left a first-order step in slot S_FIX + 1
   // response-precision copies of the cached chain (alias the above when the
   // two chains share a precision), made on the first response after a chain
   void *Yr[LMAX] = {};
   void *Vr = nullptr, *Pr = nullptr, *Sr = nullptr, *S2r = nullptr, *Br = nullptr, *Mr = nullptr;
-  void *Wr = nullptr;  // W = 2^(L/2) Qs prod_i Z_i, response precision
+  void *Wr = nullptr;  // W = 2^(L/2) Qs prod_i Z_i, response precision (Qs: see mu_shift)
   bool resp_copy = false;
   bool resp_ready = false;
   void *w[8] = {};
@@ -542,11 +544,12 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
 
 // Exact chemical-potential shift: D(mu + dmu) = D (c I + (1 - c) D)^-1 with
 // c = exp(-beta dmu), applied in passes.  Pass 1 solves the trace series
-// sum_k (1-c)^k Tr[D (I-D)^k] = N_occ (k < 5); every later pass is a Newton step
+// sum_k (1-c)^k Tr[D (I-D)^k] = N_occ (k < 6); every later pass is a Newton step
 // dmu = (N_occ - Tr D) / (beta Tr D(I-D)).  Each pass is clamped to
 // |beta dmu| <= 0.3 and is followed by its exact shift, so a poor warm start
 // costs a few shifts instead of a new chain.  Leaves D, M = D(I - D) and
-// Qs = sqrt(prod c_k) prod Q_k^-1 for the response; *dmu_out gets the total.
+// shift_c = prod c_k (the response's Qs follows from it and D); *dmu_out gets
+// the total.
 // Returns XLBOMD_E_NOCONV (without changing mu) if the passes run out.
 xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   const int n = c->n, i32 = c->is32;
@@ -554,7 +557,7 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   hipStream_t s = c->s;
   xlbomd_status st;
   void *D = c->D, *D2 = c->w[0], *D3 = c->w[1], *Mx = c->w[2], *Nx = c->w[3], *N2 = c->w[4],
-       *MN = c->w[5];
+       *MN = c->w[5], *N3 = c->w[6];
   mm(c, D, D, D2, 1.0, 1);
   mm(c, D, D2, D3, 1.0, 1);
   axpby((int)c->n2, 1.0, D, -1.0, D2, Mx, i32, s);                                  // M
@@ -562,22 +565,27 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   axpbyI_dev(n, nullptr, -2.0, D, nullptr, 1.0, D2, nullptr, 1.0, N2, i32, s);      // N^2
   axpbyI_dev(n, nullptr, 1.0, D, nullptr, -2.0, D2, nullptr, 0.0, MN, i32, s);      // D - 2D^2
   axpby((int)c->n2, 1.0, MN, 1.0, D3, MN, i32, s);                                  // + D^3
+  {
+    const void *Xs[4] = {D, D2, D3, nullptr};
+    const double a[4] = {-3.0, 3.0, -1.0, 0.0};
+    poly_comb(n, Xs, a, 1.0, N3, i32, s);                                           // N^3
+  }
   trace(n, D, c->dscal + S_TAU, i32, c->red, s);
   trace(n, Mx, c->dscal + S_TAU + 1, i32, c->red, s);
   {
-    const void *X[3] = {Mx, Mx, MN};
-    const void *Y[3] = {Nx, N2, N2};
-    dots((int)c->n2, 3, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
+    // Tr D N^k for k = 2..5 as Frobenius products of symmetric matrices
+    const void *X[4] = {Mx, Mx, MN, MN};
+    const void *Y[4] = {Nx, N2, N2, N3};
+    dots((int)c->n2, 4, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
   }
   mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->dscal + S_MU1, s);
   // Each pass shifts D exactly to D(mu + dmu) = D Q^-1, Q = c I + (1 - c) D,
   // c = exp(-beta dmu): pass 0 with dmu from the trace series, later passes
-  // with a (clamped) Newton step on Tr D.  Qs accumulates the product of the
-  // Q^-1.  The passes end with a step |1 - c| <= 1e-3, taken as the series
-  // Q^-1 = (I - r D + r^2 D^2 - r^3 D^3)/c, r = (1 - c)/c (error O(r^4)); the
-  // first-order trace correction applied afterwards then leaves O(r^4).
+  // with a (clamped) Newton step on Tr D.  A large step inverts Q by
+  // Newton-Schulz; the passes end with a small step taken as a truncated
+  // series in D.  The shifts compose: c multiplies.
   double dmu_total = 0.0, cprod = 1.0;
-  bool first = true, done = false;
+  bool done = false, wide = false;
   c->mu_passes = 0;
   for (int pass = 0; pass < 8 && !done; ++pass) {
     double mres[5];
@@ -595,18 +603,47 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     c->mu_passes = pass + 1;
     const bool clamped = mres[3] != 0.0;
     const double cc = mres[1];
-    void *Qi;  // Q^-1 of this pass (unscaled)
-    if (!clamped && std::fabs(1.0 - cc) <= 1e-3) {
-      const double r = (1.0 - cc) / cc;
+    // The series step ends the passes.  After pass 0 (trace series with k < 6)
+    // Tr D misses N_occ by O((1 - c)^6), after a Newton pass by O(dmu^2); the
+    // first-order trace correction applied afterwards leaves the square of
+    // that, so pass 0 may take the series for |1 - c| up to 8e-2, a Newton pass
+    // for |1 - c| up to 1e-3.
+    const double ser_max = pass == 0 ? 8e-2 : 1e-3;
+    if (!clamped && std::fabs(1.0 - cc) <= ser_max) {
+      wide = std::fabs(1.0 - cc) > 1e-3;
+      // D Q^-1 = (1/c) sum_{k<=K} (-r)^k D^(k+1), r = (1 - c)/c, with K the
+      // least order whose remainder |r|^(K+1) / (1 - |r|) is below 1e-13 (K <= 15)
+      const double r = (1.0 - cc) / cc, ar = std::fabs(r);
+      int K = 0;
+      for (double rem = ar; K < 15 && rem / (1.0 - ar) > 1e-13; rem *= ar) ++K;
+      const int deg = K + 1;
+      double p[17] = {};  // p[j]: coefficient of D^j
+      for (int k = 0; k <= K; ++k) p[k + 1] = std::pow(-r, k) / cc;
       void *D4 = c->w[2];
-      if (!have_d3) mm(c, D, D2, D3, 1.0, 1);
-      mm(c, D2, D2, D4, 1.0, 1);
-      const void *Xs[4] = {D, D2, D3, D4};
-      const double aq[4] = {-r / cc, r * r / cc, -r * r * r / cc, 0.0};
-      const double ad[4] = {1.0 / cc, -r / cc, r * r / cc, -r * r * r / cc};
-      Qi = c->w[3];
-      poly_comb(n, Xs, aq, 1.0 / cc, Qi, i32, s);
-      poly_comb(n, Xs, ad, 0.0, D, i32, s);  // D <- D Q^-1 in place
+      if (!have_d3 && deg >= 3) mm(c, D, D2, D3, 1.0, 1);
+      if (deg >= 4) mm(c, D2, D2, D4, 1.0, 1);
+      if (deg <= 4) {
+        const void *Xs[4] = {D, D2, deg >= 3 ? D3 : nullptr, deg >= 4 ? D4 : nullptr};
+        const double a[4] = {p[1], p[2], p[3], p[4]};
+        poly_comb(n, Xs, a, 0.0, D, i32, s);  // D <- D Q^-1 in place
+      } else {
+        // Horner in D^4 over blocks B_m = sum_{i<4} p[4m+i] D^i (the top block
+        // also takes p[4H+4] D^4): p(D) = B_0 + D^4 (B_1 + D^4 (.. + D^4 B_H))
+        const int H = (deg - 1) / 4;
+        const void *Xs[4] = {D, D2, D3, D4};
+        void *acc = c->w[3], *blk = c->w[4], *nxt = c->w[5];
+        {
+          const double a[4] = {p[4 * H + 1], p[4 * H + 2], p[4 * H + 3], 4 * H + 4 <= 16 ? p[4 * H + 4] : 0.0};
+          poly_comb(n, Xs, a, p[4 * H], acc, i32, s);
+        }
+        for (int m = H - 1; m >= 0; --m) {
+          const double a[4] = {p[4 * m + 1], p[4 * m + 2], p[4 * m + 3], 0.0};
+          poly_comb(n, Xs, a, p[4 * m], blk, i32, s);
+          void *out = m == 0 ? D : nxt;
+          mm(c, D4, acc, out, 1.0, 1, blk, 1.0);
+          std::swap(acc, nxt);
+        }
+      }
       done = true;
     } else {
       // inverse of Q (spectrum in [min(c,1), max(c,1)]) by Newton-Schulz from
@@ -649,23 +686,36 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
       void *Dn = (Za == c->w[2]) ? c->w[3] : c->w[2];
       mm(c, D, Za, Dn, 1.0, 1);
       axpby((int)c->n2, 1.0, Dn, 0.0, nullptr, D, i32, s);
-      Qi = Za;
-    }
-    // Qs <- Qs Q^-1 (all factors are functions of F and commute)
-    if (first) {
-      axpby((int)c->n2, 1.0, Qi, 0.0, nullptr, c->Qs, i32, s);
-      first = false;
-    } else {
-      mm(c, c->Qs, Qi, c->w[4], 1.0, 1);
-      axpby((int)c->n2, 1.0, c->w[4], 0.0, nullptr, c->Qs, i32, s);
     }
     dmu_total += mres[0];
     cprod *= cc;
   }
   if (!done) return XLBOMD_E_NOCONV;
-  axpby((int)c->n2, std::sqrt(cprod), c->Qs, 0.0, nullptr, c->Qs, i32, s);
-  // M = D - D^2
-  mm(c, D, D, c->M, -1.0, 1, D, 1.0);
+  c->shift_c = cprod;
+  c->fix_pending = wide;
+  if (wide) {
+    // A wide series step leaves Tr D off N_occ by up to ~1e-7 Tr M.  Step to the
+    // trace to first order, x = beta dmu by f = (N_occ - Tr D) / Tr M (slot
+    // S_FIX + 1): D += f M and M += f dM/dx, dM/dx = D - 3 D^2 + 2 D^3, so that
+    // D, M and the response's Qs (c <- c e^-f, after the host reads f) describe
+    // one chemical potential up to O(f^2).
+    void *D2n = c->w[0], *D3n = c->w[1], *Tn = c->w[2];
+    mm(c, D, D, D2n, 1.0, 1);
+    axpby((int)c->n2, 1.0, D, -1.0, D2n, c->M, i32, s);
+    mm(c, D, D2n, D3n, 1.0, 1);
+    trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
+    trace(n, D, c->dscal + S_TRD, i32, c->red, s);
+    hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
+                       c->dscal + S_FIX + 1);
+    const void *Xs[4] = {D, D2n, D3n, nullptr};
+    const double a[4] = {1.0, -3.0, 2.0, 0.0};
+    poly_comb(n, Xs, a, 0.0, Tn, i32, s);
+    axpbyI_dev(n, nullptr, 1.0, D, c->dscal + S_FIX + 1, 0.0, c->M, nullptr, 0.0, D, i32, s);
+    axpbyI_dev(n, nullptr, 1.0, c->M, c->dscal + S_FIX + 1, 0.0, Tn, nullptr, 0.0, c->M, i32, s);
+  } else {
+    // M = D - D^2
+    mm(c, D, D, c->M, -1.0, 1, D, 1.0);
+  }
   trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
   trace(n, D, c->dscal + S_TRD, i32, c->red, s);
   *dmu_out = dmu_total;
@@ -680,10 +730,14 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
 // eigenvalues of Qs).  These are Hadamard factors, so they commute: the z-parts
 // and qs collect into W = 2^(L/2) Qs Z_0 ... Z_(L-1) (L products, once per chain)
 // and each level keeps only K -> K - 4 Y_i K Y_i (two products per response).
+// The shift D -> D Q^-1, Q = c I + (1 - c) D, inverts to Q^-1 = (I - (1 - c) D')/c
+// in terms of the shifted D', and shifts compose (c multiplies), so
+// Qs = sqrt(c) Q^-1 = (I - (1 - c) D) / sqrt(c) with the cached D and c = shift_c.
 void prepare_response(xlbomd_ctx *c) {
-  const int n2 = (int)c->n2, L = c->L;
+  const int n = c->n, n2 = (int)c->n2, L = c->L;
   hipStream_t s = c->s;
-  const void *Q = c->Qs;
+  const double rs = 1.0 / std::sqrt(c->shift_c), qa = -(1.0 - c->shift_c) * rs;
+  const void *Q = c->w[0];
   if (c->resp_copy) {
     for (int i = 0; i < L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, s);
     convert(n2, c->Vst, c->is32, c->Vr, 1, s);
@@ -692,8 +746,10 @@ void prepare_response(xlbomd_ctx *c) {
     convert(n2, c->S2st, c->is32, c->S2r, 1, s);
     convert(n2, c->Bst, c->is32, c->Br, 1, s);
     convert(n2, c->M, c->is32, c->Mr, 1, s);
-    convert(n2, c->Qs, c->is32, c->w[0], 1, s);
-    Q = c->w[0];
+    convert(n2, c->D, c->is32, c->w[1], 1, s);
+    axpbyI_dev(n, nullptr, qa, c->w[1], nullptr, 0.0, nullptr, nullptr, rs, c->w[0], 1, s);
+  } else {
+    axpbyI_dev(n, nullptr, qa, c->D, nullptr, 0.0, nullptr, nullptr, rs, c->w[0], c->is32, s);
   }
   // W <- sqrt(2) Z_i W for i < L (commuting symmetric factors: symmetric products)
   const void *Wa = Q;
@@ -815,7 +871,12 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   }
   trace(n, P, c->dscal + S_TRP, 0, c->red, c->s);
   double fx[3];
-  if ((st = get_scalars(c, S_FIX, 3, fx))) return st;  // S_FIX, (pad), S_TRP
+  if ((st = get_scalars(c, S_FIX, 3, fx))) return st;  // S_FIX, first-order step of mu_shift, S_TRP
+  if (c->fix_pending) {
+    mu += fx[1] / c->beta;
+    c->shift_c *= std::exp(-fx[1]);
+    c->fix_pending = false;
+  }
   mu += fx[0] / c->beta;
   *mu_io = mu;
   if (sync_check) {
@@ -1016,7 +1077,6 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   f(c->Bst);
   f(c->D);
   f(c->M);
-  f(c->Qs);
   for (auto &p : c->w) f(p);
   for (auto &p : c->f64) f(p);
   if (c->resp_copy) {
@@ -1101,7 +1161,6 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   A(&c->Bst, mb);
   A(&c->D, mb);
   A(&c->M, mb);
-  A(&c->Qs, mb);
   for (auto &p : c->w) A(&p, c->n2 * 8);  // work matrices hold either element type
   for (auto &p : c->f64) A((void **)&p, c->n2 * 8);
   if (c->resp_copy) {

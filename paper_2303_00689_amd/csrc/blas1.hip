@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_gersh_final(int n, const double *lohi, 
   }
 }
 
-// ---- chemical potential: solve sum_{k<5} (1-c)^k tau_k = n_occ for dmu, c = exp(-beta dmu),
+// ---- chemical potential: solve sum_{k<6} (1-c)^k tau_k = n_occ for dmu, c = exp(-beta dmu),
 // by bisection on dmu in [-0.3/beta, 0.3/beta] (the truncated series is accurate there for
 // the warm starts of a trajectory).  out[0] = dmu, out[1] = c, out[2] = 2/(1+c) (Newton-Schulz
 // start for (cI + (1-c)D)^-1), out[3] = flag (1: root outside the bracket, clamped).
@@ -303,7 +303,7 @@ __global__ void k_mu_series(const double *tau, double n_occ, double beta, double
   auto g = [&](double dmu) {
     const double x = -expm1(-beta * dmu);  // 1 - c
     double s = 0.0, p = 1.0;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
       s += p * tau[k];
       p *= x;
     }
