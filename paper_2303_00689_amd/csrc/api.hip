@@ -508,17 +508,24 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
         std::swap(Za32, Zb32);
         el = el * el + 1e-7;
       }
-      // Z is a function of the FP32-rounded S, so T Z is symmetric only to
-      // ~1e-7 and E is not symmetric: the FP64 residual is formed in full, and
-      // the split GEMM (which takes its second operand transposed) gets E^T.
-      // Z E carries the asymmetry of Z and is formed in full as well.
-      convert(n2i, Za32, 1, Za, 0, c->s);
-      mm(c, Si, Za, E, -4.0, 0, Za, -1.0, nullptr, 0.0, 1.0);  // E = I - T Z in FP64
-      convert_t(n, (const double *)E, (float *)E32, c->s);
-      mm_p(c, XLBOMD_BF16X6, Za32, E32, C32, 1.0, 0);           // Z E
-      convert(n2i, C32, 1, E, 0, c->s);
-      axpby(n2i, 1.0, Za, 1.0, E, Zb, 0, c->s);                // Z + Z E
-      std::swap(Za, Zb);
+      // Y_{i+1} = 2 T^-1 Y by one residual correction of the split solve
+      // Y0 = 2 Z Y: R = 2 Y - T Y0 in FP64 (a cancellation), Y_{i+1} = Y0 + Z R,
+      // which leaves (I - Z T)(Y0 - 2 T^-1 Y), the square of the split error.
+      // Z and Y0 are functions of the FP32-rounded S and Y, so T Y0 is
+      // symmetric only to ~1e-7 and R is not symmetric: R is formed in full,
+      // and the split GEMM (which takes its second operand transposed) gets R^T.
+      void *Y32 = Zb32, *Yn32 = E32, *Yn = Za, *R = E, *C = Zb;
+      convert(n2i, Y, 0, Y32, 1, c->s);
+      mm_p(c, XLBOMD_BF16X6, Za32, Y32, Yn32, 2.0, 1);         // Y0 = 2 Z Y
+      convert(n2i, Yn32, 1, Yn, 0, c->s);
+      mm(c, Si, Yn, R, -4.0, 0, Yn, -1.0, Y, 2.0);             // R = 2 Y - Y0 - 4 S Y0 in FP64
+      convert_t(n, (const double *)R, (float *)E32, c->s);
+      mm_p(c, XLBOMD_BF16X6, Za32, E32, C32, 1.0, 0);          // Z R
+      convert(n2i, C32, 1, C, 0, c->s);
+      axpby(n2i, 1.0, Yn, 1.0, C, c->Yc[i + 1], 0, c->s);      // Y0 + Z R
+      symmetrize(n, c->Yc[i + 1], 0, c->s);
+      // the FP32 Z_i is what the response needs
+      convert(n2i, Za32, 1, c->Zc[i], 1, c->s);
     } else {
       // E0 = I - a T - b T^2 with T = I + 4S, T^2 = I + 8S + 16 S^2
       mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
@@ -530,10 +537,12 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
         std::swap(Za, Zb);
       }
     }
-    // keep Z_i in the cache
-    if (Za != c->w[3]) std::swap(c->w[3], c->w[4]);
-    std::swap(c->Zc[i], c->w[3]);
-    mm(c, Y, c->Zc[i], c->Yc[i + 1], 2.0, 1);
+    if (!mixed) {
+      // keep Z_i in the cache
+      if (Za != c->w[3]) std::swap(c->w[3], c->w[4]);
+      std::swap(c->Zc[i], c->w[3]);
+      mm(c, Y, c->Zc[i], c->Yc[i + 1], 2.0, 1);
+    }
     yb = 2.0 * yb / (1.0 + 4.0 * yb * yb);
   }
   // D = I/2 + Y_L
@@ -738,6 +747,8 @@ void prepare_response(xlbomd_ctx *c) {
   hipStream_t s = c->s;
   const double rs = 1.0 / std::sqrt(c->shift_c), qa = -(1.0 - c->shift_c) * rs;
   const void *Q = c->w[0];
+  // the FP64 chain with split Newton-Schulz keeps its Z_i in FP32
+  const bool zc32 = c->prec_dm == XLBOMD_FP64 && c->resp_copy;
   if (c->resp_copy) {
     for (int i = 0; i < L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, s);
     convert(n2, c->Vst, c->is32, c->Vr, 1, s);
@@ -755,7 +766,7 @@ void prepare_response(xlbomd_ctx *c) {
   const void *Wa = Q;
   for (int i = 0; i < L; ++i) {
     const void *Zi = c->Zc[i];
-    if (c->resp_copy) {
+    if (c->resp_copy && !zc32) {
       convert(n2, c->Zc[i], c->is32, c->w[1], 1, s);
       Zi = c->w[1];
     }
