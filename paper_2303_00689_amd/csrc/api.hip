@@ -702,6 +702,22 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   if (!done) return XLBOMD_E_NOCONV;
   c->shift_c = cprod;
   c->fix_pending = wide;
+  // M, and D^2, D^3 of the first-order step below, enter D only multiplied by a
+  // trace correction f <~ 1e-7, and the response (of split precision in the
+  // mixed modes) takes M as it is: with a split response they are BF16x6
+  // products (relative error ~1e-7); an FP64 response keeps them FP64.
+  const bool lowM = c->prec_dm == XLBOMD_FP64 && c->resp_copy;
+  const size_t half = c->n2 * 4;
+  void *D32 = c->w[3], *P2_32 = (char *)c->w[3] + half, *P3_32 = c->w[4];
+  if (lowM) convert((int)c->n2, D, 0, D32, 1, s);
+  auto dsq = [&](void *out) {  // out = D^2
+    if (lowM) {
+      mm_p(c, XLBOMD_BF16X6, D32, D32, P2_32, 1.0, 1);
+      convert((int)c->n2, P2_32, 1, out, 0, s);
+    } else {
+      mm(c, D, D, out, 1.0, 1);
+    }
+  };
   if (wide) {
     // A wide series step leaves Tr D off N_occ by up to ~1e-7 Tr M.  Step to the
     // trace to first order, x = beta dmu by f = (N_occ - Tr D) / Tr M (slot
@@ -709,9 +725,14 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     // D, M and the response's Qs (c <- c e^-f, after the host reads f) describe
     // one chemical potential up to O(f^2).
     void *D2n = c->w[0], *D3n = c->w[1], *Tn = c->w[2];
-    mm(c, D, D, D2n, 1.0, 1);
+    dsq(D2n);
     axpby((int)c->n2, 1.0, D, -1.0, D2n, c->M, i32, s);
-    mm(c, D, D2n, D3n, 1.0, 1);
+    if (lowM) {
+      mm_p(c, XLBOMD_BF16X6, D32, P2_32, P3_32, 1.0, 1);
+      convert((int)c->n2, P3_32, 1, D3n, 0, s);
+    } else {
+      mm(c, D, D2n, D3n, 1.0, 1);
+    }
     trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
     trace(n, D, c->dscal + S_TRD, i32, c->red, s);
     hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
@@ -721,9 +742,11 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     poly_comb(n, Xs, a, 0.0, Tn, i32, s);
     axpbyI_dev(n, nullptr, 1.0, D, c->dscal + S_FIX + 1, 0.0, c->M, nullptr, 0.0, D, i32, s);
     axpbyI_dev(n, nullptr, 1.0, c->M, c->dscal + S_FIX + 1, 0.0, Tn, nullptr, 0.0, c->M, i32, s);
+  } else if (lowM) {
+    dsq(c->w[0]);
+    axpby((int)c->n2, 1.0, D, -1.0, c->w[0], c->M, i32, s);  // M = D - D^2
   } else {
-    // M = D - D^2
-    mm(c, D, D, c->M, -1.0, 1, D, 1.0);
+    mm(c, D, D, c->M, -1.0, 1, D, 1.0);                       // M = D - D^2
   }
   trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
   trace(n, D, c->dscal + S_TRD, i32, c->red, s);
