@@ -26,7 +26,15 @@ constexpr int MMAX = 32;     // maximum Krylov rank
 constexpr double KB = 8.617333262e-5;           // eV / K
 constexpr double ACC = 9.648533e-3;             // (eV / (Angstrom amu)) -> Angstrom / fs^2
 constexpr int LANCZOS_K = 32;                 // Lanczos steps for the spectral bounds
-constexpr double VMAX = 1.2;                    // bound on |v| at the start of the chain
+// Start interval and least depth of the Fermi chain.  For the degree-9 start
+// followed by L doubling levels, the largest deviation from the Fermi function
+// and from its derivative over |v| <= vb (scalar recursion in FP64) is
+//   L = 1..4: 1e-2 .. 4e-11 already for vb >= 0.4 (the start's truncation error,
+//             and that of its derivative, is not yet squared away);
+//   L >= 5:   <= 4e-14 for every vb up to 1.68 (1.85 at L = 6),
+// so the chain takes L >= 5 and |v| <= 1.6.
+constexpr double VMAX = 1.6;
+constexpr int LMIN = 5;
 // Taylor coefficients of tanh(v) / v in powers of v^2 (degree-9 start)
 constexpr double TC0 = 1.0, TC1 = -1.0 / 3.0, TC2 = 2.0 / 15.0, TC3 = -17.0 / 315.0,
                  TC4 = 62.0 / 2835.0;
@@ -455,7 +463,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   const double beta = c->beta;
   const double rho = beta * std::max(hi - mu, mu - lo) / 2.0;
   int L = (int)std::ceil(std::log2(std::max(rho / VMAX, 1.0)));
-  if (L < 1) L = 1;
+  if (L < LMIN) L = LMIN;
   if (L > LMAX) return fail(c, XLBOMD_E_ARG, "spectral range too wide (needs %d levels)", L);
   c->L = L;
   const double vb = std::min(rho / std::ldexp(1.0, L), VMAX);

@@ -29,8 +29,10 @@ def lib():
 
 
 class Case:
-    def __init__(self, binding, name, seed=0, prec="fp64"):
+    def __init__(self, binding, name, seed=0, prec="fp64", T_e=None):
         self.sys, self.w = workload(name)
+        if T_e is not None:
+            self.w = dict(self.w, T_e=T_e)
         s = self.sys
         self.beta = density.beta_of(self.w["T_e"])
         rng = np.random.default_rng(seed)
@@ -111,6 +113,29 @@ def test_dm_response(case):
     got = case.np(P1)
     assert _rel(got, ref) <= TOL
     assert abs(np.trace(got)) <= 1e-10 * np.abs(ref).max() * s.n_orb
+
+
+@pytest.mark.parametrize("T_e", [30000.0, 60000.0])
+def test_hot_cluster_density_and_response(lib, T_e):
+    # A narrow spectral range in units of kT (beta (eps - mu) / 2 within about
+    # +-8 and +-4 for the 10-atom cluster) needs few doubling levels; the
+    # chain still has to meet the FP64 bar, for D and for its response.
+    case = Case(lib, "c10", T_e=T_e)
+    try:
+        s = case.sys
+        F = case.t(case.F)
+        P = torch.empty_like(F)
+        case.h.fermi_dm(F, P)
+        assert _rel(case.np(P), case.dm["P"]) <= TOL
+        V = case.rng.standard_normal((s.n_orb, s.n_orb))
+        V = V + V.T
+        F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params)
+        P1 = torch.empty_like(F)
+        case.h.dm_response(case.t(F1), P1)
+        ref = density.response(case.F, F1, s.n_elec, case.beta, case.dm)
+        assert _rel(case.np(P1), ref) <= TOL
+    finally:
+        case.h.close()
 
 
 def test_krylov_kernel(case):
