@@ -431,20 +431,20 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
       break;
     }
   }
-  std::vector<double> T((size_t)k * k, 0.0), V, th;
+  std::vector<double> dg(k), od(k), th, zl;
   for (int j = 0; j < k; ++j) {
-    T[(size_t)j * k + j] = ab[2 * j];
-    if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = ab[2 * j + 1];
+    dg[j] = ab[2 * j];
+    od[j] = ab[2 * j + 1];
   }
-  if (!jacobi_eig(k, T, V, th)) return XLBOMD_OK;
+  if (!tridiag_eig_last(k, dg, od, th, zl)) return XLBOMD_OK;
   int imin = 0, imax = 0;
   for (int i = 1; i < k; ++i) {
     if (th[i] < th[imin]) imin = i;
     if (th[i] > th[imax]) imax = i;
   }
   const double bk = ab[2 * (k - 1) + 1];
-  const double rmin = bk * std::fabs(V[(size_t)(k - 1) * k + imin]);
-  const double rmax = bk * std::fabs(V[(size_t)(k - 1) * k + imax]);
+  const double rmin = bk * std::fabs(zl[imin]);
+  const double rmax = bk * std::fabs(zl[imax]);
   const double margin = 1e-3 * (th[imax] - th[imin]) + 1e-12 * scale;
   lohi[0] = std::max(g[0], th[imin] - rmin - margin);
   lohi[1] = std::min(g[1], th[imax] + rmax + margin);
@@ -1542,7 +1542,10 @@ xlbomd_status xlbomd_profile(xlbomd_handle c, int enable) {
   c->prof = enable != 0;
   if (c->prof && c->evpool.empty()) {
     c->evpool.resize(2 * 65536);
-    for (auto &e : c->evpool) HIPCHK(c, hipEventCreate(&e));
+    // timing-only events: profile_read synchronises the stream before reading
+    // them, so the system-scope fence (a cache writeback and invalidate at every
+    // record, ~10 us between back-to-back kernels) is not needed
+    for (auto &e : c->evpool) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   return XLBOMD_OK;
 }

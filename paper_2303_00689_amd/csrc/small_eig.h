@@ -1,5 +1,7 @@
-// Host-side eigen-decomposition of small dense symmetric matrices by the
-// cyclic Jacobi method (used on the k x k Lanczos tridiagonal, k <= 64).
+// Host-side eigenvalues of the k x k Lanczos tridiagonal (k <= 64) by the
+// implicit QL iteration with Wilkinson shifts, keeping only the last row of the
+// accumulated rotations: the last component of every Ritz vector, which is all
+// the residual bounds beta_k |s_k| need.  O(k^2) work.
 #pragma once
 
 #include <cmath>
@@ -7,52 +9,62 @@
 
 namespace xl {
 
-// A: k x k symmetric, row-major, overwritten.  On return ev[i] are the
-// eigenvalues (unsorted) and column i of V (row-major k x k) the matching
-// unit eigenvector.  Returns false if the sweeps did not converge.
-inline bool jacobi_eig(int k, std::vector<double> &A, std::vector<double> &V, std::vector<double> &ev) {
-  V.assign((size_t)k * k, 0.0);
-  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
-  double frob = 0.0;
-  for (double a : A) frob += a * a;
-  bool conv = false;
-  for (int sweep = 0; sweep < 64 && !conv; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < k; ++p)
-      for (int q = p + 1; q < k; ++q) off += A[(size_t)p * k + q] * A[(size_t)p * k + q];
-    if (off <= 1e-32 * frob) {
-      conv = true;
-      break;
-    }
-    for (int p = 0; p < k; ++p) {
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[(size_t)p * k + q];
-        if (apq == 0.0) continue;
-        const double th = (A[(size_t)q * k + q] - A[(size_t)p * k + p]) / (2.0 * apq);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        // A <- J^T A J, J = rotation in the (p, q) plane
-        for (int r = 0; r < k; ++r) {
-          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
-          A[(size_t)r * k + p] = cs * arp - sn * arq;
-          A[(size_t)r * k + q] = sn * arp + cs * arq;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
-          A[(size_t)p * k + r] = cs * apr - sn * aqr;
-          A[(size_t)q * k + r] = sn * apr + cs * aqr;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
-          V[(size_t)r * k + p] = cs * vrp - sn * vrq;
-          V[(size_t)r * k + q] = sn * vrp + cs * vrq;
-        }
+// d: diagonal (k), e: off-diagonal (k - 1).  On return ev[i] are the
+// eigenvalues (unsorted) and zl[i] the last component of the matching unit
+// eigenvector.  Returns false if an eigenvalue took more than 60 QL steps.
+inline bool tridiag_eig_last(int k, const std::vector<double> &d, const std::vector<double> &e,
+                             std::vector<double> &ev, std::vector<double> &zl) {
+  ev.assign(d.begin(), d.begin() + k);
+  std::vector<double> off(k, 0.0);
+  for (int i = 0; i + 1 < k; ++i) off[i] = e[i];
+  zl.assign(k, 0.0);
+  if (k > 0) zl[k - 1] = 1.0;
+  for (int l = 0; l < k; ++l) {
+    for (int iter = 0;; ++iter) {
+      // the first negligible off-diagonal entry at or after l splits the matrix
+      int m = l;
+      for (; m + 1 < k; ++m) {
+        const double scale = std::fabs(ev[m]) + std::fabs(ev[m + 1]);
+        if (std::fabs(off[m]) <= 2.3e-16 * scale) break;
       }
+      if (m == l) break;
+      if (iter == 60) return false;
+      // Wilkinson shift from the leading 2 x 2 block of the unreduced part
+      double g = (ev[l + 1] - ev[l]) / (2.0 * off[l]);
+      double r = std::sqrt(g * g + 1.0);
+      g = ev[m] - ev[l] + off[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      bool deflated = false;
+      // chase the bulge from the bottom of the block up to l with Givens rotations
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * off[i], b = c * off[i];
+        r = std::sqrt(f * f + g * g);  // entries are energies: no overflow
+        off[i + 1] = r;
+        if (r == 0.0) {
+          ev[i + 1] -= p;
+          off[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = ev[i + 1] - p;
+        r = (ev[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        ev[i + 1] = g + p;
+        g = c * r - b;
+        // the rotation acts on columns i, i+1 of the eigenvector matrix; keep its last row
+        const double zi = zl[i], zi1 = zl[i + 1];
+        zl[i + 1] = s * zi + c * zi1;
+        zl[i] = c * zi - s * zi1;
+      }
+      if (deflated) continue;
+      ev[l] -= p;
+      off[l] = g;
+      off[m] = 0.0;
     }
   }
-  ev.resize(k);
-  for (int i = 0; i < k; ++i) ev[i] = A[(size_t)i * k + i];
-  return conv;
+  return true;
 }
 
 }  // namespace xl
