@@ -499,22 +499,31 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       ++k;
     }
     if (mixed) {
-      // FP64-accurate inverse with split-precision Newton-Schulz steps: the
-      // iteration corrects itself, so only the last residual E = I - T Z
-      // (a cancellation) needs FP64; the start and the early steps run in
-      // BF16x3 / BF16x6, and the last correction Z E (of size ~e) in BF16x6.
+      // Split-precision inverse Z ~ T^-1 to ~sqrt(eps) by Newton-Schulz (it
+      // corrects itself: start in BF16x3, steps in BF16x6); the FP64 accuracy
+      // comes from one residual correction of Y_{i+1} below.
       const size_t half = c->n2 * 4;
       void *S32 = c->w[5], *E32 = (char *)c->w[5] + half, *Za32 = c->w[6], *Zb32 = (char *)c->w[6] + half,
            *C32 = c->w[7];
       convert(n2i, Si, 0, S32, 1, c->s);
       mm_p(c, XLBOMD_BF16X3, S32, S32, E32, -16.0 * b, 1, S32, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
       mm_p(c, XLBOMD_BF16X3, S32, E32, Za32, 4.0 * b, 1, S32, 4.0 * b, E32, a + b, a + b);
+      // Steps of order 2, Z <- Z (I + E), or 3, Z <- Z (I + E + E^2) with
+      // E' = E E + E: two or three products for error e^2 or e^3.  Each step
+      // takes order 2 if that reaches the target, else order 3.
       double el = e0 * e0 + 2e-5;  // + BF16x3 rounding
-      for (int it = 0; it < 8 && el > std::sqrt(eps); ++it) {
-        mm_p(c, XLBOMD_BF16X6, S32, Za32, E32, -4.0, 1, Za32, -1.0, nullptr, 0.0, 1.0);
-        mm_p(c, XLBOMD_BF16X6, Za32, E32, Zb32, 1.0, 1, Za32, 1.0);
+      const double target = std::sqrt(eps);
+      for (int it = 0; it < 8 && el > target; ++it) {
+        mm_p(c, XLBOMD_BF16X6, S32, Za32, E32, -4.0, 1, Za32, -1.0, nullptr, 0.0, 1.0);  // E = I - T Z
+        if (el * el + 1e-7 > target) {
+          mm_p(c, XLBOMD_BF16X6, E32, E32, Zb32, 1.0, 1, E32, 1.0);                   // E' = E E + E
+          std::swap(E32, Zb32);
+          el = el * el * el + 1e-7;
+        } else {
+          el = el * el + 1e-7;
+        }
+        mm_p(c, XLBOMD_BF16X6, Za32, E32, Zb32, 1.0, 1, Za32, 1.0);                   // Z + Z E
         std::swap(Za32, Zb32);
-        el = el * el + 1e-7;
       }
       // Y_{i+1} = 2 T^-1 Y by one residual correction of the split solve
       // Y0 = 2 Z Y: R = 2 Y - T Y0 in FP64 (a cancellation), Y_{i+1} = Y0 + Z R,
