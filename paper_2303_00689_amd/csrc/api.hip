@@ -531,16 +531,20 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       // Z and Y0 are functions of the FP32-rounded S and Y, so T Y0 is
       // symmetric only to ~1e-7 and R is not symmetric: R is formed in full,
       // and the split GEMM (which takes its second operand transposed) gets R^T.
-      void *Y32 = Zb32, *Yn32 = E32, *Yn = Za, *R = E, *C = Zb;
-      convert(n2i, Y, 0, Y32, 1, c->s);
+      // Y32 (the FP32 Y_i) is the previous level's by-product, except at level 0
+      void *Y32 = c->w[0], *Yn32 = E32, *Yn = Za, *R = E;
+      if (i == 0) convert(n2i, Y, 0, Y32, 1, c->s);
       mm_p(c, XLBOMD_BF16X6, Za32, Y32, Yn32, 2.0, 1);         // Y0 = 2 Z Y
       convert(n2i, Yn32, 1, Yn, 0, c->s);
       mm(c, Si, Yn, R, -4.0, 0, Yn, -1.0, Y, 2.0);             // R = 2 Y - Y0 - 4 S Y0 in FP64
       convert_t(n, (const double *)R, (float *)E32, c->s);
       mm_p(c, XLBOMD_BF16X6, Za32, E32, C32, 1.0, 0);          // Z R
-      convert(n2i, C32, 1, C, 0, c->s);
-      axpby(n2i, 1.0, Yn, 1.0, C, c->Yc[i + 1], 0, c->s);      // Y0 + Z R
-      symmetrize(n, c->Yc[i + 1], 0, c->s);
+      // Y0 + Z R, with its FP32 copy for the next level.  Z R is symmetric only
+      // to ~1e-13 relative; every level rebuilds Y_{i+1} from the symmetric Y0,
+      // so only the last one (which gives D) is symmetrised.
+      add_mixed(n2i, (const double *)Yn, (const float *)C32, (double *)c->Yc[i + 1],
+                i + 1 < L ? (float *)Y32 : nullptr, c->s);
+      if (i + 1 == L) symmetrize(n, c->Yc[L], 0, c->s);
       // the FP32 Z_i is what the response needs
       convert(n2i, Za32, 1, c->Zc[i], 1, c->s);
     } else {

@@ -91,6 +91,16 @@ __global__ void k_convert(size_t n2, const void *in, void *out) {
     ((TO *)out)[i] = (TO)((const TI *)in)[i];
 }
 
+// out = a + (double) b, and its FP32 rounding (nullable)
+__global__ void k_add_mixed(size_t n2, const double *a, const float *b, double *out, float *out32) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double v = a[i] + (double)b[i];
+    out[i] = v;
+    if (out32) out32[i] = (float)v;
+  }
+}
+
 // M <- (M + M^T)/2 by 32x32 tiles of the upper triangle (tile pairs staged in LDS)
 template <typename T>
 __global__ void k_symmetrize(int n, T *M) {
@@ -493,6 +503,10 @@ void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t
     hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (size_t)n2, in, out);
   else
     hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (size_t)n2, in, out);
+}
+
+void add_mixed(int n2, const double *a, const float *b, double *out, float *out32, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_mixed, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, a, b, out, out32);
 }
 
 void symmetrize(int n, void *M, int is32, hipStream_t s) {

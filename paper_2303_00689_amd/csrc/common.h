@@ -45,6 +45,8 @@ void convert_t(int n, const double *in, float *out, hipStream_t s);
 void poly_comb(int n, const void *const X[4], const double a[4], double g, void *out, int is32,
                hipStream_t s);
 void symmetrize(int n, void *M, int is32, hipStream_t s);
+// out = a + b (FP64 a, FP32 b, FP64 out; out may alias a) and out32 = FP32(out) if non-null
+void add_mixed(int n2, const double *a, const float *b, double *out, float *out32, hipStream_t s);
 // out = sum_j coef[j] * M_j (coef on device), j < k <= 40, FP64
 void lincomb_dev(int n2, int k, const double *const *M, const double *coef, double *out, hipStream_t s);
 
