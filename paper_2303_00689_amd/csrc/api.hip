@@ -510,19 +510,24 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       mm_p(c, XLBOMD_BF16X3, S32, E32, Za32, 4.0 * b, 1, S32, 4.0 * b, E32, a + b, a + b);
       // Steps of order 2, Z <- Z (I + E), or 3, Z <- Z (I + E + E^2) with
       // E' = E E + E: two or three products for error e^2 or e^3.  Each step
-      // takes order 2 if that reaches the target, else order 3.
+      // takes order 2 if that reaches the target, else order 3.  Only the
+      // residual E = I - T Z is a cancellation (BF16x6); the correction
+      // products act on a quantity of size e and run in BF16x3, adding
+      // ~2e-5 e to the error.
       double el = e0 * e0 + 2e-5;  // + BF16x3 rounding
       const double target = std::sqrt(eps);
       for (int it = 0; it < 8 && el > target; ++it) {
         mm_p(c, XLBOMD_BF16X6, S32, Za32, E32, -4.0, 1, Za32, -1.0, nullptr, 0.0, 1.0);  // E = I - T Z
-        if (el * el + 1e-7 > target) {
-          mm_p(c, XLBOMD_BF16X6, E32, E32, Zb32, 1.0, 1, E32, 1.0);                   // E' = E E + E
+        const double e1 = el;
+        if (el * el + 1e-7 + 2e-5 * e1 > target) {
+          mm_p(c, XLBOMD_BF16X3, E32, E32, Zb32, 1.0, 1, E32, 1.0);                   // E' = E E + E
           std::swap(E32, Zb32);
-          el = el * el * el + 1e-7;
+          el = el * el * el;
         } else {
-          el = el * el + 1e-7;
+          el = el * el;
         }
-        mm_p(c, XLBOMD_BF16X6, Za32, E32, Zb32, 1.0, 1, Za32, 1.0);                   // Z + Z E
+        el += 1e-7 + 2e-5 * e1;
+        mm_p(c, XLBOMD_BF16X3, Za32, E32, Zb32, 1.0, 1, Za32, 1.0);                   // Z + Z E
         std::swap(Za32, Zb32);
       }
       // Y_{i+1} = 2 T^-1 Y by one residual correction of the split solve
@@ -725,15 +730,16 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
   c->fix_pending = wide;
   // M, and D^2, D^3 of the first-order step below, enter D only multiplied by a
   // trace correction f <~ 1e-7, and the response (of split precision in the
-  // mixed modes) takes M as it is: with a split response they are BF16x6
-  // products (relative error ~1e-7); an FP64 response keeps them FP64.
+  // mixed modes) takes M as it is: with a split response they are products in
+  // the response precision (relative error <~ 2e-5, so <~ 2e-12 in D); an FP64
+  // response keeps them FP64.
   const bool lowM = c->prec_dm == XLBOMD_FP64 && c->resp_copy;
   const size_t half = c->n2 * 4;
   void *D32 = c->w[3], *P2_32 = (char *)c->w[3] + half, *P3_32 = c->w[4];
   if (lowM) convert((int)c->n2, D, 0, D32, 1, s);
   auto dsq = [&](void *out) {  // out = D^2
     if (lowM) {
-      mm_p(c, XLBOMD_BF16X6, D32, D32, P2_32, 1.0, 1);
+      mm_p(c, c->prec_rs, D32, D32, P2_32, 1.0, 1);
       convert((int)c->n2, P2_32, 1, out, 0, s);
     } else {
       mm(c, D, D, out, 1.0, 1);
@@ -749,7 +755,7 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     dsq(D2n);
     axpby((int)c->n2, 1.0, D, -1.0, D2n, c->M, i32, s);
     if (lowM) {
-      mm_p(c, XLBOMD_BF16X6, D32, P2_32, P3_32, 1.0, 1);
+      mm_p(c, c->prec_rs, D32, P2_32, P3_32, 1.0, 1);
       convert((int)c->n2, P3_32, 1, D3n, 0, s);
     } else {
       mm(c, D, D2n, D3n, 1.0, 1);
