@@ -532,7 +532,9 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       }
       // Y_{i+1} = 2 T^-1 Y by one residual correction of the split solve
       // Y0 = 2 Z Y: R = 2 Y - T Y0 in FP64 (a cancellation), Y_{i+1} = Y0 + Z R,
-      // which leaves (I - Z T)(Y0 - 2 T^-1 Y), the square of the split error.
+      // which leaves (I - Z T)(Y0 - 2 T^-1 Y), the square of the split error
+      // (Y0 and Z R in BF16x6: with Y0 in BF16x3 the 840-atom D moves 1.1e-10
+      // from the exact Fermi matrix, errors near mu growing by 2^(L-i)).
       // Z and Y0 are functions of the FP32-rounded S and Y, so T Y0 is
       // symmetric only to ~1e-7 and R is not symmetric: R is formed in full,
       // and the split GEMM (which takes its second operand transposed) gets R^T.
