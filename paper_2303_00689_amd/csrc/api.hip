@@ -107,9 +107,13 @@ __global__ void k_sum_fixed(int m, const double *part, double *out) {
   *out = s;
 }
 
-// out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device
-__global__ void k_orth(size_t n2, int k, const double *v, const double *const *Vs, const double *c,
-                       double *out) {
+// out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device.  Two elements per
+// thread per step (16-byte loads), the loads of all k + 1 streams issued before
+// the first product; KB (4, 8 or MMAX) bounds k for the register arrays.  The
+// subtractions run in j order as in a plain loop.
+template <int KB>
+__global__ __launch_bounds__(256) void k_orth(size_t n2, int k, const double *v, const double *const *Vs,
+                                              const double *c, double *out) {
   __shared__ double cs[MMAX];
   __shared__ const double *vp[MMAX];
   if (threadIdx.x < k) {
@@ -117,11 +121,25 @@ __global__ void k_orth(size_t n2, int k, const double *v, const double *const *V
     vp[threadIdx.x] = Vs[threadIdx.x];
   }
   __syncthreads();
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
-       i += (size_t)gridDim.x * blockDim.x) {
-    double x = v[i];
-    for (int j = 0; j < k; ++j) x -= cs[j] * vp[j][i];
-    out[i] = x;
+  const size_t h = n2 / 2, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < h; q += stride) {
+    double2 x = ((const double2 *)v)[q], w[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) w[j] = ((const double2 *)vp[j])[q];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (j < k) {
+        x.x -= cs[j] * w[j].x;
+        x.y -= cs[j] * w[j].y;
+      }
+    }
+    ((double2 *)out)[q] = x;
+  }
+  if ((n2 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double x = v[n2 - 1];
+    for (int j = 0; j < k; ++j) x -= cs[j] * vp[j][n2 - 1];
+    out[n2 - 1] = x;
   }
 }
 
@@ -1014,7 +1032,13 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
       }
       for (int j0 = 0; j0 < k; j0 += 16)
         dots(n2, std::min(16, k - j0), xs + j0, ys + j0, c->dscal + S_ORTH + j0, 0, c->red, s);
-      hipLaunchKernelGGL(k_orth, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+      if (k <= 4)
+        hipLaunchKernelGGL(k_orth<4>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+      else if (k <= 8)
+        hipLaunchKernelGGL(k_orth<8>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+      else
+        hipLaunchKernelGGL(k_orth<MMAX>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH,
+                           tmp);
       std::swap(v, tmp);
     }
     {

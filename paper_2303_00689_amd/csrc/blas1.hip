@@ -166,29 +166,56 @@ struct PtrPack {
 };
 
 // All k dot products in one pass over the elements.  Pairs that repeat the
-// previous pair's x (or y) matrix reuse the loaded value, so a matrix shared
+// previous pair's x (or y) matrix reuse the loaded values, so a matrix shared
 // by consecutive pairs (the new direction in Gram-Schmidt, W_k in a row of
-// the overlap matrix) is read once.  Each thread sums its elements in the
-// same order as a pass per pair would.
-template <typename T>
+// the overlap matrix) is read once.  Each thread takes two consecutive
+// elements per step (one 16-byte load per FP64 matrix) and issues the loads
+// of all k pairs before the first product, so every stream has a load in
+// flight at once; KB (4, 8 or 16) bounds k for the register arrays.  An odd
+// last element goes to thread 0 of block 0.  The summation order is fixed.
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { typedef double2 type; };
+template <> struct Pair2<float> { typedef float2 type; };
+
+template <typename T, int KB>
 __global__ __launch_bounds__(256) void k_dots_partial(size_t n2, int k, PtrPack pp, double *part) {
+  typedef typename Pair2<T>::type P2;
   __shared__ double sh[4];
-  double v[MAXK];
+  double v[KB];
 #pragma unroll
-  for (int a = 0; a < MAXK; ++a) v[a] = 0.0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x) {
-    double xv = 0.0, yv = 0.0;
+  for (int a = 0; a < KB; ++a) v[a] = 0.0;
+  const size_t h = n2 / 2, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < h; q += stride) {
+    P2 xs[KB], ys[KB];
 #pragma unroll
-    for (int a = 0; a < MAXK; ++a) {
+    for (int a = 0; a < KB; ++a) {
       if (a < k) {
-        if (a == 0 || pp.x[a] != pp.x[a - 1]) xv = (double)((const T *)pp.x[a])[i];
-        if (a == 0 || pp.y[a] != pp.y[a - 1]) yv = (double)((const T *)pp.y[a])[i];
-        v[a] += xv * yv;
+        if (a == 0 || pp.x[a] != pp.x[a - 1])
+          xs[a] = ((const P2 *)pp.x[a])[q];
+        else
+          xs[a] = xs[a - 1];
+        if (a == 0 || pp.y[a] != pp.y[a - 1])
+          ys[a] = ((const P2 *)pp.y[a])[q];
+        else
+          ys[a] = ys[a - 1];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < KB; ++a) {
+      if (a < k) {
+        v[a] += (double)xs[a].x * (double)ys[a].x;
+        v[a] += (double)xs[a].y * (double)ys[a].y;
       }
     }
   }
+  if ((n2 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t i = n2 - 1;
 #pragma unroll
-  for (int a = 0; a < MAXK; ++a) {
+    for (int a = 0; a < KB; ++a)
+      if (a < k) v[a] += (double)((const T *)pp.x[a])[i] * (double)((const T *)pp.y[a])[i];
+  }
+#pragma unroll
+  for (int a = 0; a < KB; ++a) {
     if (a < k) {
       const double t = block_sum(v[a], sh);
       if (threadIdx.x == 0) part[(size_t)a * gridDim.x + blockIdx.x] = t;
@@ -221,6 +248,7 @@ __global__ __launch_bounds__(256) void k_trace_partial(int n, const void *M, dou
 // alpha_j = w.q_j, w <- w - alpha_j q_j - beta_{j-1} q_{j-1}, beta_j = |w|,
 // q_{j+1} = w / beta_j.  Q holds the Lanczos vectors row by row; ab[2j] and
 // ab[2j+1] receive alpha_j and beta_j.
+// The pair version reads rows as 16-byte pairs (n even, F and q 16-byte aligned).
 __global__ __launch_bounds__(256) void k_symv(int n, const double *F, const double *q, double *w) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -231,38 +259,60 @@ __global__ __launch_bounds__(256) void k_symv(int n, const double *F, const doub
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) w[row] = acc;
 }
+__global__ __launch_bounds__(256) void k_symv2(int n, const double *F, const double *q, double *w) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double2 *f = (const double2 *)(F + (size_t)row * n);
+  const double2 *q2 = (const double2 *)q;
+  double acc = 0.0;
+  for (int j = lane; j < n / 2; j += 64) {
+    const double2 a = f[j], b = q2[j];
+    acc += a.x * b.x;
+    acc += a.y * b.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) w[row] = acc;
+}
 
-__global__ __launch_bounds__(256) void k_lanczos_step(int n, int j, double *Q, const double *w,
-                                                      double *ab) {
-  __shared__ double sh[4];
-  __shared__ double bc;
+// sum over a workgroup of LB threads (a multiple of 64); the result is returned to every thread
+template <int LB>
+__device__ inline double block_sum_all(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < LB / 64; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_lanczos_step(int n, int j, double *Q, const double *w,
+                                                       double *ab) {
+  __shared__ double sh[16];
   const double *qj = Q + (size_t)j * n;
   const double *qp = j > 0 ? Q + (size_t)(j - 1) * n : nullptr;
   double *qn = Q + (size_t)(j + 1) * n;
   const double bprev = j > 0 ? ab[2 * j - 1] : 0.0;
   double a = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) a += w[i] * qj[i];
-  a = block_sum(a, sh);
-  if (threadIdx.x == 0) bc = a;
-  __syncthreads();
-  a = bc;
+  for (int i = threadIdx.x; i < n; i += 1024) a += w[i] * qj[i];
+  a = block_sum_all<1024>(a, sh);
   double b = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += 1024) {
     double v = w[i] - a * qj[i];
     if (qp) v -= bprev * qp[i];
     qn[i] = v;
     b += v * v;
   }
-  b = block_sum(b, sh);
-  __syncthreads();
+  b = block_sum_all<1024>(b, sh);
+  const double bc = sqrt(b);
   if (threadIdx.x == 0) {
-    bc = sqrt(b);
     ab[2 * j] = a;
     ab[2 * j + 1] = bc;
   }
-  __syncthreads();
   const double inv = bc > 0.0 ? 1.0 / bc : 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) qn[i] *= inv;
+  for (int i = threadIdx.x; i < n; i += 1024) qn[i] *= inv;
 }
 
 // Gershgorin: one wavefront per row
@@ -532,10 +582,21 @@ void dots(int n2, int k, const void *const *X, const void *const *Y, double *res
   }
   int nb = grid_for(n2);
   if (nb > RED_BLOCKS) nb = RED_BLOCKS;
-  if (is32)
-    hipLaunchKernelGGL(k_dots_partial<float>, dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
-  else
-    hipLaunchKernelGGL(k_dots_partial<double>, dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+  if (is32) {
+    if (k <= 4)
+      hipLaunchKernelGGL((k_dots_partial<float, 4>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+    else if (k <= 8)
+      hipLaunchKernelGGL((k_dots_partial<float, 8>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+    else
+      hipLaunchKernelGGL((k_dots_partial<float, 16>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+  } else {
+    if (k <= 4)
+      hipLaunchKernelGGL((k_dots_partial<double, 4>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+    else if (k <= 8)
+      hipLaunchKernelGGL((k_dots_partial<double, 8>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+    else
+      hipLaunchKernelGGL((k_dots_partial<double, 16>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
+  }
   hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, k, nb, partials, res);
 }
 
@@ -571,9 +632,15 @@ void convert_t(int n, const double *in, float *out, hipStream_t s) {
 }
 
 void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s) {
+  // Q is the library's (16-byte aligned, rows of even length); F may be the caller's
+  const bool pairs = n % 2 == 0 && ((uintptr_t)F % 16) == 0 && ((uintptr_t)Q % 16) == 0;
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL(k_symv, dim3((n + 3) / 4), dim3(256), 0, s, n, F, Q + (size_t)j * n, w);
-    hipLaunchKernelGGL(k_lanczos_step, dim3(1), dim3(256), 0, s, n, j, Q, w, ab);
+    const double *qj = Q + (size_t)j * n;
+    if (pairs)
+      hipLaunchKernelGGL(k_symv2, dim3((n + 3) / 4), dim3(256), 0, s, n, F, qj, w);
+    else
+      hipLaunchKernelGGL(k_symv, dim3((n + 3) / 4), dim3(256), 0, s, n, F, qj, w);
+    hipLaunchKernelGGL(k_lanczos_step, dim3(1), dim3(1024), 0, s, n, j, Q, w, ab);
   }
 }
 

@@ -51,7 +51,8 @@ void add_mixed(int n2, const double *a, const float *b, double *out, float *out3
 void lincomb_dev(int n2, int k, const double *const *M, const double *coef, double *out, hipStream_t s);
 
 // Deterministic FP64 reductions into device scalars.
-// dots: res[i] = <X_i, Y_i> (Frobenius) for i < k <= 16
+// dots: res[i] = <X_i, Y_i> (Frobenius) for i < k <= 16; every X_i, Y_i 16-byte aligned
+// (library buffers, or halves of them at offsets of 4 n^2 bytes with n = 4 N_atoms)
 void dots(int n2, int k, const void *const *X, const void *const *Y, double *res, int is32,
           double *partials, hipStream_t s);
 // res[0] = trace(M)
