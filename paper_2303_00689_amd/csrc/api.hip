@@ -556,8 +556,9 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       // Z and Y0 are functions of the FP32-rounded S and Y, so T Y0 is
       // symmetric only to ~1e-7 and R is not symmetric: R is formed in full,
       // and the split GEMM (which takes its second operand transposed) gets R^T.
-      // Y32 (the FP32 Y_i) is the previous level's by-product, except at level 0
-      void *Y32 = c->w[0], *Yn32 = E32, *Yn = Za, *R = E;
+      // Y32 (the FP32 Y_i, kept as the response's copy) is the previous level's
+      // by-product, except at level 0
+      void *Y32 = c->Yr[i], *Yn32 = E32, *Yn = Za, *R = E;
       if (i == 0) convert(n2i, Y, 0, Y32, 1, c->s);
       mm_p(c, XLBOMD_BF16X6, Za32, Y32, Yn32, 2.0, 1);         // Y0 = 2 Z Y
       convert(n2i, Yn32, 1, Yn, 0, c->s);
@@ -568,7 +569,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       // to ~1e-13 relative; every level rebuilds Y_{i+1} from the symmetric Y0,
       // so only the last one (which gives D) is symmetrised.
       add_mixed(n2i, (const double *)Yn, (const float *)C32, (double *)c->Yc[i + 1],
-                i + 1 < L ? (float *)Y32 : nullptr, c->s);
+                i + 1 < L ? (float *)c->Yr[i + 1] : nullptr, c->s);
       if (i + 1 == L) symmetrize(n, c->Yc[L], 0, c->s);
       // the FP32 Z_i is what the response needs
       convert(n2i, Za32, 1, c->Zc[i], 1, c->s);
@@ -820,7 +821,9 @@ void prepare_response(xlbomd_ctx *c) {
   // the FP64 chain with split Newton-Schulz keeps its Z_i in FP32
   const bool zc32 = c->prec_dm == XLBOMD_FP64 && c->resp_copy;
   if (c->resp_copy) {
-    for (int i = 0; i < L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, s);
+    // the mixed chain leaves its FP32 Y_i in Yr already
+    if (!zc32)
+      for (int i = 0; i < L; ++i) convert(n2, c->Yc[i], c->is32, c->Yr[i], 1, s);
     convert(n2, c->Vst, c->is32, c->Vr, 1, s);
     convert(n2, c->Pst, c->is32, c->Pr, 1, s);
     convert(n2, c->Sst, c->is32, c->Sr, 1, s);
@@ -862,8 +865,7 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   void *V1 = c->w[0], *dS = c->w[1], *dS2 = c->w[2], *Y1 = c->w[3], *G = c->w[4], *H = c->w[5],
        *Y1b = c->w[6];
   if (i32) {
-    convert((int)c->n2, F1, 0, c->w[7], 1, s);
-    axpby((int)c->n2, sc, c->w[7], 0.0, nullptr, V1, 1, s);
+    convert((int)c->n2, F1, 0, V1, 1, s, sc);
   } else {
     axpby((int)c->n2, sc, F1, 0.0, nullptr, V1, 0, s);
   }

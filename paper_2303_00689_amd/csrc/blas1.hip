@@ -85,10 +85,10 @@ __global__ __launch_bounds__(256) void k_convert_t(int n, const double *in, floa
 }
 
 template <typename TI, typename TO>
-__global__ void k_convert(size_t n2, const void *in, void *out) {
+__global__ void k_convert(size_t n2, const void *in, void *out, double scale) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2;
        i += (size_t)gridDim.x * blockDim.x)
-    ((TO *)out)[i] = (TO)((const TI *)in)[i];
+    ((TO *)out)[i] = scale == 1.0 ? (TO)((const TI *)in)[i] : (TO)(scale * (double)((const TI *)in)[i]);
 }
 
 // out = a + (double) b, and its FP32 rounding (nullable)
@@ -543,16 +543,16 @@ void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const doubl
                        y, g_dev, g, out);
 }
 
-void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s) {
+void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s, double scale) {
   const dim3 g(grid_for(n2)), b(256);
   if (in32 && out32)
-    hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (size_t)n2, in, out);
+    hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (size_t)n2, in, out, scale);
   else if (in32)
-    hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (size_t)n2, in, out);
+    hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (size_t)n2, in, out, scale);
   else if (out32)
-    hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (size_t)n2, in, out);
+    hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (size_t)n2, in, out, scale);
   else
-    hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (size_t)n2, in, out);
+    hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (size_t)n2, in, out, scale);
 }
 
 void add_mixed(int n2, const double *a, const float *b, double *out, float *out32, hipStream_t s) {

@@ -38,7 +38,8 @@ void axpby(int n2, double a, const void *x, double b, const void *y, void *out, 
 // out = a*x + b*y + g*I, with a, b, g taken from device scalars (null -> host value)
 void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const double *b_dev, double b,
                 const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s);
-void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s);
+// out = scale * in, converted (scale applied in FP64 before the rounding to out's type)
+void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s, double scale = 1.0);
 // out = in^T (n x n, FP64 in, FP32 out)
 void convert_t(int n, const double *in, float *out, hipStream_t s);
 // out = sum_{j<4} a_j X_j + g I (null X_j skipped; out may alias an X_j)
