@@ -78,7 +78,8 @@ def test_split_matmul(binding, mode, n_atoms, sym):
 def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
     """n = 3360 (15 tiles of 224 rows, 21 of 160) and n = 3392 (ragged last
     tiles): sizes at which the BF16 splits run the large-tile kernels, 224-row
-    tiles for full outputs and 160-row tiles for symmetric ones."""
+    tiles for full outputs and 160-row tiles for symmetric ones.  A second call
+    gives the same bits."""
     s = carbon_cluster(n_atoms, 2)
     h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
     n = s.n_orb
@@ -101,6 +102,10 @@ def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
     acc = 4.0 * np.sqrt(n) * 2.0**-24 * S / np.abs(ref).max()
     print(f"{mode} n={n} sym={sym} matmul rel err {err:.3e} (accumulation budget {acc:.1e})")
     assert err <= BOUND[mode]["mm"] + acc
+    C2 = torch.empty_like(C)
+    h.matmul(torch.tensor(A, device=dev), torch.tensor(B, device=dev), C2, sym_out=bool(sym))
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2)
     h.close()
 
 
