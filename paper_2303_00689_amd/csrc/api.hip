@@ -474,7 +474,9 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
 // recursion Y_{i+1} = 2 Y_i (I + 4 Y_i^2)^-1 started from a degree-9 Taylor
 // polynomial of tanh at v = -beta (F - mu)/2^(L+1); D = I/2 + Y_L.  The inverse
 // of every level is a Newton-Schulz iteration started from the best linear
-// polynomial of T = I + 4 Y^2 on its spectral interval.
+// polynomial of T = I + 4 Y^2 on its spectral interval; in the FP64 chain of
+// the mixed modes that iteration runs in split precision and Y_{i+1} takes one
+// FP64 residual correction instead.
 xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, double hi) {
   const int n = c->n;
   c->resp_ready = false;

@@ -14,7 +14,7 @@ namespace {
 constexpr int RED_BLOCKS = 1024;
 constexpr int MAXK = 16;
 // largest chemical-potential move of one Newton pass, in units of 1/beta, and
-// the bracket of the five-term series solve (the series in 1 - exp(-beta dmu)
+// the bracket of the six-term series solve (the series in 1 - exp(-beta dmu)
 // is accurate only well inside its radius of convergence)
 constexpr double MU_STEP = 1.0;
 constexpr double SERIES_STEP = 0.3;
