@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--workload", default="c840")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--drift-steps", type=int, default=6,
+                    help="free NVE steps per precision for the shadow-energy drift of the comparison")
     ap.add_argument("--init-mix", type=int, default=200, help="linear-mixing steps before MD")
     ap.add_argument("--no-report", action="store_true", help="skip the untimed report step after timing")
     ap.add_argument("--trajectory", choices=["reset", "free"], default="reset",
@@ -315,27 +317,58 @@ def main():
                           "avg_launch_us": 1e3 * fk["ms"] / max(fk["launches"], 1)},
     }
 
-    # ---- split vs FP64 at the same state (untimed)
+    # ---- split vs FP64 at the same state (untimed): D0, the response D1 to a
+    # seeded G(V), the Krylov kernel Y, forces and U at the prepared state, and
+    # the shadow-energy drift of a short free trajectory from it
     if args.prec != "fp64" and not args.no_compare:
+        restore()
         Xc = state.x_current().clone()
-        frc = {}
+        rng = np.random.default_rng(11)
+        Vd = rng.standard_normal((n, n))
+        Vd = torch.tensor(Vd + Vd.T, dtype=torch.float64, device=dev)
+        beta = 1.0 / (8.617333262e-5 * w["T_e"])
+        cmp = {}
         for pr, hh in (("split", h), ("fp64", None)):
             hnd = hh or binding.handle_for(sys_, w, prec="fp64")
             hnd.set_geometry(state.R)
             F = torch.empty_like(Xc)
             P = torch.empty_like(Xc)
             hnd.fock(Xc, F, True)
-            hnd.fermi_dm(F, P, mu=state.mu)
+            _, S = hnd.fermi_dm(F, P, mu=state.mu)
             f = torch.empty((sys_.n_atoms, 3), dtype=torch.float64, device=dev)
-            hnd.forces(P, Xc, f)
-            frc[pr] = (f.cpu().numpy(), P.cpu().numpy())
+            e = hnd.forces(P, Xc, f)
+            F1 = torch.empty_like(Xc)
+            hnd.fock(Vd, F1, False)
+            P1 = torch.empty_like(Xc)
+            hnd.dm_response(F1, P1)
+            Y = torch.empty_like(Xc)
+            hnd.krylov_kernel(Xc, P, w["m"], Y)
+            U = e[0] + e[1] + e[2] - 2.0 * S / beta
+            # drift: E_tot over a short free NVE trajectory from the prepared state
+            st = binding.MDState(R=snap[0].clone(), V=snap[1].clone(), A=snap[2].clone(), X=snap[3].clone(),
+                                 Y=snap[4].clone(), head=snap[5], mu=snap[6])
+            reps = hnd.step(st, args.drift_steps, report=True)
+            E = np.array([r["E_tot"] for r in reps])
+            tfs = w["dt"] * np.arange(1, len(E) + 1)
+            drift = float(np.polyfit(tfs, E, 1)[0]) * 1000.0 / sys_.n_atoms
+            torch.cuda.synchronize()
+            cmp[pr] = dict(P=P.cpu().numpy(), P1=P1.cpu().numpy(), Y=Y.cpu().numpy(), f=f.cpu().numpy(), U=U,
+                           drift=drift)
             if hh is None:
                 hnd.close()
-        ferr = float(np.abs(frc["split"][0] - frc["fp64"][0]).max())
-        derr = float(np.abs(frc["split"][1] - frc["fp64"][1]).max())
+        a_, b_ = cmp["split"], cmp["fp64"]
+        fro = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        W0 = float(np.linalg.norm(b_["P"] - Xc.cpu().numpy()))
+        ferr = float(np.abs(a_["f"] - b_["f"]).max())
         out["force_err_vs_fp64_eV_per_A"] = ferr
-        out["density_err_vs_fp64"] = derr
+        out["density_err_vs_fp64"] = float(np.abs(a_["P"] - b_["P"]).max())
         out["force_err_ok"] = ferr <= 1e-4
+        out["split_vs_fp64"] = {
+            "D0_maxabs": float(np.abs(a_["P"] - b_["P"]).max()) / 2.0, "D0_rel_fro": fro(a_["P"], b_["P"]),
+            "D1_rel_fro": fro(a_["P1"], b_["P1"]), "Y_rel_W0": float(np.linalg.norm(a_["Y"] - b_["Y"]) / W0),
+            "forces_maxabs_eV_per_A": ferr, "U_eV_per_atom": abs(a_["U"] - b_["U"]) / sys_.n_atoms,
+            "drift_eV_per_ps_per_atom": {"split": a_["drift"], "fp64": b_["drift"],
+                                         "steps": args.drift_steps, "trajectory": "free NVE from the prepared state"}}
 
     if not args.no_cpu_baseline:
         log("timing the oracle sample ...")
