@@ -512,12 +512,6 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
     mm(c, Y, Y, Si, 1.0, 1);
     double a, b, e0;
     cheb_lin(1.0 + 4.0 * yb * yb, a, b, e0);
-    int k = 1;
-    double e = e0 * e0;
-    while (e > eps && k < 8) {
-      e = e * e;
-      ++k;
-    }
     if (mixed) {
       // Split-precision inverse Z ~ T^-1 to ~sqrt(eps) by Newton-Schulz (it
       // corrects itself: start in BF16x3, steps in BF16x6); the FP64 accuracy
@@ -580,9 +574,21 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
       // Z1 = Z0 (I + E0), Z0 = (a + b) I + 4 b S
       mm(c, Si, E, Za, 4.0 * b, 1, Si, 4.0 * b, E, a + b, a + b);
-      for (int it = 1; it < k; ++it) {
+      // steps of order 2 (Z + Z E) where that reaches eps, else of order 3
+      // (Z + Z E' with E' = E E + E: three products for e^3)
+      void *E2 = c->w[5];
+      double el = e0 * e0;
+      for (int it = 0; it < 8 && el > eps; ++it) {
         mm(c, Si, Za, E, -4.0, 1, Za, -1.0, nullptr, 0.0, 1.0);   // E = I - T Z
-        mm(c, Za, E, Zb, 1.0, 1, Za, 1.0);                        // Z <- Z + Z E
+        const void *Ec = E;
+        if (el * el > eps) {
+          mm(c, E, E, E2, 1.0, 1, E, 1.0);                        // E' = E E + E
+          Ec = E2;
+          el = el * el * el;
+        } else {
+          el = el * el;
+        }
+        mm(c, Za, Ec, Zb, 1.0, 1, Za, 1.0);                       // Z <- Z + Z E
         std::swap(Za, Zb);
       }
     }
