@@ -115,6 +115,25 @@ def test_dm_response(case):
     assert abs(np.trace(got)) <= 1e-10 * np.abs(ref).max() * s.n_orb
 
 
+@pytest.mark.parametrize("dmu", [0.02, -0.05])
+def test_response_after_a_shifted_warm_start(case, dmu):
+    # A warm start off by dmu moves mu by a series shift of the chain (one pass
+    # when |1 - exp(-beta dmu)| <= 0.08, else Newton-Schulz passes); the
+    # response must follow the shifted chain to the FP64 bar.
+    s = case.sys
+    F = case.t(case.F)
+    P = torch.empty_like(F)
+    case.h.fermi_dm(F, P, mu=case.dm["mu"] + dmu)
+    assert _rel(case.np(P), case.dm["P"]) <= TOL
+    V = case.rng.standard_normal((s.n_orb, s.n_orb))
+    V = V + V.T
+    F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params)
+    P1 = torch.empty_like(F)
+    case.h.dm_response(case.t(F1), P1)
+    ref = density.response(case.F, F1, s.n_elec, case.beta, case.dm)
+    assert _rel(case.np(P1), ref) <= TOL
+
+
 @pytest.mark.parametrize("T_e", [30000.0, 60000.0])
 def test_hot_cluster_density_and_response(lib, T_e):
     # A narrow spectral range in units of kT (beta (eps - mu) / 2 within about
