@@ -236,6 +236,7 @@ struct xlbomd_ctx {
   bool resp_ready = false;
   void *w[8] = {};
   int L = 0;
+  int Lalloc = 0;  // chain levels with storage (grown on demand up to LMAX)
   int mu_passes = 0;
   bool chain_valid = false;
   double mu_chain = 0.0;
@@ -477,6 +478,18 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
 // polynomial of T = I + 4 Y^2 on its spectral interval; in the FP64 chain of
 // the mixed modes that iteration runs in split precision and Y_{i+1} takes one
 // FP64 residual correction instead.
+// Storage of chain levels Lalloc .. L - 1 (Y up to Y_L); levels are kept once allocated.
+bool ensure_levels(xlbomd_ctx *c, int L) {
+  const size_t mb = c->n2 * c->esz, m4 = c->n2 * 4;
+  for (int i = c->Lalloc; i < L; ++i) {
+    if (!c->Yc[i + 1] && !dev_alloc(&c->Yc[i + 1], mb)) return false;
+    if (!c->Zc[i] && !dev_alloc(&c->Zc[i], mb)) return false;
+    if (c->resp_copy && !c->Yr[i] && !dev_alloc(&c->Yr[i], m4)) return false;
+  }
+  if (L > c->Lalloc) c->Lalloc = L;
+  return true;
+}
+
 xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, double hi) {
   const int n = c->n;
   c->resp_ready = false;
@@ -485,6 +498,7 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
   int L = (int)std::ceil(std::log2(std::max(rho / VMAX, 1.0)));
   if (L < LMIN) L = LMIN;
   if (L > LMAX) return fail(c, XLBOMD_E_ARG, "spectral range too wide (needs %d levels)", L);
+  if (!ensure_levels(c, L)) return fail(c, XLBOMD_E_NOMEM, "no memory for %d chain levels", L);
   c->L = L;
   const double vb = std::min(rho / std::ldexp(1.0, L), VMAX);
   const double sc = -beta / std::ldexp(1.0, L + 1);
@@ -1249,8 +1263,7 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   A((void **)&c->lq, sizeof(double) * (LANCZOS_K + 1) * (size_t)c->n);
   A((void **)&c->lw, sizeof(double) * (size_t)c->n);
   const size_t mb = c->n2 * c->esz;
-  for (auto &p : c->Yc) A(&p, mb);
-  for (auto &p : c->Zc) A(&p, mb);
+  A(&c->Yc[0], mb);  // levels beyond the first are allocated as chains need them
   A(&c->Vst, mb);
   A(&c->Pst, mb);
   A(&c->Sst, mb);
@@ -1262,7 +1275,6 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   for (auto &p : c->f64) A((void **)&p, c->n2 * 8);
   if (c->resp_copy) {
     const size_t m4 = c->n2 * 4;
-    for (auto &p : c->Yr) A(&p, m4);
     A(&c->Vr, m4);
     A(&c->Pr, m4);
     A(&c->Sr, m4);
