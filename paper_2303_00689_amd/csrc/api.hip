@@ -384,6 +384,11 @@ xlbomd_status get_scalars(xlbomd_ctx *c, int slot, int cnt, double *out) {
   HIPCHK(c, hipStreamSynchronize(c->s));
   return XLBOMD_OK;
 }
+// two groups of slots behind one synchronisation
+xlbomd_status get_scalars2(xlbomd_ctx *c, int slot1, int cnt1, double *out1, int slot2, int cnt2, double *out2) {
+  HIPCHK(c, hipMemcpyAsync(out1, c->dscal + slot1, sizeof(double) * cnt1, hipMemcpyDeviceToHost, c->s));
+  return get_scalars(c, slot2, cnt2, out2);
+}
 
 // Newton-Schulz stopping bound (a-priori error of each inverse).  In FP64 the
 // relative error of every level's inverse passes unamplified into Y for the
@@ -434,11 +439,10 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
   const int K = std::min(LANCZOS_K, n);
   lanczos(n, K, F, c->lq, c->lw, c->dscal + S_LANC, c->s);
   double g[2], ab[2 * LANCZOS_K];
-  xlbomd_status st = get_scalars(c, S_LOHI, 2, g);
+  xlbomd_status st = get_scalars2(c, S_LOHI, 2, g, S_LANC, 2 * K, ab);
   if (st) return st;
   if (!std::isfinite(g[0]) || !std::isfinite(g[1]))
     return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
-  if ((st = get_scalars(c, S_LANC, 2 * K, ab))) return st;
   lohi[0] = g[0];
   lohi[1] = g[1];
   const double scale = std::max(std::fabs(g[0]), std::fabs(g[1]));
@@ -1094,15 +1098,13 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
     src = c->Wk[k - 1];
     if (tol > 0.0) {
       double kc[4];
-      if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
-      if ((st = get_scalars(c, S_KCTL, 4, kc))) return st;
+      if ((st = get_scalars2(c, S_KRES, 3, kres, S_KCTL, 4, kc))) return st;
       rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
       if (rel < tol || kc[3] >= 0.0) break;
     }
   }
   double kc[4];
-  if ((st = get_scalars(c, S_KRES, 3, kres))) return st;
-  if ((st = get_scalars(c, S_KCTL, 4, kc))) return st;
+  if ((st = get_scalars2(c, S_KRES, 3, kres, S_KCTL, 4, kc))) return st;
   rel = std::sqrt(std::max(kres[0], 0.0) / nw0sq);
   const int rank = kc[3] >= 0.0 ? std::min(k, (int)kc[3]) : k;
   if (k > 0) {
@@ -1454,7 +1456,8 @@ static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, x
     double e[3];
     int rank = 0;
     double rel = 0, w0 = 0, S = 0.0;
-    if ((s = evaluate_state(c, st, e, &rank, &rel, &w0, rep ? &S : nullptr))) return s;
+    // energies (a host round trip) only for a report
+    if ((s = evaluate_state(c, st, rep ? e : nullptr, &rank, &rel, &w0, rep ? &S : nullptr))) return s;
     kick_drift(3 * c->N, st->R, st->V, st->A, c->prm.dt, 0, c->s);
     if (rep) {
       // kinetic energy from V (host copy of a few KB)
