@@ -214,6 +214,34 @@ def test_md_step_matches_oracle(case, lib):
     assert reps[0]["E_tot"] == pytest.approx(rep["E_tot"], rel=1e-10)
 
 
+def test_steps_without_report_match_reported_steps(case, lib):
+    # with rep = NULL the step skips the host read of the energies; the state
+    # it leaves is the same, bit for bit (fresh handles: a handle keeps the
+    # last steps' mu for its warm start)
+    s = case.sys
+    st = dynamics.Settings(T_e=case.w["T_e"], m=case.w["m"], dt=case.w["dt"])
+    o = dynamics.init_state(s, st, case.X)
+    n = s.n_orb
+    out = []
+    for report in (True, False):
+        h = lib.handle_for(s, case.w)
+        try:
+            h.set_geometry(case.t(s.R))
+            Xr = torch.zeros((7, n, n), dtype=torch.float64, device=case.dev)
+            for k in range(7):
+                Xr[k] = case.t(o.Xhist[k])
+            state = lib.MDState(R=case.t(o.R), V=case.t(o.V), A=case.t(o.A), X=Xr, Y=case.t(o.Y), head=0,
+                                mu=o.mu)
+            h.step(state, 2, report=report)
+            torch.cuda.synchronize()
+            out.append((state.R.cpu(), state.V.cpu(), state.x_current().cpu(), state.Y.cpu(), state.mu))
+        finally:
+            h.close()
+    for x, y in zip(out[0][:4], out[1][:4]):
+        assert torch.equal(x, y)
+    assert out[0][4] == out[1][4]
+
+
 def test_original_xlbomd_step_matches_oracle(case, lib):
     # m = 0: the scaled-identity kernel K = -c I of the original XL-BOMD
     s = case.sys
