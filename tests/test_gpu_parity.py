@@ -315,6 +315,40 @@ def test_nve_energy_fluctuation_scales_as_dt_squared(lib):
     assert 3.0 < ratio < 5.5, (spans, ratio)
 
 
+@pytest.mark.parametrize("n_atoms", [1, 2, 3])
+def test_smallest_systems_density_and_response(lib, n_atoms):
+    # n = 4, 8, 12: the Lanczos bounds stop at an invariant subspace after at
+    # most n steps, and every GEMM is a single ragged tile
+    s = carbon_cluster(n_atoms, 21)
+    T_e = 3000.0
+    beta = density.beta_of(T_e)
+    n = s.n_orb
+    rng = np.random.default_rng(n_atoms)
+    X = np.eye(n) * s.n_elec / n + 0.02 * rng.standard_normal((n, n))
+    X = 0.5 * (X + X.T)
+    F = model.fock(X, s.R, s.onecenter, s.noise, s.params)
+    dm = density.density_matrix(F, s.n_elec, beta)
+    h = lib.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, T_e=T_e, m=2, dt=0.5)
+    try:
+        dev = torch.device("cuda:0")
+        t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+        h.set_geometry(t(s.R))
+        P = torch.empty((n, n), dtype=torch.float64, device=dev)
+        h.fermi_dm(t(F), P)
+        torch.cuda.synchronize()
+        assert _rel(P.cpu().numpy(), dm["P"]) <= TOL
+        V = rng.standard_normal((n, n))
+        V = V + V.T
+        F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params) if n_atoms > 1 else V
+        P1 = torch.empty_like(P)
+        h.dm_response(t(F1), P1)
+        torch.cuda.synchronize()
+        ref = density.response(F, F1, s.n_elec, beta, dm)
+        assert np.abs(P1.cpu().numpy() - ref).max() <= TOL * max(np.abs(ref).max(), 1e-3)
+    finally:
+        h.close()
+
+
 @pytest.mark.parametrize("n_atoms", [10, 50, 67])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_matmul_fp64_kernel(lib, n_atoms, sym):
