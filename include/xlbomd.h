@@ -108,7 +108,9 @@ typedef struct {
 } xlbomd_params;
 
 /* MD state of xlbomd_step, all DEVICE pointers owned by the caller.  The X
- * history is a ring of 7 matrices: X(t - k dt) lives in slot (head + k) % 7. */
+ * history is a ring of 7 matrices: X(t - k dt) lives in slot (head + k) % 7.
+ * Every call taking a state returns XLBOMD_E_ARG, touching nothing, if a
+ * pointer is null or head is outside [0, 7). */
 typedef struct {
   double *R;      /* n_atoms x 3, Angstrom                                  */
   double *V;      /* n_atoms x 3, Angstrom/fs                               */

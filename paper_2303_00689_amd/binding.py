@@ -250,8 +250,9 @@ class Handle:
     def step_langevin(self, state: MDState, xi, gamma, T_ion, report=True):
         """len(xi) / (3 n_atoms) Langevin steps; xi: device float64 standard normals."""
         import torch
-        if xi.dtype != torch.float64 or not xi.is_contiguous() or xi.numel() % (3 * self.n_atoms):
-            raise XLBOMDError("xi must be a contiguous float64 tensor of n_steps x n_atoms x 3")
+        if (not isinstance(xi, torch.Tensor) or not xi.is_cuda or xi.dtype != torch.float64
+                or not xi.is_contiguous() or xi.numel() % (3 * self.n_atoms)):
+            raise XLBOMDError("xi must be a contiguous float64 device tensor of n_steps x n_atoms x 3")
         n_steps = xi.numel() // (3 * self.n_atoms)
         sc = state._c(self)
         reps = (Report * max(n_steps, 1))() if report else None

@@ -1384,8 +1384,13 @@ xlbomd_status xlbomd_forces(xlbomd_handle c, const double *P0, const double *X, 
   return XLBOMD_OK;
 }
 
+// an MD state with every buffer present and its ring slot inside the history
+static bool state_ok(const xlbomd_md_state *st) {
+  return st && st->R && st->V && st->A && st->X && st->Y && st->head >= 0 && st->head < 7;
+}
+
 xlbomd_status xlbomd_integrate(xlbomd_handle c, xlbomd_md_state *st) {
-  if (!c || !st || !st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+  if (!c || !state_ok(st)) return XLBOMD_E_ARG;
   const int n2 = (int)c->n2;
   const double *Xk[7];
   for (int k = 0; k < 7; ++k) Xk[k] = st->X + (size_t)((st->head + k) % 7) * c->n2;
@@ -1423,7 +1428,7 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
 }
 
 xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
-  if (!c || !st || !st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
+  if (!c || !state_ok(st)) return XLBOMD_E_ARG;
   c->mu_prev = NAN;
   // replicate X(t0) into every history slot
   const double *X0 = st->X + (size_t)st->head * c->n2;
@@ -1439,10 +1444,10 @@ xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
 // the steps of xlbomd_step and xlbomd_step_langevin (xi == nullptr: NVE)
 static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep,
                               double c1, double c2, const double *xi) {
+  if (!state_ok(st)) return XLBOMD_E_ARG;
   for (int k = 0; k < n_steps; ++k) {
     xlbomd_status s;
     if (xi) {
-      if (!st->R || !st->V || !st->A || !st->X || !st->Y) return XLBOMD_E_ARG;
       const double *Xk[7];
       for (int j = 0; j < 7; ++j) Xk[j] = st->X + (size_t)((st->head + j) % 7) * c->n2;
       const int nh = (st->head + 6) % 7;

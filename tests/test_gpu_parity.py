@@ -369,3 +369,30 @@ def test_matmul_fp64_kernel(lib, n_atoms, sym):
     ref = A @ B
     assert _rel(C.cpu().numpy(), ref) <= 1e-13
     h.close()
+
+
+def test_state_arguments_are_checked_before_any_work(lib):
+    """A ring slot outside the 7-matrix history, or host noise for the
+    Langevin step, is refused before any kernel runs; the state is untouched."""
+    case = Case(lib, "c10")
+    s = case.sys
+    n = s.n_orb
+    st = dynamics.Settings(T_e=case.w["T_e"], m=case.w["m"], dt=case.w["dt"])
+    o = dynamics.init_state(s, st, case.X)
+    Xr = torch.stack([case.t(o.Xhist[k]) for k in range(7)])
+    for head in (-1, 7, 100):
+        state = lib.MDState(R=case.t(o.R), V=case.t(o.V), A=case.t(o.A), X=Xr.clone(), Y=case.t(o.Y),
+                            head=head, mu=o.mu)
+        X0, R0 = state.X.clone(), state.R.clone()
+        xi = torch.zeros((1, s.n_atoms, 3), dtype=torch.float64, device=case.dev)
+        for call in (lambda: case.h.integrate(state), lambda: case.h.md_init(state),
+                     lambda: case.h.step(state, 1), lambda: case.h.step_langevin(state, xi, 0.01, 300.0)):
+            with pytest.raises(lib.XLBOMDError):
+                call()
+        torch.cuda.synchronize()
+        assert state.head == head
+        assert torch.equal(state.X, X0) and torch.equal(state.R, R0)
+    state = lib.MDState(R=case.t(o.R), V=case.t(o.V), A=case.t(o.A), X=Xr, Y=case.t(o.Y), head=0, mu=o.mu)
+    with pytest.raises(lib.XLBOMDError):
+        case.h.step_langevin(state, torch.zeros((1, s.n_atoms, 3), dtype=torch.float64), 0.01, 300.0)
+    case.h.close()
