@@ -172,6 +172,14 @@ xlbomd_status xlbomd_fock(xlbomd_handle h, const double *P, double *F, int inclu
 xlbomd_status xlbomd_fermi_dm(xlbomd_handle h, const double *F, double *mu, double *P,
                               double *entropy);
 
+/* Spectral bounds of F, the step that fixes the chain depth: on return
+ * lohi[0] <= every eigenvalue of F <= lohi[1].  Gershgorin discs, tightened by
+ * min(32, n) Lanczos steps: the extreme Ritz values widened by their residual
+ * bounds beta_k |s_k| and by 1e-3 of the Ritz spread.  F: DEVICE n x n
+ * symmetric; lohi: HOST, 2 doubles.  Synchronises the handle's stream.
+ * XLBOMD_E_NONFINITE if F holds a non-finite entry. */
+xlbomd_status xlbomd_spectral_bounds(xlbomd_handle h, const double *F, double *lohi);
+
 /* canonical first-order response P1 = 2 dD/dlambda of D[F + lambda F1] at the
  * state of the last xlbomd_fermi_dm (eq. 36), with mu re-solved (Tr P1 = 0).
  * F1, P1: DEVICE n x n.  XLBOMD_E_STATE if no chain is cached. */

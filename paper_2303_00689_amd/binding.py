@@ -25,7 +25,7 @@ STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
 
 # symbols declared in include/xlbomd.h
 SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
-           "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm",
+           "xlbomd_set_geometry", "xlbomd_hcore", "xlbomd_fock", "xlbomd_fermi_dm", "xlbomd_spectral_bounds",
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
            "xlbomd_step", "xlbomd_step_langevin", "xlbomd_ensemble_step", "xlbomd_md_init", "xlbomd_scf",
            "xlbomd_matmul",
@@ -84,6 +84,7 @@ def load():
     lib.xlbomd_hcore.argtypes = [vp, vp]
     lib.xlbomd_fock.argtypes = [vp, vp, vp, i]
     lib.xlbomd_fermi_dm.argtypes = [vp, vp, pd, vp, pd]
+    lib.xlbomd_spectral_bounds.argtypes = [vp, vp, pd]
     lib.xlbomd_dm_response.argtypes = [vp, vp, vp]
     lib.xlbomd_krylov_kernel.argtypes = [vp, vp, vp, i, d, vp, pi, pd]
     lib.xlbomd_forces.argtypes = [vp, vp, vp, vp, pd]
@@ -210,6 +211,12 @@ class Handle:
         self._check(self.lib.xlbomd_fermi_dm(self.h, self._mat(F), C.byref(m), self._mat(P), C.byref(S)),
                     "fermi_dm")
         return m.value, S.value
+
+    def spectral_bounds(self, F):
+        """(lo, hi) enclosing the spectrum of F (the chain-depth step)."""
+        lohi = (C.c_double * 2)()
+        self._check(self.lib.xlbomd_spectral_bounds(self.h, self._mat(F), lohi), "spectral_bounds")
+        return lohi[0], lohi[1]
 
     def dm_response(self, F1, P1):
         self._check(self.lib.xlbomd_dm_response(self.h, self._mat(F1), self._mat(P1)), "dm_response")

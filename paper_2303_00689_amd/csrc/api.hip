@@ -1350,6 +1350,14 @@ xlbomd_status xlbomd_fermi_dm(xlbomd_handle c, const double *F, double *mu, doub
   return XLBOMD_OK;
 }
 
+xlbomd_status xlbomd_spectral_bounds(xlbomd_handle c, const double *F, double *lohi) {
+  if (!c || !F || !lohi) return c ? fail(c, XLBOMD_E_ARG, "bad spectral_bounds arguments") : XLBOMD_E_ARG;
+  xlbomd_status st = spectral_bounds(c, F, lohi);
+  if (st) return st;
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
 xlbomd_status xlbomd_dm_response(xlbomd_handle c, const double *F1, double *P1) {
   if (!c || !F1 || !P1 || F1 == P1) return c ? fail(c, XLBOMD_E_ARG, "bad response arguments") : XLBOMD_E_ARG;
   if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");

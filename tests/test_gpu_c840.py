@@ -69,6 +69,7 @@ def _run(binding, ref, prec):
         X = _dev(ref.X)
         F = torch.empty_like(X)
         h.fock(X, F, True)
+        lohi = np.array(h.spectral_bounds(F))
         P = torch.empty_like(X)
         h.fermi_dm(F, P)
         P1 = torch.empty_like(X)
@@ -76,7 +77,9 @@ def _run(binding, ref, prec):
         frc = torch.empty((s.n_atoms, 3), dtype=torch.float64, device="cuda:0")
         h.forces(P, X, frc)
         torch.cuda.synchronize()
-        return {k: v.cpu().numpy() for k, v in dict(F=F, P=P, P1=P1, frc=frc).items()}
+        out = {k: v.cpu().numpy() for k, v in dict(F=F, P=P, P1=P1, frc=frc).items()}
+        out["lohi"] = lohi
+        return out
     finally:
         h.close()
 
@@ -88,6 +91,12 @@ def test_fp64_step_parts_match_oracle(binding, ref):
     for k, v in errs.items():
         assert v <= TOL, (k, v)
     assert abs(np.trace(out["P"]) - ref.sys.n_elec) <= 1e-11 * ref.sys.n_elec
+    # the spectral bounds of the chain-depth step enclose the spectrum, tightly
+    lo, hi = out["lohi"]
+    eps = ref.dm["eps"]
+    print(f"bounds [{lo:.4f}, {hi:.4f}] eV, spectrum [{eps.min():.4f}, {eps.max():.4f}] eV")
+    assert lo <= eps.min() and hi >= eps.max()
+    assert hi - lo <= 1.05 * (eps.max() - eps.min())
 
 
 @pytest.mark.parametrize("prec", ["dm64_bf16x3", "dm64_fp16x3"])

@@ -99,6 +99,21 @@ def test_fermi_dm_cold_and_warm(case):
     assert _rel(case.np(P), case.dm["P"]) <= TOL
 
 
+def _check_bounds(lo, hi, F, eps, slack=1.05):
+    """Enclosure of the spectrum, inside the Gershgorin interval, and tight."""
+    r = np.abs(F).sum(axis=1) - np.abs(np.diag(F))
+    g_lo, g_hi = float(np.min(np.diag(F) - r)), float(np.max(np.diag(F) + r))
+    spread = float(eps.max() - eps.min())
+    assert lo <= eps.min() and hi >= eps.max(), (lo, hi, eps.min(), eps.max())
+    assert lo >= g_lo and hi <= g_hi
+    assert hi - lo <= slack * spread, (hi - lo, spread)
+
+
+def test_spectral_bounds(case):
+    lo, hi = case.h.spectral_bounds(case.t(case.F))
+    _check_bounds(lo, hi, case.F, case.dm["eps"])
+
+
 def test_dm_response(case):
     s = case.sys
     F = case.t(case.F)
@@ -333,6 +348,8 @@ def test_smallest_systems_density_and_response(lib, n_atoms):
         dev = torch.device("cuda:0")
         t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
         h.set_geometry(t(s.R))
+        lo, hi = h.spectral_bounds(t(F))
+        _check_bounds(lo, hi, F, dm["eps"], slack=1.01)
         P = torch.empty((n, n), dtype=torch.float64, device=dev)
         h.fermi_dm(t(F), P)
         torch.cuda.synchronize()
