@@ -71,7 +71,7 @@ def _run(binding, ref, prec):
         h.fock(X, F, True)
         lohi = np.array(h.spectral_bounds(F))
         P = torch.empty_like(X)
-        h.fermi_dm(F, P)
+        mu, _ = h.fermi_dm(F, P)
         P1 = torch.empty_like(X)
         h.dm_response(_dev(ref.F1), P1)
         frc = torch.empty((s.n_atoms, 3), dtype=torch.float64, device="cuda:0")
@@ -79,6 +79,7 @@ def _run(binding, ref, prec):
         torch.cuda.synchronize()
         out = {k: v.cpu().numpy() for k, v in dict(F=F, P=P, P1=P1, frc=frc).items()}
         out["lohi"] = lohi
+        out["mu"] = mu
         return out
     finally:
         h.close()
@@ -91,6 +92,9 @@ def test_fp64_step_parts_match_oracle(binding, ref):
     for k, v in errs.items():
         assert v <= TOL, (k, v)
     assert abs(np.trace(out["P"]) - ref.sys.n_elec) <= 1e-11 * ref.sys.n_elec
+    # mu to what the electron count fixes: dN / (dN/dmu), dN/dmu = 2 beta sum f(1 - f)
+    f = ref.dm["f"]
+    assert abs(out["mu"] - ref.dm["mu"]) <= 1e-11 * ref.sys.n_elec / (2.0 * ref.beta * np.sum(f * (1.0 - f)))
     # the spectral bounds of the chain-depth step enclose the spectrum, tightly
     lo, hi = out["lohi"]
     eps = ref.dm["eps"]

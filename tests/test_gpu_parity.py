@@ -94,6 +94,9 @@ def test_fermi_dm_cold_and_warm(case):
     assert _rel(Pg, case.dm["P"]) <= TOL
     assert S == pytest.approx(density.entropy(case.dm["f"]), rel=1e-9, abs=1e-9)
     assert abs(np.trace(Pg) - s.n_elec) <= 1e-11 * s.n_elec
+    # mu (eq. 8) to what the electron count fixes: dN / (dN/dmu), dN/dmu = 2 beta sum f(1 - f)
+    f = case.dm["f"]
+    assert abs(mu - case.dm["mu"]) <= 1e-11 * s.n_elec / (2.0 * case.beta * np.sum(f * (1.0 - f))) + 1e-12
     # warm start from a slightly wrong mu lands on the same density matrix
     mu2, _ = case.h.fermi_dm(F, P, mu=mu + 0.02)
     assert _rel(case.np(P), case.dm["P"]) <= TOL
