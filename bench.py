@@ -242,13 +242,15 @@ def main():
     # few steps and its per-step cost drifts with it.  By default every step
     # therefore starts from the same prepared state (t0 after md_init); the
     # restore is a few device copies on the library's stream, inside the
-    # timed region.
-    snap = (state.R.clone(), state.V.clone(), state.A.clone(), state.X.clone(), state.Y.clone(),
+    # timed region.  A step writes the nuclei, Y and the one ring slot of X it
+    # advances into, (head + 6) % 7; those are what the restore puts back.
+    slot = (state.head + 6) % 7
+    snap = (state.R.clone(), state.V.clone(), state.A.clone(), state.X[slot].clone(), state.Y.clone(),
             state.head, state.mu)
 
     def restore():
         if args.trajectory == "reset":
-            for dst, src in zip((state.R, state.V, state.A, state.X, state.Y), snap[:5]):
+            for dst, src in zip((state.R, state.V, state.A, state.X[slot], state.Y), snap[:5]):
                 dst.copy_(src)
             state.head, state.mu = snap[5], snap[6]
 
@@ -322,6 +324,7 @@ def main():
     # the shadow-energy drift of a short free trajectory from it
     if args.prec != "fp64" and not args.no_compare:
         restore()
+        Xsnap = state.X.clone()  # the whole prepared history
         Xc = state.x_current().clone()
         rng = np.random.default_rng(11)
         Vd = rng.standard_normal((n, n))
@@ -345,7 +348,7 @@ def main():
             hnd.krylov_kernel(Xc, P, w["m"], Y)
             U = e[0] + e[1] + e[2] - 2.0 * S / beta
             # drift: E_tot over a short free NVE trajectory from the prepared state
-            st = binding.MDState(R=snap[0].clone(), V=snap[1].clone(), A=snap[2].clone(), X=snap[3].clone(),
+            st = binding.MDState(R=snap[0].clone(), V=snap[1].clone(), A=snap[2].clone(), X=Xsnap.clone(),
                                  Y=snap[4].clone(), head=snap[5], mu=snap[6])
             reps = hnd.step(st, args.drift_steps, report=True)
             E = np.array([r["E_tot"] for r in reps])
