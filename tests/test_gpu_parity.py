@@ -97,9 +97,11 @@ def test_fermi_dm_cold_and_warm(case):
     # mu (eq. 8) to what the electron count fixes: dN / (dN/dmu), dN/dmu = 2 beta sum f(1 - f)
     f = case.dm["f"]
     assert abs(mu - case.dm["mu"]) <= 1e-11 * s.n_elec / (2.0 * case.beta * np.sum(f * (1.0 - f))) + 1e-12
-    # warm start from a slightly wrong mu lands on the same density matrix
-    mu2, _ = case.h.fermi_dm(F, P, mu=mu + 0.02)
-    assert _rel(case.np(P), case.dm["P"]) <= TOL
+    # warm start from a slightly wrong mu lands on the same density matrix, and
+    # so does one far off (clamped shift passes, or bisection with new chains)
+    for off in (0.02, 1.0, -3.0):
+        case.h.fermi_dm(F, P, mu=mu + off)
+        assert _rel(case.np(P), case.dm["P"]) <= TOL, off
 
 
 def _check_bounds(lo, hi, F, eps, slack=1.05):
