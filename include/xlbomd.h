@@ -85,7 +85,7 @@ typedef struct {
  * repacked into the library's tile-major device layout) and may be freed
  * afterwards. */
 typedef struct {
-  int n_atoms;               /* >= 1                                                 */
+  int n_atoms;               /* 1 .. 8191 (n^2 < 2^30 elements per matrix)           */
   double n_elec;             /* N_e, 0 < N_e < 2n                                     */
   const double *onecenter;   /* host, n_atoms x 5: Gss, Gsp, Gpp, Gp2, Hsp (eV)       */
   const float *noise55;      /* host, n_pair x 55, packed symmetric blocks, pair order */

@@ -1219,7 +1219,10 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
                             xlbomd_handle *out) {
   if (!sys || !prm || !out) return XLBOMD_E_ARG;
   *out = nullptr;
-  if (sys->n_atoms < 1 || !sys->onecenter || (sys->n_atoms > 1 && !sys->noise55)) return XLBOMD_E_ARG;
+  // n = 4 n_atoms <= 32764: element counts n^2 stay below 2^30 (32-bit in the
+  // element-wise kernels) and n within the split GEMM's 16-bit tile indexing
+  if (sys->n_atoms < 1 || sys->n_atoms > 8191 || !sys->onecenter || (sys->n_atoms > 1 && !sys->noise55))
+    return XLBOMD_E_ARG;
   const double n = 4.0 * sys->n_atoms;
   if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
   if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6 ||
@@ -1246,7 +1249,6 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   c->resp_copy = c->prec_dm != c->prec_rs;
   c->esz = c->is32 ? 4 : 8;
   const int N = c->N, T = (N + 15) / 16;
-  const int ntp = T * (T + 1) / 2;
   bool ok = true;
   auto A = [&](void **p, size_t bytes) { ok = ok && dev_alloc(p, bytes); };
   A((void **)&c->R, sizeof(double) * 3 * N);
@@ -1289,7 +1291,6 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
     xlbomd_destroy(c);
     return XLBOMD_E_NOMEM;
   }
-  (void)ntp;
   if (hipMemcpy(c->onecenter, sys->onecenter, sizeof(double) * 5 * N, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->j55, sys->model.j55, sizeof(double) * 55, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess || !lanczos_start(c)) {
@@ -1303,10 +1304,16 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
       xlbomd_destroy(c);
       return XLBOMD_E_NOMEM;
     }
-    hipMemcpy(tmp, sys->noise55, sizeof(float) * npair * 55, hipMemcpyHostToDevice);
-    repack_noise(N, tmp, c->noise_t, c->s);
-    hipStreamSynchronize(c->s);
+    bool copied = hipMemcpy(tmp, sys->noise55, sizeof(float) * npair * 55, hipMemcpyHostToDevice) == hipSuccess;
+    if (copied) {
+      repack_noise(N, tmp, c->noise_t, c->s);
+      copied = hipStreamSynchronize(c->s) == hipSuccess;
+    }
     hipFree(tmp);
+    if (!copied) {
+      xlbomd_destroy(c);
+      return XLBOMD_E_HIP;
+    }
   }
   if (hipGetLastError() != hipSuccess) {
     xlbomd_destroy(c);
