@@ -195,8 +195,11 @@ __device__ __forceinline__ void gemm_f64_big_body(GemmArgs p, int TI, int TJ) {
   else
     tile_of_rect_sym(blockIdx.x, TI, TJ, bi, bj);
   const int i0 = bi * FT, j0 = bj * TN;
-  __shared__ double sa[FSTAGE];
-  __shared__ double sb[FSTAGE];
+  // a stage holds the A rows (padded) and the B panel; 128 x 64 tiles need
+  // only half the B space, which lets three workgroups share a CU's LDS
+  constexpr int STAGE = TN == FT ? FSTAGE : FK * FROW + FK * TN;
+  __shared__ double sa[STAGE];
+  __shared__ double sb[STAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -349,9 +352,16 @@ __device__ __forceinline__ void gemm_f64_big_body(GemmArgs p, int TI, int TJ) {
   }
 }
 
-template <int BTRANS, int TN>
+template <int BTRANS>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64_big(GemmArgs p, int TI, int TJ) {
-  gemm_f64_big_body<BTRANS, TN>(p, TI, TJ);
+  gemm_f64_big_body<BTRANS, FT>(p, TI, TJ);
+}
+
+// the 128 x 64 tiles of symmetric outputs: 52 KB of LDS and 104 VGPRs, so
+// three workgroups share a CU and the 729 tiles at n = 3360 run in one round
+template <int BTRANS>
+__global__ __launch_bounds__(256, 3) void k_gemm_f64_half(GemmArgs p, int TI, int TJ) {
+  gemm_f64_big_body<BTRANS, 64>(p, TI, TJ);
 }
 
 }  // namespace
@@ -365,15 +375,15 @@ void gemm_f64(const GemmArgs &a, hipStream_t s) {
       const int TJ = (a.n + 63) / 64;
       const int blocks = tile_count_rect_sym(TI, TJ);
       if (a.btrans)
-        hipLaunchKernelGGL((k_gemm_f64_big<1, 64>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
+        hipLaunchKernelGGL((k_gemm_f64_half<1>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
       else
-        hipLaunchKernelGGL((k_gemm_f64_big<0, 64>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
+        hipLaunchKernelGGL((k_gemm_f64_half<0>), dim3(blocks), dim3(256), 0, s, a, TI, TJ);
     } else {
       const int blocks = tile_count(TI, 0);
       if (a.btrans)
-        hipLaunchKernelGGL((k_gemm_f64_big<1, 128>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
+        hipLaunchKernelGGL((k_gemm_f64_big<1>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
       else
-        hipLaunchKernelGGL((k_gemm_f64_big<0, 128>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
+        hipLaunchKernelGGL((k_gemm_f64_big<0>), dim3(blocks), dim3(256), 0, s, a, TI, TI);
     }
     return;
   }
