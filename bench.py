@@ -48,11 +48,15 @@ def make_state(binding, torch, sys_, X0, dev):
                            mu=float("nan"))
 
 
-def cpu_baseline(sys_, w, X):
+def cpu_baseline(sys_, w, X, threads=0):
     """Oracle (plain FP64 NumPy) on a bounded sample of the same step: one Fock
     build, one density matrix by eigendecomposition, one Krylov direction
     (G(V) plus canonical response) and the forces; the step time is
-    t_fock + t_dm + m * t_dir + t_forces."""
+    t_fock + t_dm + m * t_dir + t_forces.  threads > 0 limits the BLAS pools."""
+    if threads > 0:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=threads):
+            return cpu_baseline(sys_, w, X)
     import numpy as np
     from oracle import model, density, dynamics
     try:
@@ -174,6 +178,7 @@ def main():
     ap.add_argument("--prec", default="dm64_bf16x3", choices=MODES)
     ap.add_argument("--workload", default="c840")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="BLAS threads of the oracle leg (0: all)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--drift-steps", type=int, default=6,
                     help="free NVE steps per precision for the shadow-energy drift of the comparison")
@@ -375,7 +380,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("timing the oracle sample ...")
-        out["cpu_baseline"] = cpu_baseline(sys_, w, state.x_current().cpu().numpy())
+        out["cpu_baseline"] = cpu_baseline(sys_, w, state.x_current().cpu().numpy(), args.cpu_threads)
     h.close()
     print(json.dumps(out))
 
