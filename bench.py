@@ -59,9 +59,13 @@ def cpu_baseline(sys_, w, X, threads=0):
             return cpu_baseline(sys_, w, X)
     import numpy as np
     from oracle import model, density, dynamics
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        pools = threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in pools] + [1])
+        blas = ", ".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in pools
+                                 if i.get("user_api") == "blas"})) or blas
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
     p = sys_.params
@@ -80,6 +84,7 @@ def cpu_baseline(sys_, w, X, threads=0):
     t4 = time.perf_counter()
     t_step = (t1 - t0) + (t2 - t1) + w["m"] * (t3 - t2) + (t4 - t3)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "host": {"cpus": os.cpu_count(), "blas": blas},
             "sample": (f"one oracle step at the 840-atom state assembled from timed parts: Fock build "
                        f"{t1 - t0:.1f} s, eigendecomposition density matrix {t2 - t1:.1f} s, one Krylov "
                        f"direction (G(V) + Loewner response) {t3 - t2:.1f} s x m={w['m']}, forces "
