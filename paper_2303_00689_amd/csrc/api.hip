@@ -916,13 +916,8 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   trace(n, H, c->dscal + S_TRR, i32, c->red, s);
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
                      c->dscal + S_CAN);
-  axpbyI_dev(n, nullptr, 2.0, H, c->dscal + S_CAN, 0.0, Mr, nullptr, 0.0, G, i32, s);
-  // b = 2 * (-TrR/TrM) -> scale M term by 2 as well
-  axpbyI_dev(n, nullptr, 1.0, G, c->dscal + S_CAN, 0.0, Mr, nullptr, 0.0, G, i32, s);
-  if (i32)
-    convert((int)c->n2, G, 1, P1, 0, s);
-  else
-    HIPCHK(c, hipMemcpyAsync(P1, G, c->n2 * 8, hipMemcpyDeviceToDevice, s));
+  // P1 = 2 (R + s M), s = -Tr R / Tr M, straight into the caller's FP64 buffer
+  canon_out((int)c->n2, H, Mr, c->dscal + S_CAN, P1, i32, s);
   return XLBOMD_OK;
 }
 
