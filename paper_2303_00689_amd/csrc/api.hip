@@ -876,8 +876,9 @@ void prepare_response(xlbomd_ctx *c) {
   c->resp_ready = true;
 }
 
-// canonical response of the cached chain to F1 (FP64, spin-summed F1): P1 = 2 D1
-xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
+// canonical response of the cached chain to F1 (FP64, spin-summed F1): P1 = 2 D1,
+// or P1 = 2 D1 - sub when sub is given (the Krylov kernel's J V = P1[G(V)] - V)
+xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1, const double *sub = nullptr) {
   const int n = c->n, i32 = c->rs32, L = c->L;
   hipStream_t s = c->s;
   // the Fermi-chain cache itself, or its response-precision copy
@@ -917,7 +918,7 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1) {
   hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
                      c->dscal + S_CAN);
   // P1 = 2 (R + s M), s = -Tr R / Tr M, straight into the caller's FP64 buffer
-  canon_out((int)c->n2, H, Mr, c->dscal + S_CAN, P1, i32, s);
+  canon_out((int)c->n2, H, Mr, c->dscal + S_CAN, sub, P1, i32, s);
   return XLBOMD_OK;
 }
 
@@ -1015,7 +1016,7 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
   if (m < 0 || m > MMAX) return fail(c, XLBOMD_E_ARG, "m must be in [0, %d]", MMAX);
   if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");
   if ((st = ensure_krylov(c, m))) return st;
-  double *W0 = c->f64[0], *v = c->f64[1], *tmp = c->f64[2], *F1 = c->f64[3], *P1 = c->f64[4];
+  double *W0 = c->f64[0], *v = c->f64[1], *tmp = c->f64[2], *F1 = c->f64[3];
   axpby(n2, 1.0, P0, -1.0, X, W0, 0, s);
   {
     const void *a[1] = {W0};
@@ -1072,8 +1073,7 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
     axpbyI_dev(c->n, ctl + 2, 0.0, v, nullptr, 0.0, nullptr, nullptr, 0.0, c->Vk[k], 0, s);
     // W_k = J V_k = P1[G(V_k)] - V_k
     fock_t(c, c->Vk[k], F1, 0);
-    if ((st = response(c, F1, P1))) return st;
-    axpby(n2, 1.0, P1, -1.0, c->Vk[k], c->Wk[k], 0, s);
+    if ((st = response(c, F1, c->Wk[k], c->Vk[k]))) return st;
     {
       const void *xs[MMAX + 1], *ys[MMAX + 1];
       for (int j = 0; j <= k; ++j) {

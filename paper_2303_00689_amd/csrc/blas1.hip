@@ -51,13 +51,17 @@ __global__ void k_axpbyI(int n, const double *a_dev, double a, const void *x, co
   }
 }
 
-// out = 2 (H + s M) in FP64 from H, M of element type T, s a device scalar:
-// the canonical response written to the caller in one pass
+// out = 2 (H + s M) - sub in FP64 from H, M of element type T, s a device
+// scalar, sub FP64 or null: the canonical response written to the caller in
+// one pass (with the Krylov kernel's - V folded in)
 template <typename T>
-__global__ void k_canon_out(size_t n2, const void *H, const void *M, const double *s_dev, double *out) {
+__global__ void k_canon_out(size_t n2, const void *H, const void *M, const double *s_dev, const double *sub,
+                            double *out) {
   const double sv = *s_dev;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x)
-    out[i] = 2.0 * (ld<T>(H, i) + sv * ld<T>(M, i));
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n2; i += (size_t)gridDim.x * blockDim.x) {
+    const double r = 2.0 * (ld<T>(H, i) + sv * ld<T>(M, i));
+    out[i] = sub ? r - sub[i] : r;
+  }
 }
 
 // out = sum_j a_j X_j + g I over four matrices (null X_j skipped); out may
@@ -564,11 +568,14 @@ void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t
     hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, s, (size_t)n2, in, out, scale);
 }
 
-void canon_out(int n2, const void *H, const void *M, const double *s_dev, double *out, int is32, hipStream_t s) {
+void canon_out(int n2, const void *H, const void *M, const double *s_dev, const double *sub, double *out,
+               int is32, hipStream_t s) {
   if (is32)
-    hipLaunchKernelGGL(k_canon_out<float>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, H, M, s_dev, out);
+    hipLaunchKernelGGL(k_canon_out<float>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, H, M, s_dev, sub,
+                       out);
   else
-    hipLaunchKernelGGL(k_canon_out<double>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, H, M, s_dev, out);
+    hipLaunchKernelGGL(k_canon_out<double>, dim3(grid_for(n2)), dim3(256), 0, s, (size_t)n2, H, M, s_dev, sub,
+                       out);
 }
 
 void add_mixed(int n2, const double *a, const float *b, double *out, float *out32, hipStream_t s) {

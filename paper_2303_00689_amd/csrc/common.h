@@ -40,8 +40,10 @@ void axpbyI_dev(int n, const double *a_dev, double a, const void *x, const doubl
                 const void *y, const double *g_dev, double g, void *out, int is32, hipStream_t s);
 // out = scale * in, converted (scale applied in FP64 before the rounding to out's type)
 void convert(int n2, const void *in, int in32, void *out, int out32, hipStream_t s, double scale = 1.0);
-// out = 2 (H + s M), FP64 out; H, M FP32 (is32) or FP64; s a device scalar
-void canon_out(int n2, const void *H, const void *M, const double *s_dev, double *out, int is32, hipStream_t s);
+// out = 2 (H + s M) - sub, FP64 out; H, M FP32 (is32) or FP64; s a device
+// scalar; sub FP64 or null (then nothing is subtracted)
+void canon_out(int n2, const void *H, const void *M, const double *s_dev, const double *sub, double *out,
+               int is32, hipStream_t s);
 // out = in^T (n x n, FP64 in, FP32 out)
 void convert_t(int n, const double *in, float *out, hipStream_t s);
 // out = sum_{j<4} a_j X_j + g I (null X_j skipped; out may alias an X_j)
