@@ -1046,31 +1046,34 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
   double rel = 1.0;
   double kres[3] = {0.0, 0.0, 0.0};
   for (; k < m;) {
-    // classical Gram-Schmidt applied twice
-    HIPCHK(c, hipMemcpyAsync(v, src, c->n2 * 8, hipMemcpyDeviceToDevice, s));
+    // classical Gram-Schmidt applied twice; the sweeps read the previous W (or
+    // W0) in place and write the two work vectors in turn
+    const double *cur = src;
+    double *out = v;
     for (int sweep = 0; sweep < 2 && k > 0; ++sweep) {
       const void *xs[MMAX], *ys[MMAX];
       for (int j = 0; j < k; ++j) {
         xs[j] = c->Vk[j];
-        ys[j] = v;
+        ys[j] = cur;
       }
       for (int j0 = 0; j0 < k; j0 += 16)
         dots(n2, std::min(16, k - j0), xs + j0, ys + j0, c->dscal + S_ORTH + j0, 0, c->red, s);
       if (k <= 4)
-        hipLaunchKernelGGL(k_orth<4>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+        hipLaunchKernelGGL(k_orth<4>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH, out);
       else if (k <= 8)
-        hipLaunchKernelGGL(k_orth<8>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH, tmp);
+        hipLaunchKernelGGL(k_orth<8>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH, out);
       else
-        hipLaunchKernelGGL(k_orth<MMAX>, dim3(2048), dim3(256), 0, s, c->n2, k, v, c->dptr, c->dscal + S_ORTH,
-                           tmp);
-      std::swap(v, tmp);
+        hipLaunchKernelGGL(k_orth<MMAX>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH,
+                           out);
+      cur = out;
+      out = out == v ? tmp : v;
     }
     {
-      const void *a[1] = {v};
+      const void *a[1] = {cur};
       dots(n2, 1, a, a, ctl, 0, c->red, s);
     }
     hipLaunchKernelGGL(k_kscale, dim3(1), dim3(64), 0, s, k, ctl);
-    axpbyI_dev(c->n, ctl + 2, 0.0, v, nullptr, 0.0, nullptr, nullptr, 0.0, c->Vk[k], 0, s);
+    axpbyI_dev(c->n, ctl + 2, 0.0, cur, nullptr, 0.0, nullptr, nullptr, 0.0, c->Vk[k], 0, s);
     // W_k = J V_k = P1[G(V_k)] - V_k
     fock_t(c, c->Vk[k], F1, 0);
     if ((st = response(c, F1, c->Wk[k], c->Vk[k]))) return st;
