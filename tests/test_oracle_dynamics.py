@@ -51,6 +51,60 @@ def test_full_rank_krylov_equals_exact_inverse_jacobian():
     np.testing.assert_allclose(Y, Yref, atol=1e-9 * np.abs(Yref).max())
 
 
+def _assembled_jacobian(sys_, X, beta):
+    """J of the residual on the orthonormal basis of symmetric n x n matrices,
+    assembled column by column, with the coordinate maps."""
+    n = sys_.n_orb
+    P0, jac = _jacobian_apply(sys_, X, beta)
+    basis = []
+    for i, j in zip(*np.triu_indices(n)):
+        E = np.zeros((n, n))
+        if i == j:
+            E[i, i] = 1.0
+        else:
+            E[i, j] = E[j, i] = 1.0 / np.sqrt(2.0)
+        basis.append(E)
+    coords = lambda M: np.array([np.sum(B * M) for B in basis])
+    mat = lambda y: sum(c * B for c, B in zip(y, basis))
+    J = np.array([coords(jac(B)) for B in basis]).T
+    return P0, jac, J, coords, mat
+
+
+def test_krylov_early_stop_is_the_first_rank_below_tol():
+    # Eq. 34 over span{V_1..V_k} = span{W0, J W0, .., J^(k-1) W0} with
+    # M = (W^T W)^-1 is the least-squares solution of J Y = W0 over that
+    # Krylov space (GMRES).  Reference: the Krylov matrix built by repeated
+    # products with the assembled J, orthonormalised by numpy's QR, and the
+    # small least-squares problem solved by lstsq.  With tol > 0 the kernel
+    # must stop at the first rank whose relative residual is below tol and
+    # return that rank's solution.
+    sys_ = carbon_cluster(2, 8)
+    beta = density.beta_of(3000.0)
+    X = _start_density(sys_, np.random.default_rng(8))
+    P0, jac, J, coords, mat = _assembled_jacobian(sys_, X, beta)
+    w0 = coords(P0 - X)
+    cols = [w0 / np.linalg.norm(w0)]
+    for _ in range(7):
+        v = J @ cols[-1]
+        cols.append(v / np.linalg.norm(v))
+    res, sols = [], []
+    for k in range(1, 8):
+        Q, _ = np.linalg.qr(np.array(cols[:k]).T)
+        y, *_ = np.linalg.lstsq(J @ Q, w0, rcond=None)
+        res.append(np.linalg.norm(J @ Q @ y - w0) / np.linalg.norm(w0))
+        sols.append(Q @ y)
+    assert all(b < a for a, b in zip(res, res[1:]))   # GMRES residuals decrease
+    for k_stop in (2, 3, 5):
+        tol = np.sqrt(res[k_stop - 2] * res[k_stop - 1])   # between ranks k_stop - 1 and k_stop
+        Y, rank, rel = krylov.krylov_kernel(X, P0, jac, m=7, tol=tol)
+        assert rank == k_stop, (k_stop, rank, res)
+        assert rel == pytest.approx(res[k_stop - 1], rel=1e-8)
+        np.testing.assert_allclose(coords(Y), sols[k_stop - 1], atol=1e-9 * np.abs(sols[k_stop - 1]).max())
+    # tol = 0 runs the full requested rank
+    Y, rank, rel = krylov.krylov_kernel(X, P0, jac, m=4, tol=0.0)
+    assert rank == 4 and rel == pytest.approx(res[3], rel=1e-8)
+
+
 def test_rank_one_closed_form_and_zero_interaction_limit():
     sys_ = carbon_cluster(3, 9)
     beta = density.beta_of(3000.0)
@@ -144,9 +198,50 @@ def test_integration_is_time_reversible_without_damping():
 
 
 def test_damping_coefficients_are_consistent():
+    # the damping sum of eq. 35 vanishes on polynomial histories of degree 1
+    # and on the cubic term (sum c_k = sum k c_k = sum k^3 c_k = 0), so it
+    # leaves a smoothly moving X(t) alone up to its high-order content
     c = np.array(dynamics.XL_C)
     k = np.arange(7)
-    assert c.sum() == 0.0 and (k * c).sum() == 0.0
+    assert c.sum() == 0.0 and (k * c).sum() == 0.0 and (k**3 * c).sum() == 0.0
+
+
+def _error_rate(Xhist0, st, steps):
+    """Iterate the oracle's eq. 35 update on a 1 x 1 'density' with ground
+    state X_min = 0 and an exact kernel.  Near X_min the residual is
+    W0 = D0[X] - X = J (X - X_min), so Y = J^-1 W0 = X - X_min = X.  Returns
+    the asymptotic factor per step by which the history's norm changes."""
+    hist = [np.array([[x]]) for x in Xhist0]
+    errs = []
+    for _ in range(steps):
+        Y = hist[0]
+        Xn = dynamics.integrate_x(hist, Y, st)
+        hist = [Xn] + hist[:-1]
+        errs.append(np.sqrt(sum(float(h[0, 0]) ** 2 for h in hist)))
+    a, b = steps // 2, steps - 1
+    return (errs[b] / errs[a]) ** (1.0 / (b - a))
+
+
+def test_damping_alpha_makes_the_electronic_recurrence_contract():
+    # Linearised about the ground state X_min = 0 with an exact kernel, eq. 35
+    # becomes e_{n+1} = (2 - kappa) e_n - e_{n-1} + alpha sum_k c_k e_{n-k}.
+    # Without damping (alpha = 0) it is the Verlet oscillator, |z| = 1 for
+    # 0 < kappa < 4: errors neither grow nor decay.  The damping the method's
+    # coefficients were chosen for contracts every mode, weakly (spectral
+    # radius just below one); an alpha ten times larger, or the damping sum
+    # with its sign flipped, makes the recurrence blow up.  Both the oracle's
+    # integrator and its constants enter through integrate_x.
+    rng = np.random.default_rng(35)
+    h0 = list(rng.standard_normal(7))
+    base = dynamics.Settings(T_e=3000.0, m=0, dt=0.5)
+    r_tab = _error_rate(h0, base, 2000)
+    r_undamped = _error_rate(h0, dataclasses.replace(base, alpha=0.0), 2000)
+    r_big = _error_rate(h0, dataclasses.replace(base, alpha=10 * base.alpha), 400)
+    r_flip = _error_rate(h0, dataclasses.replace(base, c=tuple(-x for x in base.c)), 2000)
+    assert abs(r_undamped - 1.0) < 2e-3, r_undamped
+    assert 0.90 < r_tab < 0.99, r_tab
+    assert r_big > 1.2, r_big
+    assert r_flip > 1.0, r_flip
 
 
 def test_scf_reaches_fixed_point():
