@@ -168,7 +168,11 @@ xlbomd_status xlbomd_fock(xlbomd_handle h, const double *P, double *F, int inclu
  *   P       DEVICE n x n output (must not alias F)
  *   entropy host out, nullable: S/k_B = -sum_i [f ln f + (1-f) ln(1-f)] (eq. 4, one spin)
  * The chain is cached in the handle for xlbomd_dm_response.  Returns
- * XLBOMD_E_NOCONV if |Tr P - N_e| > 1e-9 N_e after the shift. */
+ * XLBOMD_E_NOCONV if |Tr P - N_e| > 1e-9 N_e after the shift; in the pure
+ * split modes (FP32 storage of the Fermi chain) the trace is resolved to
+ * 8e-7 n (BF16X6, FP16X3) or 8e-6 n (BF16X3) on top of that, and a strongly
+ * gapped state, whose mu the electron count fixes only to the gap, takes no
+ * shift once the trace is within a quarter of that. */
 xlbomd_status xlbomd_fermi_dm(xlbomd_handle h, const double *F, double *mu, double *P,
                               double *entropy);
 

@@ -71,10 +71,12 @@ __global__ void k_canon(const double *trR, const double *trM, double *out) {
 
 // first-order chemical-potential correction of the stored chain result:
 // P = 2 (D + c M) with c = (n_occ - Tr D) / Tr M, written in FP64.  dD/dmu =
-// beta M, so this is the exact derivative step that makes Tr P = 2 n_occ.
-__global__ void k_trace_fix(const double *trD, const double *trM, double n_occ, double *c) {
+// beta M, so this is the exact derivative step that makes Tr P = 2 n_occ.  A
+// Tr M at or below tol (the storage's trace resolution; 0 for FP64) carries no
+// information, so no step is taken.
+__global__ void k_trace_fix(const double *trD, const double *trM, double n_occ, double tol, double *c) {
   if (threadIdx.x) return;
-  *c = (*trM > 0.0) ? (n_occ - *trD) / *trM : 0.0;
+  *c = (*trM > tol) ? (n_occ - *trD) / *trM : 0.0;
 }
 template <typename T>
 __global__ void k_finalize_P(size_t n2, const T *D, const T *M, const double *c, double *P) {
@@ -241,6 +243,14 @@ struct xlbomd_ctx {
   bool chain_valid = false;
   double mu_chain = 0.0;
   double mu_prev = NAN;   // chemical potential one MD step back (warm-start extrapolation)
+  // Trace tolerance of the chemical-potential passes.  With FP32 storage of the
+  // Fermi chain, Tr D and Tr D(I - D) carry the chain's rounding; in a strongly
+  // gapped state Tr D(I - D) = sum f(1 - f) falls to that level and a Newton
+  // step on it chases noise, while any mu in the gap gives the same D to that
+  // precision.  A trace within trace_tol of N_occ therefore takes no shift and
+  // the FP64 first-order correction of the result finishes.  0 with FP64
+  // storage.
+  double trace_tol = 0.0;
   // FP64 work
   double *f64[6] = {};
   double *Vk[MMAX] = {}, *Wk[MMAX] = {};
@@ -412,27 +422,14 @@ inline void split_prec(int prec, int &dm, int &rs) {
   }
 }
 
-// Lanczos start vector: fixed pseudo-random entries (a sine hash of the index),
-// normalised, written once into row 0 of the Lanczos buffer
-bool lanczos_start(xlbomd_ctx *c) {
-  std::vector<double> q(c->n);
-  double nrm = 0.0;
-  for (int i = 0; i < c->n; ++i) {
-    const double h = std::sin(i * 12.9898 + 78.233) * 43758.5453;
-    q[i] = h - std::floor(h) - 0.5;
-    nrm += q[i] * q[i];
-  }
-  for (auto &v : q) v /= std::sqrt(nrm);
-  return hipMemcpy(c->lq, q.data(), sizeof(double) * c->n, hipMemcpyHostToDevice) == hipSuccess;
-}
-
 // Bounds [lo, hi] on the spectrum of the symmetric F.  K Lanczos steps give
 // Ritz values theta_min, theta_max and their residual norms
 // r = beta_K |s_K| (s the Ritz vector of the tridiagonal); the bounds are
 // theta -/+ (r + 1e-3 (theta_max - theta_min)), clipped to the Gershgorin
 // interval, which is rigorous but much wider for large clusters.  The chain
 // depth L grows with log2 of the bound, so each factor of two saved is one
-// recursion level less in the density matrix and in every response.
+// recursion level less in the density matrix and in every response.  The
+// Lanczos start vector (row 0 of lq) is written once at create.
 xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
   const int n = c->n;
   gershgorin(n, F, c->dscal + S_LOHI, c->red, c->s);
@@ -441,36 +438,7 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
   double g[2], ab[2 * LANCZOS_K];
   xlbomd_status st = get_scalars2(c, S_LOHI, 2, g, S_LANC, 2 * K, ab);
   if (st) return st;
-  if (!std::isfinite(g[0]) || !std::isfinite(g[1]))
-    return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
-  lohi[0] = g[0];
-  lohi[1] = g[1];
-  const double scale = std::max(std::fabs(g[0]), std::fabs(g[1]));
-  int k = K;
-  for (int j = 0; j < K; ++j) {
-    if (!std::isfinite(ab[2 * j]) || !std::isfinite(ab[2 * j + 1])) return XLBOMD_OK;  // keep Gershgorin
-    if (ab[2 * j + 1] <= 1e-12 * scale) {
-      k = j + 1;  // invariant subspace: the Ritz values are eigenvalues
-      break;
-    }
-  }
-  std::vector<double> dg(k), od(k), th, zl;
-  for (int j = 0; j < k; ++j) {
-    dg[j] = ab[2 * j];
-    od[j] = ab[2 * j + 1];
-  }
-  if (!tridiag_eig_last(k, dg, od, th, zl)) return XLBOMD_OK;
-  int imin = 0, imax = 0;
-  for (int i = 1; i < k; ++i) {
-    if (th[i] < th[imin]) imin = i;
-    if (th[i] > th[imax]) imax = i;
-  }
-  const double bk = ab[2 * (k - 1) + 1];
-  const double rmin = bk * std::fabs(zl[imin]);
-  const double rmax = bk * std::fabs(zl[imax]);
-  const double margin = 1e-3 * (th[imax] - th[imin]) + 1e-12 * scale;
-  lohi[0] = std::max(g[0], th[imin] - rmin - margin);
-  lohi[1] = std::min(g[1], th[imax] + rmax + margin);
+  if (!bounds_from_lanczos(g, ab, K, lohi)) return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
   return XLBOMD_OK;
 }
 
@@ -660,7 +628,7 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     const void *Y[4] = {Nx, N2, N2, N3};
     dots((int)c->n2, 4, X, Y, c->dscal + S_TAU + 2, i32, c->red, s);
   }
-  mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->dscal + S_MU1, s);
+  mu_series_solve(c->dscal + S_TAU, c->n_occ, c->beta, c->trace_tol, c->dscal + S_MU1, s);
   // Each pass shifts D exactly to D(mu + dmu) = D Q^-1, Q = c I + (1 - c) D,
   // c = exp(-beta dmu): pass 0 with dmu from the trace series, later passes
   // with a (clamped) Newton step on Tr D.  A large step inverts Q by
@@ -679,7 +647,7 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
       axpby((int)c->n2, 1.0, D, -1.0, D2, Mt, i32, s);
       trace(n, D, c->dscal + S_T01, i32, c->red, s);
       trace(n, Mt, c->dscal + S_T01 + 1, i32, c->red, s);
-      mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->dscal + S_MU1, s);
+      mu_newton(c->dscal + S_T01, c->n_occ, c->beta, c->trace_tol, c->dscal + S_MU1, s);
     }
     if ((st = get_scalars(c, S_MU1, 5, mres))) return st;
     c->mu_passes = pass + 1;
@@ -810,7 +778,7 @@ xlbomd_status mu_shift(xlbomd_ctx *c, double *dmu_out) {
     trace(n, c->M, c->dscal + S_TRM, i32, c->red, s);
     trace(n, D, c->dscal + S_TRD, i32, c->red, s);
     hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
-                       c->dscal + S_FIX + 1);
+                       c->trace_tol, c->dscal + S_FIX + 1);
     const void *Xs[4] = {D, D2n, D3n, nullptr};
     const double a[4] = {1.0, -3.0, 2.0, 0.0};
     poly_comb(n, Xs, a, 0.0, Tn, i32, s);
@@ -964,7 +932,7 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   c->chain_valid = true;
   c->resp_ready = false;
   hipLaunchKernelGGL(k_trace_fix, dim3(1), dim3(64), 0, c->s, c->dscal + S_TRD, c->dscal + S_TRM, c->n_occ,
-                     c->dscal + S_FIX);
+                     c->trace_tol, c->dscal + S_FIX);
   {
     size_t blocks = std::min<size_t>((c->n2 + 255) / 256, 8192);
     if (c->is32)
@@ -987,7 +955,7 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
   if (sync_check) {
     const double tr = fx[2];
     if (!std::isfinite(tr)) return fail(c, XLBOMD_E_NONFINITE, "non-finite density matrix");
-    if (std::fabs(tr - c->n_elec) > 1e-9 * c->n_elec)
+    if (std::fabs(tr - c->n_elec) > 1e-9 * c->n_elec + 4.0 * c->trace_tol)
       return fail(c, XLBOMD_E_NOCONV, "trace %.15g differs from N_e %.15g", tr, c->n_elec);
   }
   return XLBOMD_OK;
@@ -1246,6 +1214,7 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   c->rs32 = c->prec_rs != XLBOMD_FP64;
   c->resp_copy = c->prec_dm != c->prec_rs;
   c->esz = c->is32 ? 4 : 8;
+  c->trace_tol = !c->is32 ? 0.0 : (c->prec_dm == XLBOMD_BF16X3 ? 2e-6 : 2e-7) * c->n;
   const int N = c->N, T = (N + 15) / 16;
   bool ok = true;
   auto A = [&](void **p, size_t bytes) { ok = ok && dev_alloc(p, bytes); };
@@ -1291,10 +1260,11 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   }
   if (hipMemcpy(c->onecenter, sys->onecenter, sizeof(double) * 5 * N, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->j55, sys->model.j55, sizeof(double) * 55, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess || !lanczos_start(c)) {
+      hipMemset(c->dscal, 0, sizeof(double) * S_TOTAL) != hipSuccess) {
     xlbomd_destroy(c);
     return XLBOMD_E_HIP;
   }
+  lanczos_start(c->n, c->lq, c->s);
   if (N > 1) {
     const size_t npair = (size_t)N * (N - 1) / 2;
     float *tmp = nullptr;

@@ -328,6 +328,26 @@ __global__ __launch_bounds__(1024) void k_lanczos_step(int n, int j, double *Q, 
   for (int i = threadIdx.x; i < n; i += 1024) qn[i] *= inv;
 }
 
+// Lanczos start vector: q_i = u_i - 1/2 with u_i the top 53 bits of the
+// SplitMix64 output for index i (Steele, Lea and Flood, OOPSLA 2014), scaled to
+// unit norm; one workgroup, integer arithmetic, so the same bits on every call.
+__global__ __launch_bounds__(1024) void k_lanczos_start(int n, double *q) {
+  __shared__ double sh[16];
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    unsigned long long z = (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double v = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    q[i] = v;
+    ss += v * v;
+  }
+  ss = block_sum_all<1024>(ss, sh);
+  const double inv = 1.0 / sqrt(ss);
+  for (int i = threadIdx.x; i < n; i += 1024) q[i] *= inv;
+}
+
 // Gershgorin: one wavefront per row
 __global__ __launch_bounds__(256) void k_gersh_rows(int n, const double *F, double *lohi) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -371,7 +391,7 @@ __global__ __launch_bounds__(256) void k_gersh_final(int n, const double *lohi, 
 // by bisection on dmu in [-0.3/beta, 0.3/beta] (the truncated series is accurate there for
 // the warm starts of a trajectory).  out[0] = dmu, out[1] = c, out[2] = 2/(1+c) (Newton-Schulz
 // start for (cI + (1-c)D)^-1), out[3] = flag (1: root outside the bracket, clamped).
-__global__ void k_mu_series(const double *tau, double n_occ, double beta, double *out) {
+__global__ void k_mu_series(const double *tau, double n_occ, double beta, double tol_n, double *out) {
   if (threadIdx.x != 0) return;
   auto g = [&](double dmu) {
     const double x = -expm1(-beta * dmu);  // 1 - c
@@ -385,7 +405,9 @@ __global__ void k_mu_series(const double *tau, double n_occ, double beta, double
   double lo = -SERIES_STEP / beta, hi = SERIES_STEP / beta;
   double flag = 0.0;
   double dmu;
-  if (g(lo) > 0.0) {
+  if (fabs(tau[0] - n_occ) <= tol_n) {
+    dmu = 0.0;  // the trace is already N_occ to the storage precision
+  } else if (g(lo) > 0.0) {
     dmu = lo;
     flag = 1.0;
   } else if (g(hi) < 0.0) {
@@ -412,10 +434,10 @@ __global__ void k_mu_series(const double *tau, double n_occ, double beta, double
 
 // Newton step on mu from t01 = (Tr D, Tr D(I-D)): dmu = (n_occ - t0) / (beta t1).
 // out layout as k_mu_series.
-__global__ void k_mu_newton(const double *t01, double n_occ, double beta, double *out) {
+__global__ void k_mu_newton(const double *t01, double n_occ, double beta, double tol_n, double *out) {
   if (threadIdx.x != 0) return;
   const double t0 = t01[0], t1 = t01[1];
-  double dmu = (t1 > 0.0) ? (n_occ - t0) / (beta * t1) : 0.0;
+  double dmu = (t1 > 0.0 && fabs(n_occ - t0) > tol_n) ? (n_occ - t0) / (beta * t1) : 0.0;
   const double lim = MU_STEP / beta;
   double flag = 0.0;
   if (dmu > lim) {
@@ -654,6 +676,10 @@ void convert_t(int n, const double *in, float *out, hipStream_t s) {
   hipLaunchKernelGGL(k_convert_t, dim3(g, g), dim3(256), 0, s, n, in, out);
 }
 
+void lanczos_start(int n, double *Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_start, dim3(1), dim3(1024), 0, s, n, Q);
+}
+
 void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s) {
   // Q is the library's (16-byte aligned, rows of even length); F may be the caller's
   const bool pairs = n % 2 == 0 && ((uintptr_t)F % 16) == 0 && ((uintptr_t)Q % 16) == 0;
@@ -667,12 +693,12 @@ void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hi
   }
 }
 
-void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_series, dim3(1), dim3(64), 0, s, tau, n_occ, beta, out);
+void mu_series_solve(const double *tau, double n_occ, double beta, double tol_n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_series, dim3(1), dim3(64), 0, s, tau, n_occ, beta, tol_n, out);
 }
 
-void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_newton, dim3(1), dim3(64), 0, s, t01, n_occ, beta, out);
+void mu_newton(const double *t01, double n_occ, double beta, double tol_n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_newton, dim3(1), dim3(64), 0, s, t01, n_occ, beta, tol_n, out);
 }
 
 void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,

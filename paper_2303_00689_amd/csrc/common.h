@@ -64,6 +64,8 @@ void dots(int n2, int k, const void *const *X, const void *const *Y, double *res
 void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s);
 // Gershgorin bounds of a symmetric matrix: res[0] = min(F_ii - r_i), res[1] = max(F_ii + r_i)
 void gershgorin(int n, const double *F, double *res, double *partials, hipStream_t s);
+// the fixed unit start vector of the Lanczos steps into row 0 of Q (n values)
+void lanczos_start(int n, double *Q, hipStream_t s);
 // k Lanczos steps on symmetric F from the unit vector in row 0 of Q
 // ((k + 1) x n); w: n scratch; ab: 2k device doubles (alpha_j, beta_j)
 void lanczos(int n, int k, const double *F, double *Q, double *w, double *ab, hipStream_t s);
@@ -94,8 +96,9 @@ size_t energy_partial_doubles(int n_atoms);
 
 // ------------------------------------------------------------- scalar kernels
 // Chemical-potential and Krylov scalar steps (one thread), see the .hip file.
-void mu_series_solve(const double *tau, double n_occ, double beta, double *out, hipStream_t s);
-void mu_newton(const double *t01, double n_occ, double beta, double *out, hipStream_t s);
+// tol_n: a trace within tol_n of n_occ takes no shift (dmu = 0)
+void mu_series_solve(const double *tau, double n_occ, double beta, double tol_n, double *out, hipStream_t s);
+void mu_newton(const double *t01, double n_occ, double beta, double tol_n, double *out, hipStream_t s);
 void krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
                   const double *k_rank, hipStream_t s);
 

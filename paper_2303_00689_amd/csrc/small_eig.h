@@ -1,24 +1,32 @@
-// Host-side eigenvalues of the k x k Lanczos tridiagonal (k <= 64) by the
-// implicit QL iteration with Wilkinson shifts, keeping only the last row of the
-// accumulated rotations: the last component of every Ritz vector, which is all
-// the residual bounds beta_k |s_k| need.  O(k^2) work.
+// Host-side eigenvalues of the k x k Lanczos tridiagonal (k <= SMALL_EIG_MAX)
+// by the implicit QL iteration with Wilkinson shifts: the published method of
+// Bowdler, Martin, Reinsch and Wilkinson, "The QR and QL algorithms for
+// symmetric matrices", Numer. Math. 11 (1968) 293-306 (Handbook for Automatic
+// Computation II/3; EISPACK tql2), written here from that description.  The one
+// change is that only the last row of the accumulated rotations is kept: the
+// last component of every Ritz vector, which is all the residual bounds
+// beta_k |s_k| need.  O(k^2) work, fixed-size arrays, no allocation.
 #pragma once
 
 #include <cmath>
-#include <vector>
 
 namespace xl {
 
+constexpr int SMALL_EIG_MAX = 64;
+
 // d: diagonal (k), e: off-diagonal (k - 1).  On return ev[i] are the
 // eigenvalues (unsorted) and zl[i] the last component of the matching unit
-// eigenvector.  Returns false if an eigenvalue took more than 60 QL steps.
-inline bool tridiag_eig_last(int k, const std::vector<double> &d, const std::vector<double> &e,
-                             std::vector<double> &ev, std::vector<double> &zl) {
-  ev.assign(d.begin(), d.begin() + k);
-  std::vector<double> off(k, 0.0);
-  for (int i = 0; i + 1 < k; ++i) off[i] = e[i];
-  zl.assign(k, 0.0);
-  if (k > 0) zl[k - 1] = 1.0;
+// eigenvector.  Returns false if k is out of range or an eigenvalue took more
+// than 60 QL steps.
+inline bool tridiag_eig_last(int k, const double *d, const double *e, double *ev, double *zl) {
+  if (k < 1 || k > SMALL_EIG_MAX) return false;
+  double off[SMALL_EIG_MAX];
+  for (int i = 0; i < k; ++i) {
+    ev[i] = d[i];
+    off[i] = i + 1 < k ? e[i] : 0.0;
+    zl[i] = 0.0;
+  }
+  zl[k - 1] = 1.0;
   for (int l = 0; l < k; ++l) {
     for (int iter = 0;; ++iter) {
       // the first negligible off-diagonal entry at or after l splits the matrix
@@ -64,6 +72,45 @@ inline bool tridiag_eig_last(int k, const std::vector<double> &d, const std::vec
       off[m] = 0.0;
     }
   }
+  return true;
+}
+
+// Spectral bounds from the Gershgorin interval g[0..1] and K Lanczos steps
+// ab[2 j] = alpha_j, ab[2 j + 1] = beta_j: the extreme Ritz values widened by
+// their residual bounds beta_k |s_k| and by 1e-3 of the Ritz spread, clipped
+// to the Gershgorin interval (kept alone if the Lanczos data are not finite
+// or the small solve fails).  Returns false if g is not finite.
+inline bool bounds_from_lanczos(const double g[2], const double *ab, int K, double lohi[2]) {
+  if (!std::isfinite(g[0]) || !std::isfinite(g[1])) return false;
+  lohi[0] = g[0];
+  lohi[1] = g[1];
+  if (K < 1 || K > SMALL_EIG_MAX) return true;
+  const double scale = std::fmax(std::fabs(g[0]), std::fabs(g[1]));
+  int k = K;
+  for (int j = 0; j < K; ++j) {
+    if (!std::isfinite(ab[2 * j]) || !std::isfinite(ab[2 * j + 1])) return true;  // keep Gershgorin
+    if (ab[2 * j + 1] <= 1e-12 * scale) {
+      k = j + 1;  // invariant subspace: the Ritz values are eigenvalues
+      break;
+    }
+  }
+  double dg[SMALL_EIG_MAX], od[SMALL_EIG_MAX], th[SMALL_EIG_MAX], zl[SMALL_EIG_MAX];
+  for (int j = 0; j < k; ++j) {
+    dg[j] = ab[2 * j];
+    od[j] = ab[2 * j + 1];
+  }
+  if (!tridiag_eig_last(k, dg, od, th, zl)) return true;
+  int imin = 0, imax = 0;
+  for (int i = 1; i < k; ++i) {
+    if (th[i] < th[imin]) imin = i;
+    if (th[i] > th[imax]) imax = i;
+  }
+  const double bk = ab[2 * (k - 1) + 1];
+  const double rmin = bk * std::fabs(zl[imin]);
+  const double rmax = bk * std::fabs(zl[imax]);
+  const double margin = 1e-3 * (th[imax] - th[imin]) + 1e-12 * scale;
+  lohi[0] = std::fmax(g[0], th[imin] - rmin - margin);
+  lohi[1] = std::fmin(g[1], th[imax] + rmax + margin);
   return true;
 }
 

@@ -1,7 +1,8 @@
 """Parity at the full 840-atom size (n = 3360), through the C ABI, in the
 launch configuration the benchmark times: the benchmark cluster (5000 K,
-rank 6) and the low-gap cluster (hopping x0.6, s-p split 4 eV, 10000 K,
-rank 8).
+rank 6), the same cluster with the literal all-ones 10 x 10 J of the
+benchmark configuration in its two-centre blocks, and the low-gap cluster
+(hopping x0.6, s-p split 4 eV, 10000 K, rank 8).
 
 The FP64 oracle handles this size in seconds per call (one eigendecomposition
 of a 3360 x 3360 matrix, dense pair loops), so every element is compared, not
@@ -10,11 +11,13 @@ a sample.  FP64 mode is held to 1e-10 relative per matrix; the mixed mode
 force target and to the split-response error budget.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
-from synth import workload
-from oracle import model, density, dynamics
+from synth import workload, carbon_cluster
+from oracle import model, density, dynamics, krylov
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,7 +33,13 @@ class Ref:
     """Oracle results at one seeded state of an 840-atom cluster."""
 
     def __init__(self, name="c840"):
+        j_pattern = "monopole"
+        if name.endswith("_allones"):
+            name, j_pattern = name[: -len("_allones")], "allones"
         s, w = workload(name)
+        if j_pattern != s.params.j_pattern:
+            s = carbon_cluster(s.n_atoms, s.seed, params=dataclasses.replace(s.params, j_pattern=j_pattern))
+        self.j_pattern = j_pattern
         self.sys, self.w = s, w
         self.beta = density.beta_of(w["T_e"])
         n = s.n_orb
@@ -46,7 +55,7 @@ class Ref:
         self.frc = dynamics.forces(s.R, self.dm["P"], self.X, s.params, s.noise)
 
 
-@pytest.fixture(scope="module", params=["c840", "c840_lowgap"])
+@pytest.fixture(scope="module", params=["c840", "c840_allones", "c840_lowgap"])
 def ref(request):
     return Ref(request.param)
 
@@ -112,4 +121,41 @@ def test_mixed_precision_forces_meet_target(binding, ref, prec):
     print(f"{ref.w['n_atoms']} atoms, T_e {ref.w['T_e']}: {prec}: P {perr:.2e}  P1 {p1err:.2e}  forces {ferr:.2e} eV/A")
     assert perr <= TOL
     assert ferr <= 1e-4
-    assert p1err <= 1e-2
+    # split response: about three times the measured error (MI355X, relative
+    # max-abs): dm64_bf16x3 3.8e-4 / 9.5e-5 / 8.0e-5 and dm64_fp16x3
+    # 2.1e-5 / 6.6e-6 / 1.2e-5 for the benchmark, all-ones J and low-gap clusters
+    bound = {"dm64_bf16x3": {"c840": 1.2e-3, "c840_allones": 3e-4, "c840_lowgap": 2.5e-4},
+             "dm64_fp16x3": {"c840": 6e-5, "c840_allones": 2e-5, "c840_lowgap": 4e-5}}[prec]
+    key = "c840_allones" if ref.j_pattern == "allones" else ("c840_lowgap" if ref.w["T_e"] == 10000.0 else "c840")
+    assert p1err <= bound[key]
+
+
+def test_fp64_krylov_kernel_matches_oracle(binding, ref):
+    """The rank-m kernel (eq. 34) at the full size: Y element by element, the
+    rank and the relative residual against the oracle's m Loewner responses."""
+    s = ref.sys
+    m = ref.w["m"]
+
+    def jac(V):
+        F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params)
+        return density.response(ref.F, F1, s.n_elec, ref.beta, ref.dm) - V
+    Yref, rref, relref = krylov.krylov_kernel(ref.X, ref.dm["P"], jac, m)
+    h = binding.handle_for(s, ref.w, prec="fp64")
+    try:
+        h.set_geometry(_dev(s.R))
+        X = _dev(ref.X)
+        F = torch.empty_like(X)
+        h.fock(X, F, True)
+        P = torch.empty_like(X)
+        h.fermi_dm(F, P)
+        Y = torch.empty_like(X)
+        rank, rel = h.krylov_kernel(X, P, m, Y)
+        torch.cuda.synchronize()
+        err = _rel(Y.cpu().numpy(), Yref)
+    finally:
+        h.close()
+    print(f"{ref.w['n_atoms']} atoms, J {ref.j_pattern}, rank {m}: Y error {err:.2e} of max|Y|, "
+          f"relres {rel:.4f} (oracle {relref:.4f})")
+    assert rank == rref
+    assert rel == pytest.approx(relref, rel=1e-9)
+    assert err <= TOL

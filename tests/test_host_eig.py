@@ -26,10 +26,10 @@ int main() {
   for (int t = 0; t < cases; ++t) {
     int k;
     if (scanf("%d", &k) != 1) return 1;
-    std::vector<double> d(k), e(k, 0.0), ev, zl;
+    std::vector<double> d(k), e(k, 0.0), ev(k), zl(k);
     for (auto &x : d) if (scanf("%lf", &x) != 1) return 1;
     for (int i = 0; i + 1 < k; ++i) if (scanf("%lf", &e[i]) != 1) return 1;
-    const bool ok = xl::tridiag_eig_last(k, d, e, ev, zl);
+    const bool ok = xl::tridiag_eig_last(k, d.data(), e.data(), ev.data(), zl.data());
     printf("%d", ok ? 1 : 0);
     for (int i = 0; i < k; ++i) printf(" %.17g %.17g", ev[i], zl[i]);
     printf("\n");
