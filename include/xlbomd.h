@@ -184,6 +184,24 @@ xlbomd_status xlbomd_fermi_dm(xlbomd_handle h, const double *F, double *mu, doub
  * XLBOMD_E_NONFINITE if F holds a non-finite entry. */
 xlbomd_status xlbomd_spectral_bounds(xlbomd_handle h, const double *F, double *lohi);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the bounds
+ * of xlbomd_spectral_bounds, bit for bit the same, without a handle and
+ * without any allocation.  The kernels' scratch (min(32, n) + 1 Lanczos
+ * vectors, a product vector, per-row Gershgorin intervals and the reduced
+ * scalars, about 4.7 MB) is one file-scope device array of the library, one
+ * copy per GPU, held until the process ends.
+ *   F       DEVICE n x n symmetric FP64 on the current device
+ *   n       1 .. XLBOMD_SPECTRAL_BOUNDS_NOALLOC_MAX_N; larger n returns
+ *           XLBOMD_E_ARG before any work
+ *   stream  hipStream_t (NULL = default stream); the call synchronises it
+ *   lohi    HOST, 2 doubles: lohi[0] <= every eigenvalue of F <= lohi[1]
+ * XLBOMD_E_NONFINITE if F holds a non-finite entry.  Every call on a GPU
+ * shares that GPU's scratch array, so calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller. */
+#define XLBOMD_SPECTRAL_BOUNDS_NOALLOC_MAX_N 16384
+xlbomd_status xlbomd_spectral_bounds_noalloc(const double *F, int n, void *stream, double *lohi);
+
 /* canonical first-order response P1 = 2 dD/dlambda of D[F + lambda F1] at the
  * state of the last xlbomd_fermi_dm (eq. 36), with mu re-solved (Tr P1 = 0).
  * F1, P1: DEVICE n x n.  XLBOMD_E_STATE if no chain is cached. */

@@ -29,7 +29,10 @@ SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
            "xlbomd_step", "xlbomd_step_langevin", "xlbomd_ensemble_step", "xlbomd_md_init", "xlbomd_scf",
            "xlbomd_matmul",
-           "xlbomd_profile", "xlbomd_profile_read"]
+           "xlbomd_profile", "xlbomd_profile_read", "xlbomd_spectral_bounds_noalloc"]
+
+# largest n of xlbomd_spectral_bounds_noalloc (XLBOMD_SPECTRAL_BOUNDS_NOALLOC_MAX_N)
+SPECTRAL_BOUNDS_NOALLOC_MAX_N = 16384
 
 
 class Model(C.Structure):
@@ -97,6 +100,7 @@ def load():
     lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
     lib.xlbomd_profile.argtypes = [vp, i]
     lib.xlbomd_profile_read.argtypes = [vp, pd]
+    lib.xlbomd_spectral_bounds_noalloc.argtypes = [vp, i, vp, pd]
     for name in SYMBOLS:
         if name not in ("xlbomd_last_error", "xlbomd_n_orb"):
             getattr(lib, name).restype = i
@@ -317,6 +321,21 @@ def ensemble_step(handles, states, n_steps=1, report=True):
         return None
     return [[{k: getattr(reps[m * n_steps + j], k) for k, _ in Report._fields_} for j in range(n_steps)]
             for m in range(count)]
+
+
+def spectral_bounds_noalloc(F, stream=None):
+    """(lo, hi) enclosing the spectrum of the symmetric n x n FP64 device
+    tensor F, from xlbomd_spectral_bounds_noalloc (no handle, no allocation)."""
+    import torch
+    lib = load()
+    if not isinstance(F, torch.Tensor) or F.dim() != 2 or F.shape[0] != F.shape[1]:
+        raise XLBOMDError("F must be a square device tensor")
+    n = F.shape[0]
+    lohi = (C.c_double * 2)()
+    st = lib.xlbomd_spectral_bounds_noalloc(_ptr(F, n * n, torch.float64), int(n), C.c_void_p(stream or 0), lohi)
+    if st != 0:
+        raise XLBOMDError(f"spectral_bounds_noalloc: {STATUS.get(st, st)}")
+    return lohi[0], lohi[1]
 
 
 def handle_for(system, settings: dict, prec="fp64", stream=None) -> Handle:
