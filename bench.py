@@ -1,5 +1,6 @@
 #!/usr/bin/env python
-"""Steps/s of the KSA-XL-BOMD hot path on the 840-atom carbon cluster.
+"""Steps/s of the KSA-XL-BOMD hot path on the 840-atom carbon cluster, split
+BF16 response chains against plain FP64.
 
 One step = one pass of the whole per-step path of the method (paper,
 Methods sections 3-6): leapfrog and damped X-Verlet integration (eqs. 27-29,
@@ -8,8 +9,16 @@ with its chemical potential (eqs. 7, 8, 19), the rank-m Krylov kernel with m
 canonical responses (eqs. 34, 36), and the eq. 37 forces with the shadow
 energy.  Workload: the 840-atom synthetic carbon cluster (3360 x 3360 Fock,
 T_e = 5000 K, rank m = 6, dt = 0.5 fs), seeded; inputs are resident in HBM
-before the timed region.  Every timed step starts from the same prepared MD
-state (--trajectory free runs one continuous NVE trajectory instead).
+before the timed region.  MD starts from the SCF iterate of xlbomd_scf
+(linear mixing, then rank-12 Newton-Krylov steps; the residual is reported).
+
+Timed legs, all from that start: the split mode (the value) and plain FP64,
+each with every timed step restarting from the prepared state, and a free
+NVE trajectory of the split mode.  Untimed: the force error of the split
+mode at the states of its own trajectory (FP64 re-evaluation at the same
+R and X), the divergence of split and FP64 trajectories from the same start
+next to that of two FP64 trajectories whose start differs by as much, and the
+oracle timed on the host.
 
 Prints one JSON line.  --gpus N > 1 is rejected: this build runs on one GPU.
 """
@@ -31,6 +40,16 @@ PEAK_F64, PEAK_LOWP = 78.6, 2500.0     # TFLOP/s, dense MFMA (FP64; BF16 and FP1
 DTYPE = {"fp64": "f64", "bf16x3": "bf16", "bf16x6": "bf16", "fp16x3": "f16",
          "dm64_bf16x3": "bf16", "dm64_bf16x6": "bf16", "dm64_fp16x3": "f16"}
 HBM_PEAK_GBS = 8000.0
+ACC = 9.648533e-3    # eV / (Angstrom amu) -> Angstrom / fs^2
+# the kernel behind each GEMM class at n = 3360 (n % 32 == 0)
+KERNEL = {"gemm_f64": "k_gemm_f64_big (128 x 128 tiles)",
+          "gemm_f64_sym": "k_gemm_f64_half (128 x 64 tiles over the upper triangle)",
+          "gemm_bf16x3": "k_gemm_split_big<0, 7> (BF16x3, 224 x 224 tiles)",
+          "gemm_bf16x3_sym": "k_gemm_split_big<0, 5> (BF16x3, 160 x 160 upper tiles)",
+          "gemm_bf16x6": "k_gemm_split_big<1, 7> (BF16x6, 224 x 224 tiles)",
+          "gemm_bf16x6_sym": "k_gemm_split_big<1, 5> (BF16x6, 160 x 160 upper tiles)",
+          "gemm_fp16x3": "k_gemm_split_lds<2> (FP16x3, 128 x 128 tiles)",
+          "gemm_fp16x3_sym": "k_gemm_split_lds<2> (FP16x3, 128 x 128 upper tiles)"}
 
 
 def log(*a):
@@ -98,6 +117,10 @@ def kernel_traffic(kclass):
     taken on a different version of the kernel's source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_c840.json")
+    if kclass.startswith("gemm_f64"):
+        kclass = "gemm_f64"
+    elif kclass.startswith("gemm_"):
+        kclass = "gemm_split"
     src = {"gemm_f64": "gemm_f64.hip", "gemm_split": "gemm_split.hip", "fock": "pairs.hip"}.get(kclass)
     if not src or not os.path.exists(path):
         return None
@@ -126,7 +149,7 @@ def run_ensemble(args, binding, torch, dev):
         hi = binding.handle_for(sys_, w, prec="fp16x3")
         hi.set_geometry(R0)
         X0 = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
-        hi.scf(X0, m=8, tol=1e-12, max_iter=0, allow_noconv=True)   # 50 mixing steps
+        hi.scf(X0, m=8, tol=1e-12, max_iter=0, mix_tol=0.0, max_mix=50, allow_noconv=True)
         hi.close()
         strm = torch.cuda.Stream()
         h = binding.Handle(sys_.n_atoms, sys_.n_elec, sys_.onecenter, sys_.noise, sys_.params, prec=args.prec,
@@ -175,23 +198,182 @@ def run_ensemble(args, binding, torch, dev):
         "steps": args.steps, "warmup": args.warmup, "data": "synthetic"}))
 
 
+def gemm_roofline(prof, classes, elapsed):
+    """The GEMM class (one kernel) with the most time among `classes`: executed
+    MFMA flops over its launch time, HIP events on the library stream."""
+    best = max(classes, key=lambda k: prof[k]["ms"])
+    g = prof[best]
+    peak = PEAK_F64 if best.startswith("gemm_f64") else PEAK_LOWP
+    tfs = g["work"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    return {"bound": "mfma", "kernel": KERNEL.get(best, best), "class": best, "achieved": tfs, "peak": peak,
+            "unit": "TFLOP/s", "frac": tfs / peak, "traffic": kernel_traffic(best), "launches": g["launches"],
+            "avg_launch_us": 1e3 * g["ms"] / max(g["launches"], 1), "share_of_step": g["ms"] * 1e-3 / elapsed}
+
+
+def class_summary(prof, steps):
+    out = {}
+    for k, g in prof.items():
+        if g["launches"]:
+            unit = 1e12 if k.startswith("gemm") else 1e9
+            out[k] = {"ms_per_step": g["ms"] / steps, "launches_per_step": g["launches"] / steps,
+                      ("tflops" if unit == 1e12 else "gbs"): g["work"] / (g["ms"] * 1e-3) / unit if g["ms"] else 0.0}
+    return out
+
+
+class Snapshot:
+    """Device copy of an MD state: the whole state, or (restore_step) only what
+    one step writes -- the nuclei, Y and the ring slot (head + 6) % 7."""
+
+    def __init__(self, state):
+        self.R, self.V, self.A = state.R.clone(), state.V.clone(), state.A.clone()
+        self.X, self.Y = state.X.clone(), state.Y.clone()
+        self.head, self.mu = state.head, state.mu
+        self.slot = (state.head + 6) % 7
+
+    def new_state(self, binding):
+        return binding.MDState(R=self.R.clone(), V=self.V.clone(), A=self.A.clone(), X=self.X.clone(),
+                               Y=self.Y.clone(), head=self.head, mu=self.mu)
+
+    def restore_step(self, state):
+        for dst, src in zip((state.R, state.V, state.A, state.X[self.slot], state.Y),
+                            (self.R, self.V, self.A, self.X[self.slot], self.Y)):
+            dst.copy_(src)
+        state.head, state.mu = self.head, self.mu
+
+
+def timed_reset_leg(torch, h, state, snap, steps, warmup):
+    """Steps/s with every step restarting from the prepared state (restore
+    inside the timed region), and the per-class profile of the timed steps."""
+    for k in range(warmup):
+        snap.restore_step(state)
+        h.step(state, 1, report=False)
+        log(f"  warmup step {k + 1} done")
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        snap.restore_step(state)
+        h.step(state, 1, report=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = h.profile_read()
+    h.profile(False)
+    return elapsed, prof
+
+
+def free_leg(binding, torch, h, snap, steps):
+    """One continuous NVE trajectory of `steps` steps from the prepared state,
+    timed step by step (no report), then the chain depth and mu passes of a
+    reported copy of the same trajectory."""
+    st = snap.new_state(binding)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(st, steps, report=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = snap.new_state(binding)
+    reps = h.step(st, steps, report=True)
+    return elapsed, reps
+
+
+def md_start(binding, torch, sys_, X0, dev):
+    n = sys_.n_orb
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev).contiguous()
+    return binding.MDState(R=t(sys_.R), V=t(sys_.V), A=torch.zeros((sys_.n_atoms, 3), dtype=torch.float64, device=dev),
+                           X=torch.stack([X0.clone()] * 7), Y=torch.zeros((n, n), dtype=torch.float64, device=dev),
+                           head=0, mu=float("nan"))
+
+
+def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
+    """Untimed accuracy of the split mode against FP64 over `steps` MD steps.
+
+    same_state: along the split trajectory, the forces the split step used
+      against an FP64 re-evaluation at the same (R, X) -- the force error of
+      the split arithmetic (DM64 modes: the density matrix is FP64, so this
+      isolates anything else).
+    divergence: split and FP64 trajectories from the same start; the split
+      kernel Y enters through X(t + dt) of eq. 35.  Beside it, two FP64
+      trajectories whose starts differ by a symmetric perturbation as large as
+      the first step's split-vs-FP64 difference of X: what any perturbation of
+      that size does on this trajectory.
+    drift: slope of E_tot (eq. 26) over the trajectory, eV/ps/atom."""
+    mass = sys_.params.mass
+    conv = mass / ACC
+    hs = binding.handle_for(sys_, w, prec=prec)
+    h64 = binding.handle_for(sys_, w, prec="fp64")
+    hev = binding.handle_for(sys_, w, prec="fp64")
+    R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
+    for h in (hs, h64, hev):
+        h.set_geometry(R0)
+    n = sys_.n_orb
+    F = torch.empty((n, n), dtype=torch.float64, device=dev)
+    P = torch.empty_like(F)
+    f64 = torch.empty((sys_.n_atoms, 3), dtype=torch.float64, device=dev)
+
+    def run(h, Xstart, evaluate=False):
+        st = md_start(binding, torch, sys_, Xstart, dev)
+        h.md_init(st)
+        frc, X, E, same = [], [], [], []
+        for _ in range(steps):
+            E.append(h.step(st, 1, report=True)[0]["E_tot"])
+            fs = st.A * conv
+            frc.append(fs.clone())
+            X.append(st.x_current().clone())
+            if evaluate:
+                Xc = st.x_current()
+                hev.set_geometry(st.R)
+                hev.fock(Xc, F, True)
+                hev.fermi_dm(F, P, mu=st.mu)
+                hev.forces(P, Xc, f64)
+                same.append(float((f64 - fs).abs().max()))
+        return frc, X, E, same
+
+    def drift(E):
+        tfs = w["dt"] * np.arange(1, len(E) + 1)
+        return float(np.polyfit(tfs, np.array(E), 1)[0]) * 1000.0 / sys_.n_atoms
+
+    fs_, Xs_, Es_, same = run(hs, X0, evaluate=True)
+    log("  split trajectory with FP64 re-evaluation done")
+    f6_, X6_, E6_, _ = run(h64, X0)
+    log("  FP64 trajectory done")
+    d1 = float(torch.linalg.norm(Xs_[0] - X6_[0]))
+    rng = np.random.default_rng(29)
+    pert = rng.standard_normal((n, n))
+    pert = pert + pert.T
+    pert *= d1 / np.linalg.norm(pert)
+    fp_, Xp_, Ep_, _ = run(h64, X0 + torch.tensor(pert, dtype=torch.float64, device=dev))
+    log("  perturbed FP64 trajectory done")
+    for h in (hs, h64, hev):
+        h.close()
+    fdiff = lambda a, b: [float((x - y).abs().max()) for x, y in zip(a, b)]
+    xdiff = lambda a, b: [float(torch.linalg.norm(x - y)) for x, y in zip(a, b)]
+    return {
+        "steps": steps,
+        "same_state_force_err_eV_per_A": {"max": max(same), "per_step": same},
+        "divergence": {
+            "split_vs_fp64": {"force_maxabs_eV_per_A": fdiff(fs_, f6_), "X_fro": xdiff(Xs_, X6_)},
+            "fp64_vs_fp64_perturbed": {"perturbation_fro": d1, "force_maxabs_eV_per_A": fdiff(fp_, f6_),
+                                       "X_fro": xdiff(Xp_, X6_)}},
+        "drift_eV_per_ps_per_atom": {"split": drift(Es_), "fp64": drift(E6_), "fp64_perturbed": drift(Ep_)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="dm64_bf16x3", choices=MODES)
     ap.add_argument("--workload", default="c840")
+    ap.add_argument("--fp64-steps", type=int, default=10, help="timed steps of the FP64 leg (0: skip)")
+    ap.add_argument("--free-steps", type=int, default=20, help="steps of the free NVE trajectory leg (0: skip)")
+    ap.add_argument("--compare-steps", type=int, default=20,
+                    help="MD steps of the untimed split-vs-FP64 accuracy legs (0: skip)")
+    ap.add_argument("--init-mix", type=int, default=300, help="linear-mixing steps of the initial SCF")
+    ap.add_argument("--init-newton", type=int, default=10, help="rank-12 Newton-Krylov steps of the initial SCF")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="BLAS threads of the oracle leg (0: all)")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--drift-steps", type=int, default=6,
-                    help="free NVE steps per precision for the shadow-energy drift of the comparison")
-    ap.add_argument("--init-mix", type=int, default=200, help="linear-mixing steps before MD")
     ap.add_argument("--no-report", action="store_true", help="skip the untimed report step after timing")
-    ap.add_argument("--trajectory", choices=["reset", "free"], default="reset",
-                    help="reset: every step starts from the prepared MD state (default); "
-                         "free: one continuous NVE trajectory")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="instead: the ragged ensemble of this many clusters (20-300 atoms, 3000 K, "
                          "rank 4) through xlbomd_ensemble_step, against the same members stepped one "
@@ -228,73 +410,40 @@ def main():
     sys_, w = workload(args.workload)
     n = sys_.n_orb
 
-    # ---- initial state (untimed): linear mixing from the uniform density
-    # (X <- X + 0.04 (D0[X] - X), 50 steps per library call) in the fast
-    # FP16x3 chain (a kernel instance the timed modes do not use, so profiles
-    # of the timed path stay clean); the clusters' SCF is stiff, so MD starts
-    # from this partially converged density and the residual is reported
+    # ---- initial state (untimed): xlbomd_scf from the uniform density --
+    # linear mixing X <- X + 0.04 (D0[X] - X), then rank-12 Newton-Krylov
+    # steps -- with an FP64 density matrix.  The seeded cluster's SCF is stiff
+    # (it stalls near 0.3 even with rank-30 Newton steps), so MD starts from
+    # this partially converged density and its residual is reported.
     t = time.perf_counter()
     R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
-    hi = binding.handle_for(sys_, w, prec="fp16x3")
+    hi = binding.handle_for(sys_, w, prec="dm64_bf16x3")
     hi.set_geometry(R0)
     X0 = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
-    res = float("nan")
-    for k in range(args.init_mix // 50):
-        res = hi.scf(X0, m=8, tol=1e-12, max_iter=0, allow_noconv=True)
-        log(f"init mixing {50 * (k + 1)} steps: residual {res:.3e} ({time.perf_counter() - t:.1f} s)")
+    init = hi.scf(X0, m=12, tol=1e-10, max_iter=args.init_newton, mix=0.04, mix_tol=0.0,
+                  max_mix=args.init_mix, allow_noconv=True)
     hi.close()
-    h = binding.handle_for(sys_, w, prec=args.prec)
-    h.set_geometry(R0)
-    state = make_state(binding, torch, sys_, X0, dev)
-    h.md_init(state)
-    # The seeded random clusters are far from mechanical equilibrium (forces of
-    # tens of eV/Angstrom), so a free NVE trajectory heats by thousands of K per
-    # few steps and its per-step cost drifts with it.  By default every step
-    # therefore starts from the same prepared state (t0 after md_init); the
-    # restore is a few device copies on the library's stream, inside the
-    # timed region.  A step writes the nuclei, Y and the one ring slot of X it
-    # advances into, (head + 6) % 7; those are what the restore puts back.
-    slot = (state.head + 6) % 7
-    snap = (state.R.clone(), state.V.clone(), state.A.clone(), state.X[slot].clone(), state.Y.clone(),
-            state.head, state.mu)
-
-    def restore():
-        if args.trajectory == "reset":
-            for dst, src in zip((state.R, state.V, state.A, state.X[slot], state.Y), snap[:5]):
-                dst.copy_(src)
-            state.head, state.mu = snap[5], snap[6]
-
-    for k in range(args.warmup):
-        restore()
-        h.step(state, 1, report=False)
-        log(f"warmup step {k + 1} done")
-
-    # ---- timed region
-    h.profile(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        restore()
-        h.step(state, 1, report=False)
-    torch.cuda.synchronize()
+    init["seconds"] = time.perf_counter() - t
+    log(f"initial SCF: {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps, "
+        f"residual {init['residual']:.3e} ({init['seconds']:.1f} s)")
+
+    def prepared(prec):
+        h = binding.handle_for(sys_, w, prec=prec)
+        h.set_geometry(R0)
+        st = md_start(binding, torch, sys_, X0, dev)
+        h.md_init(st)
+        return h, st
+
+    # ---- timed leg of the requested mode: the value
+    h, state = prepared(args.prec)
+    snap = Snapshot(state)
+    elapsed, prof = timed_reset_leg(torch, h, state, snap, args.steps, args.warmup)
     log("timed steps done")
-    elapsed = time.perf_counter() - t0
-    prof = h.profile_read()
-    h.profile(False)
     steps_per_s = args.steps / elapsed
-    # one more (untimed) step with the full report: shadow energy, chain depth
-    restore()
+    snap.restore_step(state)
     rep = None if args.no_report else h.step(state, 1, report=True)[0]
-
-    # dominant kernel: the GEMM class with the larger share of the timed region
-    split_kind = args.prec.split("_")[-1]
-    g64, gs = prof["gemm_f64"], prof["gemm_split"]
-    # profiled work is executed MFMA flops (every split product counts)
-    if gs["ms"] >= g64["ms"]:
-        g, peak, kname, kcls = gs, PEAK_LOWP, f"split GEMM ({split_kind})", "gemm_split"
-    else:
-        g, peak, kname, kcls = g64, PEAK_F64, "FP64 GEMM", "gemm_f64"
-    gemm_tfs = g["work"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else 0.0
+    gemm_classes = [k for k in prof if k.startswith("gemm")]
     fk = prof["fock"]
     fock_gbs = fk["work"] / (fk["ms"] * 1e-3) / 1e9 if fk["ms"] > 0 else 0.0
     out = {
@@ -310,83 +459,54 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.prec],
         "data": "synthetic (seeded 840-atom carbon cluster, random-init integrals)",
-        "config": {"workload": "840-atom carbon cluster, 3360x3360 Fock, T_e 5000 K, Krylov rank 6, dt 0.5 fs",
+        "config": {"workload": (f"840-atom carbon cluster (seeded random packing, {sys_.params.j_pattern} J), "
+                                f"3360x3360 Fock, T_e 5000 K, Krylov rank 6, dt 0.5 fs; MD from the SCF iterate "
+                                f"after {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps "
+                                f"(residual {init['residual']:.3g}); every timed step restarts from that state"),
                    "n_atoms": sys_.n_atoms, "n_orb": n, "T_e_K": w["T_e"], "rank": w["m"], "dt_fs": w["dt"],
-                   "precision": args.prec, "init_mixing_steps": args.init_mix, "trajectory": args.trajectory,
-                   "init_residual": res},
-        "roofline": {"bound": "mfma", "kernel": kname, "achieved": gemm_tfs, "peak": peak,
-                     "unit": "TFLOP/s", "frac": gemm_tfs / peak, "traffic": kernel_traffic(kcls),
-                     "launches": g["launches"], "avg_launch_us": 1e3 * g["ms"] / max(g["launches"], 1),
-                     "share_of_step": g["ms"] * 1e-3 / elapsed},
-        "other_gemm": {"fp64_ms_per_step": g64["ms"] / args.steps, "split_ms_per_step": gs["ms"] / args.steps,
-                       "fp64_tflops": (g64["work"] / (g64["ms"] * 1e-3) / 1e12) if g64["ms"] > 0 else 0.0,
-                       "split_executed_tflops": (gs["work"] / (gs["ms"] * 1e-3) / 1e12) if gs["ms"] > 0 else 0.0,
-                       "fp64_launches": g64["launches"], "split_launches": gs["launches"]},
+                   "precision": args.prec, "j_pattern": sys_.params.j_pattern, "trajectory": "reset",
+                   "init": init},
+        "roofline": gemm_roofline(prof, gemm_classes, elapsed),
+        "kernel_classes": class_summary(prof, args.steps),
         "step_report": None if rep is None else {k: rep[k] for k in ("E_tot", "mu", "W0", "relres", "rank",
                                                                       "levels", "mu_passes")},
         "fock_roofline": {"bound": "hbm", "achieved": fock_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": fock_gbs / HBM_PEAK_GBS, "traffic": kernel_traffic("fock"), "launches": fk["launches"],
-                          "avg_launch_us": 1e3 * fk["ms"] / max(fk["launches"], 1)},
+                          "frac": fock_gbs / HBM_PEAK_GBS, "traffic": kernel_traffic("fock"),
+                          "launches": fk["launches"], "avg_launch_us": 1e3 * fk["ms"] / max(fk["launches"], 1)},
     }
 
-    # ---- split vs FP64 at the same state (untimed): D0, the response D1 to a
-    # seeded G(V), the Krylov kernel Y, forces and U at the prepared state, and
-    # the shadow-energy drift of a short free trajectory from it
-    if args.prec != "fp64" and not args.no_compare:
-        restore()
-        Xsnap = state.X.clone()  # the whole prepared history
-        Xc = state.x_current().clone()
-        rng = np.random.default_rng(11)
-        Vd = rng.standard_normal((n, n))
-        Vd = torch.tensor(Vd + Vd.T, dtype=torch.float64, device=dev)
-        beta = 1.0 / (8.617333262e-5 * w["T_e"])
-        cmp = {}
-        for pr, hh in (("split", h), ("fp64", None)):
-            hnd = hh or binding.handle_for(sys_, w, prec="fp64")
-            hnd.set_geometry(state.R)
-            F = torch.empty_like(Xc)
-            P = torch.empty_like(Xc)
-            hnd.fock(Xc, F, True)
-            _, S = hnd.fermi_dm(F, P, mu=state.mu)
-            f = torch.empty((sys_.n_atoms, 3), dtype=torch.float64, device=dev)
-            e = hnd.forces(P, Xc, f)
-            F1 = torch.empty_like(Xc)
-            hnd.fock(Vd, F1, False)
-            P1 = torch.empty_like(Xc)
-            hnd.dm_response(F1, P1)
-            Y = torch.empty_like(Xc)
-            hnd.krylov_kernel(Xc, P, w["m"], Y)
-            U = e[0] + e[1] + e[2] - 2.0 * S / beta
-            # drift: E_tot over a short free NVE trajectory from the prepared state
-            st = binding.MDState(R=snap[0].clone(), V=snap[1].clone(), A=snap[2].clone(), X=Xsnap.clone(),
-                                 Y=snap[4].clone(), head=snap[5], mu=snap[6])
-            reps = hnd.step(st, args.drift_steps, report=True)
-            E = np.array([r["E_tot"] for r in reps])
-            tfs = w["dt"] * np.arange(1, len(E) + 1)
-            drift = float(np.polyfit(tfs, E, 1)[0]) * 1000.0 / sys_.n_atoms
-            torch.cuda.synchronize()
-            cmp[pr] = dict(P=P.cpu().numpy(), P1=P1.cpu().numpy(), Y=Y.cpu().numpy(), f=f.cpu().numpy(), U=U,
-                           drift=drift)
-            if hh is None:
-                hnd.close()
-        a_, b_ = cmp["split"], cmp["fp64"]
-        fro = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
-        W0 = float(np.linalg.norm(b_["P"] - Xc.cpu().numpy()))
-        ferr = float(np.abs(a_["f"] - b_["f"]).max())
-        out["force_err_vs_fp64_eV_per_A"] = ferr
-        out["density_err_vs_fp64"] = float(np.abs(a_["P"] - b_["P"]).max())
-        out["force_err_ok"] = ferr <= 1e-4
-        out["split_vs_fp64"] = {
-            "D0_maxabs": float(np.abs(a_["P"] - b_["P"]).max()) / 2.0, "D0_rel_fro": fro(a_["P"], b_["P"]),
-            "D1_rel_fro": fro(a_["P1"], b_["P1"]), "Y_rel_W0": float(np.linalg.norm(a_["Y"] - b_["Y"]) / W0),
-            "forces_maxabs_eV_per_A": ferr, "U_eV_per_atom": abs(a_["U"] - b_["U"]) / sys_.n_atoms,
-            "drift_eV_per_ps_per_atom": {"split": a_["drift"], "fp64": b_["drift"],
-                                         "steps": args.drift_steps, "trajectory": "free NVE from the prepared state"}}
+    # ---- free NVE trajectory of the same mode from the same state
+    if args.free_steps:
+        el, reps = free_leg(binding, torch, h, snap, args.free_steps)
+        out["free_trajectory"] = {"steps_per_s": args.free_steps / el, "ms_per_step": 1e3 * el / args.free_steps,
+                                  "steps": args.free_steps,
+                                  "levels": [r["levels"] for r in reps], "mu_passes": [r["mu_passes"] for r in reps],
+                                  "W0": [r["W0"] for r in reps], "T_ion_K": [r["T_ion"] for r in reps]}
+        log("free trajectory done")
+    h.close()
+
+    # ---- timed FP64 leg from the same state
+    if args.fp64_steps and args.prec != "fp64":
+        h64, st64 = prepared("fp64")
+        el64, prof64 = timed_reset_leg(torch, h64, st64, Snapshot(st64), args.fp64_steps, 1)
+        h64.close()
+        out["fp64_leg"] = {"steps_per_s": args.fp64_steps / el64, "ms_per_step": 1e3 * el64 / args.fp64_steps,
+                           "steps": args.fp64_steps, "warmup": 1,
+                           "roofline": gemm_roofline(prof64, [k for k in prof64 if k.startswith("gemm_f64")], el64),
+                           "kernel_classes": class_summary(prof64, args.fp64_steps)}
+        out["speedup_over_fp64"] = steps_per_s / out["fp64_leg"]["steps_per_s"]
+        log("FP64 leg done")
+
+    # ---- untimed accuracy of the split mode against FP64
+    if args.compare_steps and args.prec != "fp64":
+        cmp = compare_legs(binding, torch, np, sys_, w, args.prec, X0, args.compare_steps, dev)
+        out["force_err_vs_fp64_eV_per_A"] = cmp["same_state_force_err_eV_per_A"]["max"]
+        out["force_err_ok"] = out["force_err_vs_fp64_eV_per_A"] <= 1e-4
+        out["split_vs_fp64"] = cmp
 
     if not args.no_cpu_baseline:
         log("timing the oracle sample ...")
-        out["cpu_baseline"] = cpu_baseline(sys_, w, state.x_current().cpu().numpy(), args.cpu_threads)
-    h.close()
+        out["cpu_baseline"] = cpu_baseline(sys_, w, X0.cpu().numpy(), args.cpu_threads)
     print(json.dumps(out))
 
 

@@ -268,11 +268,37 @@ xlbomd_status xlbomd_ensemble_step(xlbomd_handle *h, xlbomd_md_state *st, int co
  * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5). */
 xlbomd_status xlbomd_md_init(xlbomd_handle h, xlbomd_md_state *st);
 
-/* Ground state by Newton-Krylov iterations X <- X - lam Y (the paper's KSA SCF),
- * preceded by linear mixing until ||P0 - X|| < mix_tol.  X: DEVICE n x n in/out
- * (initial guess in, D_min out).  Returns XLBOMD_E_NOCONV past max_iter. */
-xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, int m, double tol, int max_iter,
-                         double *residual);
+/* Settings of xlbomd_scf.  Linear mixing X <- X + mix (P0[X] - X) runs first,
+ * until the residual ||P0[X] - X||_F is below mix_tol (or tol) or max_mix
+ * steps are taken; then Newton-Krylov steps X <- X - lam Y with Y the rank-m
+ * kernel of eq. 34 (the paper's KSA SCF, Results: SCF optimisation), lam
+ * halved from 1 until the residual decreases (down to 1/16384). */
+typedef struct {
+  int m;           /* Krylov rank of a Newton step, 1 .. 30                  */
+  double tol;      /* stop once the residual is <= tol (spin-summed, F-norm) */
+  int max_iter;    /* Newton-Krylov steps, >= 0                              */
+  double mix;      /* linear-mixing coefficient, 0 < mix <= 1               */
+  double mix_tol;  /* mixing ends below this residual                       */
+  int max_mix;     /* at most this many mixing steps, >= 0                   */
+} xlbomd_scf_params;
+
+/* What xlbomd_scf did (host). */
+typedef struct {
+  double residual;   /* final ||P0[X] - X||_F                                  */
+  int mix_steps;     /* mixing steps taken                                     */
+  int newton_steps;  /* Newton-Krylov steps taken                              */
+  int evaluations;   /* Fock builds + density matrices, line-search trials too */
+  int responses;     /* density-matrix responses (Krylov directions)           */
+} xlbomd_scf_report;
+
+/* Ground state D_min of the self-consistency P0[X] = X (Methods, section 5:
+ * the MD history starts from it).  X: DEVICE n x n in/out (initial guess in,
+ * D_min out).  history: HOST, nullable, receives the residual after every
+ * mixing step and every Newton step, at most history_len values.  rep: HOST,
+ * nullable.  Returns XLBOMD_E_NOCONV if the residual is still above tol at
+ * the end (X then holds the last iterate and rep is filled). */
+xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, const xlbomd_scf_params *p, double *history,
+                         int history_len, xlbomd_scf_report *rep);
 
 /* Diagnostic: C = A B (+ optional symmetric-output mode) with the response-chain
  * GEMM of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric).  In
@@ -286,11 +312,13 @@ xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, d
  * 65536 launches; later ones are not recorded); 0 stops.  Either call clears
  * earlier records. */
 xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
-/* Sums over the recorded launches, 4 classes x {launches, milliseconds,
- * work}: [0..2] FP64 GEMM and [3..5] split-precision GEMM (work = executed
- * MFMA flops: 2n^3 per product, n^3 for a product with symmetric output, times
- * the 3 or 6 MFMA products a split product runs), [6..8] Fock build and
- * [9..11] forces (work = algorithmic HBM bytes: 220 per atom pair plus 16 n^2). */
+/* Sums over the recorded launches, 10 classes x {launches, milliseconds,
+ * work} (30 doubles): GEMMs by arithmetic and output kind, [0] FP64 full,
+ * [1] FP64 symmetric output, [2] / [3] BF16x3 split full / symmetric, [4] / [5]
+ * BF16x6, [6] / [7] FP16x3 (work = executed MFMA flops: 2n^3 per product, n^3
+ * for a product with symmetric output, times the 3 or 6 MFMA products a split
+ * product runs), [8] Fock build and [9] forces (work = algorithmic HBM bytes:
+ * 220 per atom pair plus 16 n^2). */
 xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
 
 #ifdef __cplusplus

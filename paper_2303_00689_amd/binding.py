@@ -58,6 +58,16 @@ class MDStateC(C.Structure):
                 ("Y", C.c_void_p), ("head", C.c_int), ("mu", C.c_double)]
 
 
+class SCFParams(C.Structure):
+    _fields_ = [("m", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("mix", C.c_double),
+                ("mix_tol", C.c_double), ("max_mix", C.c_int)]
+
+
+class SCFReport(C.Structure):
+    _fields_ = [("residual", C.c_double), ("mix_steps", C.c_int), ("newton_steps", C.c_int),
+                ("evaluations", C.c_int), ("responses", C.c_int)]
+
+
 class Report(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("E_tot", "KE", "U", "TS", "T_ion", "mu", "W0", "relres")] + \
                [("rank", C.c_int), ("status", C.c_int), ("levels", C.c_int), ("mu_passes", C.c_int)]
@@ -96,7 +106,7 @@ def load():
     lib.xlbomd_step_langevin.argtypes = [vp, C.POINTER(MDStateC), i, d, d, vp, C.POINTER(Report)]
     lib.xlbomd_ensemble_step.argtypes = [C.POINTER(vp), C.POINTER(MDStateC), i, i, C.POINTER(Report)]
     lib.xlbomd_md_init.argtypes = [vp, C.POINTER(MDStateC)]
-    lib.xlbomd_scf.argtypes = [vp, vp, i, d, i, pd]
+    lib.xlbomd_scf.argtypes = [vp, vp, C.POINTER(SCFParams), pd, i, C.POINTER(SCFReport)]
     lib.xlbomd_matmul.argtypes = [vp, vp, vp, vp, i, i]
     lib.xlbomd_profile.argtypes = [vp, i]
     lib.xlbomd_profile_read.argtypes = [vp, pd]
@@ -281,46 +291,35 @@ class Handle:
     def profile(self, enable=True):
         self._check(self.lib.xlbomd_profile(self.h, int(bool(enable))), "profile")
 
-    def profile_read(self):
-        out = (C.c_double * 12)()
-        self._check(self.lib.xlbomd_profile_read(self.h, out), "profile_read")
-        names = ("gemm_f64", "gemm_split", "fock", "forces")
-        return {nm: dict(launches=int(out[3 * k]), ms=out[3 * k + 1], work=out[3 * k + 2])
-                for k, nm in enumerate(names)}
+    PROFILE_CLASSES = ("gemm_f64", "gemm_f64_sym", "gemm_bf16x3", "gemm_bf16x3_sym", "gemm_bf16x6",
+                       "gemm_bf16x6_sym", "gemm_fp16x3", "gemm_fp16x3_sym", "fock", "forces")
 
-    def scf(self, X, m=20, tol=1e-10, max_iter=100, allow_noconv=False):
-        """Returns the final residual ||D0[X] - X||_F; with allow_noconv a run that
-        stops above tol returns its residual instead of raising."""
-        res = C.c_double(0.0)
-        st = self.lib.xlbomd_scf(self.h, self._mat(X), int(m), float(tol), int(max_iter), C.byref(res))
+    def profile_read(self):
+        """Per kernel class: launches, milliseconds and work (see xlbomd_profile_read)."""
+        out = (C.c_double * 30)()
+        self._check(self.lib.xlbomd_profile_read(self.h, out), "profile_read")
+        return {nm: dict(launches=int(out[3 * k]), ms=out[3 * k + 1], work=out[3 * k + 2])
+                for k, nm in enumerate(self.PROFILE_CLASSES)}
+
+    def scf(self, X, m=20, tol=1e-10, max_iter=100, mix=0.04, mix_tol=1e-2, max_mix=5000,
+            allow_noconv=False, history=0):
+        """Ground state into X (xlbomd_scf).  Returns a dict with the final
+        residual ||D0[X] - X||_F, the mixing and Newton steps taken, the
+        density-matrix evaluations and responses, and (history > 0) the first
+        `history` residuals.  With allow_noconv a run that stops above tol
+        returns its report instead of raising."""
+        prm = SCFParams(int(m), float(tol), int(max_iter), float(mix), float(mix_tol), int(max_mix))
+        rep = SCFReport()
+        hist = (C.c_double * max(int(history), 1))()
+        st = self.lib.xlbomd_scf(self.h, self._mat(X), C.byref(prm), hist if history else None,
+                                 int(history), C.byref(rep))
         if not (allow_noconv and st == -3):
             self._check(st, "scf")
-        return res.value
-
-
-def ensemble_step(handles, states, n_steps=1, report=True):
-    """Advance every (handle, state) pair by n_steps concurrently
-    (xlbomd_ensemble_step); returns one list of reports per member."""
-    count = len(handles)
-    if len(states) != count:
-        raise XLBOMDError("one state per handle")
-    if count == 0:
-        return []
-    lib = handles[0].lib
-    hs = (C.c_void_p * count)(*[h.h for h in handles])
-    scs = (MDStateC * count)(*[s._c(h) for h, s in zip(handles, states)])
-    reps = (Report * max(count * n_steps, 1))() if report else None
-    st = lib.xlbomd_ensemble_step(hs, scs, int(count), int(n_steps), reps)
-    for k, (h, s) in enumerate(zip(handles, states)):
-        s.head, s.mu = scs[k].head, scs[k].mu
-    if st != 0:
-        msgs = "; ".join(f"member {k}: {h.lib.xlbomd_last_error(h.h).decode()}" for k, h in enumerate(handles)
-                         if h.lib.xlbomd_last_error(h.h))
-        raise XLBOMDError(f"ensemble_step failed: {STATUS.get(st, st)} ({msgs})")
-    if not report:
-        return None
-    return [[{k: getattr(reps[m * n_steps + j], k) for k, _ in Report._fields_} for j in range(n_steps)]
-            for m in range(count)]
+        out = {k: getattr(rep, k) for k, _ in SCFReport._fields_}
+        if history:
+            nh = min(int(history), rep.mix_steps + rep.newton_steps + 1)
+            out["history"] = list(hist[:nh])
+        return out
 
 
 def spectral_bounds_noalloc(F, stream=None):

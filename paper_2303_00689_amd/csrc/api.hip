@@ -289,8 +289,15 @@ xlbomd_status fail(xlbomd_ctx *c, xlbomd_status st, const char *fmt, ...) {
 
 bool dev_alloc(void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
 
-// kernel classes of the timing hooks
-enum { PC_GEMM64 = 0, PC_GEMMS = 1, PC_FOCK = 2, PC_FORCE = 3, PC_N = 4 };
+// kernel classes of the timing hooks: GEMMs by precision and output kind (each
+// class is one kernel at a given n), then the pair passes
+enum {
+  PC_GEMM64 = 0,      // + sym: FP64 full / symmetric output
+  PC_GEMMS = 2,       // + 2 (prec - 1) + sym: BF16x3, BF16x6, FP16x3 split, full / symmetric
+  PC_FOCK = 8,
+  PC_FORCE = 9,
+  PC_N = 10
+};
 
 int prof_begin(xlbomd_ctx *c) {
   if (!c->prof) return -1;
@@ -333,7 +340,8 @@ void mm_p(xlbomd_ctx *c, int prec, const void *A, const void *B, void *out, doub
   // profiled work: executed MFMA flops (a split product runs 3 or 6 MFMA products)
   const double n = (double)c->n;
   const double parts = prec == XLBOMD_FP64 ? 1.0 : (prec == XLBOMD_BF16X6 ? 6.0 : 3.0);
-  prof_end(c, e, prec == XLBOMD_FP64 ? PC_GEMM64 : PC_GEMMS, parts * g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
+  const int cls = (prec == XLBOMD_FP64 ? PC_GEMM64 : PC_GEMMS + 2 * (prec - 1)) + (sym ? 1 : 0);
+  prof_end(c, e, cls, parts * g.nprod * (sym ? 1.0 : 2.0) * n * n * n);
   ++c->n_gemm;
 }
 
@@ -1521,56 +1529,74 @@ xlbomd_status xlbomd_step_langevin(xlbomd_handle c, xlbomd_md_state *st, int n_s
   return md_steps(c, st, n_steps, rep, c1, c2, xi);
 }
 
-xlbomd_status xlbomd_scf(xlbomd_handle c, double *X, int m, double tol, int max_iter, double *residual) {
-  if (!c || !X || m < 1 || m > MMAX - 2 || max_iter < 0) return XLBOMD_E_ARG;
+xlbomd_status xlbomd_scf(xlbomd_handle c, double *X, const xlbomd_scf_params *p, double *history,
+                         int history_len, xlbomd_scf_report *rep) {
+  if (!c || !X || !p) return XLBOMD_E_ARG;
+  const int m = p->m;
+  if (m < 1 || m > MMAX - 2 || p->max_iter < 0 || p->max_mix < 0 || !(p->mix > 0.0 && p->mix <= 1.0) ||
+      !(p->tol >= 0.0) || !(p->mix_tol >= 0.0) || history_len < 0)
+    return fail(c, XLBOMD_E_ARG, "bad scf settings");
   if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
   const int n2 = (int)c->n2;
   xlbomd_status s;
+  xlbomd_scf_report r{};
+  int nh = 0;
+  auto record = [&](double v) {
+    if (history && nh < history_len) history[nh++] = v;
+  };
   // the Krylov kernel owns f64[0..4], Vk[0..m-1], Wk[0..m-1]; the SCF keeps its
   // own matrices in the two slots after them
   if ((s = ensure_krylov(c, m + 2))) return s;
   double *F = c->f64[5];
   double *Pm = c->Wk[m], *Ptrial = c->Wk[m + 1], *Ystep = c->Vk[m], *Xtrial = c->Vk[m + 1];
   double mu = NAN;
-  auto resid = [&](const double *Xc, double *Pout, double &r) -> xlbomd_status {
+  auto resid = [&](const double *Xc, double *Pout, double &res) -> xlbomd_status {
     fock_t(c, Xc, F, 1);
     xlbomd_status q = fermi(c, F, &mu, Pout, true);
     if (q) return q;
+    ++r.evaluations;
     axpby(n2, 1.0, Pout, -1.0, Xc, c->f64[0], 0, c->s);
     const void *a[1] = {c->f64[0]};
     dots(n2, 1, a, a, c->dscal + S_DOTS, 0, c->red, c->s);
     double r2;
     q = get_scalars(c, S_DOTS, 1, &r2);
-    r = std::sqrt(r2);
+    res = std::sqrt(r2);
+    if (!std::isfinite(res)) return fail(c, XLBOMD_E_NONFINITE, "non-finite SCF residual");
     return q;
   };
   // linear mixing settles into a stable fixed point; Newton-Krylov then converges fast
-  double r = 0.0;
-  const int max_mix = 50 * std::max(max_iter, 1);
-  for (int it = 0; it < max_mix; ++it) {
-    if ((s = resid(X, Pm, r))) return s;
-    if (r < 1e-2 || r <= tol) break;
-    axpby(n2, 0.96, X, 0.04, Pm, X, 0, c->s);
+  double res = 0.0;
+  if ((s = resid(X, Pm, res))) return s;
+  record(res);
+  while (r.mix_steps < p->max_mix && res > p->mix_tol && res > p->tol) {
+    axpby(n2, 1.0 - p->mix, X, p->mix, Pm, X, 0, c->s);
+    ++r.mix_steps;
+    if ((s = resid(X, Pm, res))) return s;
+    record(res);
   }
-  for (int it = 0; it < max_iter && r > tol; ++it) {
+  while (r.newton_steps < p->max_iter && res > p->tol) {
     int rank;
     double rel;
     // the chain cached by the last resid() call belongs to the current X
     if ((s = krylov(c, X, Pm, m, 0.0, Ystep, &rank, &rel, nullptr))) return s;
+    r.responses += rank;
     double lam = 1.0, rt = 0.0;
     while (true) {
       axpby(n2, 1.0, X, -lam, Ystep, Xtrial, 0, c->s);
       if ((s = resid(Xtrial, Ptrial, rt))) return s;
-      if (rt < r || lam < 1e-4) break;
+      if (rt < res || lam < 1e-4) break;
       lam *= 0.5;
     }
     HIPCHK(c, hipMemcpyAsync(X, Xtrial, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
     HIPCHK(c, hipMemcpyAsync(Pm, Ptrial, c->n2 * 8, hipMemcpyDeviceToDevice, c->s));
-    r = rt;
+    res = rt;
+    ++r.newton_steps;
+    record(res);
   }
-  if (residual) *residual = r;
+  r.residual = res;
+  if (rep) *rep = r;
   HIPCHK(c, hipStreamSynchronize(c->s));
-  if (!(r <= tol)) return fail(c, XLBOMD_E_NOCONV, "SCF residual %.3e above tolerance", r);
+  if (!(res <= p->tol)) return fail(c, XLBOMD_E_NOCONV, "SCF residual %.3e above tolerance", res);
   return XLBOMD_OK;
 }
 

@@ -36,14 +36,15 @@ def ground(lib):
     h.set_geometry(torch.tensor(s.R, dtype=torch.float64, device=dev))
     n = s.n_orb
     X = torch.eye(n, dtype=torch.float64, device=dev) * (s.n_elec / n)
-    res = h.scf(X, m=20, tol=1e-10, max_iter=100)
+    rep = h.scf(X, m=20, tol=1e-10, max_iter=100, history=400)
     torch.cuda.synchronize()
-    yield s, w, h, X, res
+    yield s, w, h, X, rep
     h.close()
 
 
 def test_scf_reaches_the_oracle_ground_state(ground):
-    s, w, h, X, res = ground
+    s, w, h, X, rep = ground
+    res = rep["residual"]
     assert res <= 1e-10
     Xg = X.cpu().numpy()
     beta = density.beta_of(w["T_e"])
@@ -86,3 +87,30 @@ def test_md_from_the_ground_state_matches_stored_trajectory(ground, lib):
         assert g["rank"] == r["rank"]
     torch.cuda.synchronize()
     assert np.abs(state.R.cpu().numpy() - np.array(ref["steps"][-1]["R"])).max() <= 1e-11
+
+
+def test_scf_report_and_history(ground, lib):
+    """The report counts what the iteration did: one residual per mixing and
+    Newton step after the first, the mixing phase ends below mix_tol, the
+    Newton phase only decreases the residual (backtracking), and every Newton
+    step spends at least one density-matrix evaluation and one response."""
+    s, w, h, X, rep = ground
+    hist = rep["history"]
+    assert len(hist) == 1 + rep["mix_steps"] + rep["newton_steps"]
+    assert hist[-1] == rep["residual"]
+    k = rep["mix_steps"]
+    assert all(v > 1e-2 for v in hist[:k]) and hist[k] <= 1e-2
+    newton = hist[k:]
+    assert all(b < a for a, b in zip(newton, newton[1:]))
+    assert rep["evaluations"] >= 1 + rep["mix_steps"] + rep["newton_steps"]
+    assert rep["responses"] >= rep["newton_steps"]
+    print(f"10 atoms: {rep['mix_steps']} mixing steps, {rep['newton_steps']} Newton-Krylov steps, "
+          f"{rep['evaluations']} evaluations, {rep['responses']} responses")
+
+
+def test_scf_rejects_bad_settings(ground, lib):
+    s, w, h, X, rep = ground
+    for kw in (dict(m=0), dict(m=31), dict(mix=0.0), dict(mix=1.5), dict(max_iter=-1), dict(max_mix=-1),
+               dict(tol=-1.0)):
+        with pytest.raises(lib.XLBOMDError):
+            h.scf(X.clone(), **kw)
