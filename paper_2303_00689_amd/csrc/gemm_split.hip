@@ -32,6 +32,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <utility>
+
 namespace xl {
 namespace {
 
@@ -500,10 +502,12 @@ __global__ __launch_bounds__(320) void k_gemm_split_lds(GemmArgs p, int T) {
 //
 // The larger wave tiles cut the LDS bytes read per MFMA against 64 x 64
 // waves.  All four waves stream the FP32 panels (A rows and B rows x 32 k)
-// into LDS with buffer loads, two stages deep.  The stages are separate LDS
-// arrays, so the loads into one stage carry no wait for the reads of the
-// other, and the one barrier per panel is also where the next stage's loads
-// are complete.  Each wave splits its fragments into BF16 parts on read.
+// into LDS with buffer loads, two stages deep, and read every fragment of the
+// next panel into registers under the MFMAs of the current one.  The stages
+// are separate LDS arrays, so the loads into one stage carry no wait for the
+// reads of the other, and the one barrier per panel is also where the next
+// stage's loads are complete.  Each wave splits its fragments into BF16 parts
+// on read.
 // BF16 parts of eight FP32 values, two at a time: v_cvt_pk_bf16_f32 rounds a
 // pair to nearest even, and each rounded part goes back to FP32 by a shift
 // or a mask of its half of the packed word.
@@ -539,6 +543,16 @@ __device__ inline void split8_pk(const float (&x)[8], us8 (&o)[3]) {
 constexpr int BIG_GROUP = 3;          // tile rows per L2-sharing group
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor word 3 (32-bit data format)
 
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0 .. N - 1, each i a compile-time constant
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles) or 5 (160)
 template <int MODE, int BNB>
 __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
@@ -573,7 +587,7 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   const int kt_per = n / TK;
   const int ktiles = kt_per * p.nprod;
 
-  // loads: wave w fills stage rows [112 w, 112 w + 112) (waves 0, 1: A rows,
+  // loads: wave w fills stage rows [BW w, BW w + BW) (waves 0, 1: A rows,
   // 2, 3: B rows), eight rows per instruction; lane -> row lane / 8,
   // physical chunk lane % 8
   const int lr = lane >> 3, lpc = lane & 7;
@@ -581,7 +595,7 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   const int g0 = (ldA ? i0 : j0) + (wave & 1) * BW;
   // Buffer loads to LDS: the lane's byte offset of each load row is computed
   // once (n^2 FP32 values fit in 32 bits for n <= 32767) and the k panel is
-  // the scalar offset.  Stage row 112 w + 8 j + lr has swizzle
+  // the scalar offset.  Stage row BW w + 8 j + lr has swizzle
   // lpc ^ lr ^ (j & 1).
   unsigned roff[BW / 8];
 #pragma unroll
@@ -600,7 +614,6 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
     for (int j = 0; j < BW / 8; ++j)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&stg[(wave * BW + 8 * j) * LROW], 16, roff[j], kb,
                                                0, 0);
-    __builtin_amdgcn_sched_barrier(0);
   };
 
   const int fr = lane & 15, fq = lane >> 4;
@@ -626,106 +639,82 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
     acc[r][c] = mfma(a[0], bc[0], acc[r][c], false);
   };
   constexpr int TERMS = (MODE == 1) ? 6 : 3;
-  constexpr int RM = BNB * TERMS;  // MFMAs per row block
+  constexpr int RM = BNB * TERMS;                    // MFMAs per row block
+  constexpr int SPLIT_VALU = (MODE == 1) ? 44 : 24;  // VALU instructions of one split8_pk
 
-  // Software pipeline over k panels.  Within a panel the A fragment of row
-  // block r + 1 is split, and that of r + 2 read, under the MFMAs of block r.
-  // The one barrier per panel sits after row block BNB - 3, whose reads are
-  // the panel's last: past it the next panel's loads have landed (each wave
-  // waits for its own), so the last two row blocks read and split the next
-  // panel's B fragments and first A fragments under their MFMAs, and the
-  // loads of the panel after next go into the stage just read.  Group
-  // barriers interleave the MFMAs with that VALU and LDS work.
-  us8 b[BNB][3], a[3];
-  float xn[8];
+  // Software pipeline over k panels with a full panel of lookahead: the LDS
+  // stages hold panels k (already in registers) and k + 1, and every fragment
+  // of panel k + 1 is read from LDS under the MFMAs of panel k, while panel
+  // k + 2 streams into the stage of panel k.  Registers: raw A of a panel
+  // (block r is refilled with the next panel's block r once split), split A
+  // of the row block being multiplied (a) and of the next one (an), split B
+  // of the current panel (b) and of the next (bn), raw B blocks of the next
+  // panel in flight (xb).  Per row block the next panel's reads go first,
+  // then the block's MFMAs interleaved with the splits of fragments read at
+  // least one row block earlier.  Per accumulator the MFMA sequence over k is
+  // fixed, so the result does not depend on this schedule.
+  float xa[BNB][8], xb[BNB][8];
+  us8 b[BNB][3], bn[BNB][3], a[3];
   issue(0, st0);
   if (ktiles > 1) issue(1, st1);
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
-  {
+#pragma unroll
+  for (int c = 0; c < BNB; ++c) {
     float x[8];
-#pragma unroll
-    for (int c = 0; c < BNB; ++c) {
-      fetch(st0, BT + wn + 16 * c + fr, x);
-      split8_pk<MODE>(x, b[c]);
-    }
-    fetch(st0, wm + fr, x);
-    split8_pk<MODE>(x, a);
-    fetch(st0, wm + 16 + fr, xn);
+    fetch(st0, BT + wn + 16 * c + fr, x);
+    split8_pk<MODE>(x, b[c]);
   }
-  for (int kt = 0; kt < ktiles; ++kt) {
-    float *cur = (kt & 1) ? st1 : st0;
-    float *nxt = (kt & 1) ? st0 : st1;
-    us8 an[3];
 #pragma unroll
-    for (int r = 0; r < BNB - 2; ++r) {
-      split8_pk<MODE>(xn, an);
-      fetch(cur, wm + 16 * (r + 2) + fr, xn);
+  for (int r = 0; r < BNB; ++r) fetch(st0, wm + 16 * r + fr, xa[r]);
+  split8_pk<MODE>(xa[0], a);
+  // every read of stage 0 is done before any wave loads panel 2 into it (the
+  // compiler does not wait for buffer loads to LDS or count them at barriers)
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    float *cur = (kt & 1) ? st1 : st0;  // panel kt, already in registers
+    float *nxt = (kt & 1) ? st0 : st1;  // panel kt + 1, landed
+    if (kt + 2 < ktiles) issue(kt + 2, cur);
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<BNB>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      // the next panel's A block r and B block r + 1 (B blocks 0 and 1 in
+      // row block 0).  The last panel reads the other stage too (in bounds,
+      // values unused), so that no branch separates reads and uses.
+      constexpr int nreads = 2 + (r == 0 ? 2 : 0) + (r + 1 < BNB ? 2 : 0);
+      fetch(nxt, wm + 16 * r + fr, xa[r]);
+      if (r == 0) fetch(nxt, BT + wn + fr, xb[0]);
+      if (r + 1 < BNB) fetch(nxt, BT + wn + 16 * (r + 1) + fr, xb[r + 1 < BNB ? r + 1 : 0]);
+      // splits under this row block's MFMAs: the A block multiplied next (the
+      // next panel's block 0 in the last row block) and the B block(s) read
+      // at least one row block earlier
+      us8 an[3];
+      split8_pk<MODE>(r + 1 < BNB ? xa[r + 1 < BNB ? r + 1 : 0] : xa[0], an);
+      constexpr int nsplit = 1 + (r >= 1 ? 1 : 0) + (r == BNB - 1 ? 1 : 0);
+      if (r >= 1) split8_pk<MODE>(xb[r >= 1 ? r - 1 : 0], bn[r >= 1 ? r - 1 : 0]);
+      if (r == BNB - 1) split8_pk<MODE>(xb[BNB - 1], bn[BNB - 1]);
 #pragma unroll
       for (int c = 0; c < BNB; ++c) mma(r, c, a, b[c]);
-      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // DS read
+      constexpr int per = (nsplit * SPLIT_VALU + RM - 1) / RM;
+      __builtin_amdgcn_sched_group_barrier(0x100, nreads, 0);  // DS read
 #pragma unroll
-      for (int i = 0; i < RM; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
+      for (int q = 0; q < RM; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, per, 0);  // VALU
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int q = 0; q < 3; ++q) a[q] = an[q];
-    }
-    // the LDS writes of this wave's buffer loads are done once vmcnt drains
-    // (the compiler does not wait for them here by itself)
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    __syncthreads();
-    if (kt + 2 < ktiles) issue(kt + 2, cur);
-    us8 bn[BNB][3];
-    constexpr int H = (BNB + 1) / 2;  // next-panel B blocks split under row block BNB - 2
-    // row block BNB - 2: split its successor's A block; B blocks 0 .. H - 1 of the next panel
-    split8_pk<MODE>(xn, an);
-#pragma unroll
-    for (int c = 0; c < H; ++c) {
-      float x[8];
-      fetch(nxt, BT + wn + 16 * c + fr, x);
-      split8_pk<MODE>(x, bn[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < BNB; ++c) mma(BNB - 2, c, a, b[c]);
-    __builtin_amdgcn_sched_group_barrier(0x100, 2 * H, 0);
-#pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // row block BNB - 1: B blocks H .. BNB - 1 and A blocks 0, 1 of the next panel
-#pragma unroll
-    for (int c = H; c < BNB; ++c) {
-      float x[8];
-      fetch(nxt, BT + wn + 16 * c + fr, x);
-      split8_pk<MODE>(x, bn[c]);
-    }
-    us8 a0[3];
-    {
-      float x[8];
-      fetch(nxt, wm + fr, x);
-      split8_pk<MODE>(x, a0);
-    }
-#pragma unroll
-    for (int c = 0; c < BNB; ++c) mma(BNB - 1, c, an, b[c]);
-    fetch(nxt, wm + 16 + fr, xn);
-    __builtin_amdgcn_sched_group_barrier(0x100, 2 * (BNB - H) + 4, 0);
-#pragma unroll
-    for (int i = 0; i < RM; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+    });
 #pragma unroll
     for (int c = 0; c < BNB; ++c)
 #pragma unroll
       for (int q = 0; q < 3; ++q) b[c][q] = bn[c][q];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) a[q] = a0[q];
+    // panel kt + 2 has landed (this wave's loads) and every read of panel
+    // kt + 1 is done before the barrier hands the stages over
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+    __syncthreads();
   }
 
   const float *C1 = (const float *)p.C1;
