@@ -322,6 +322,31 @@ class Handle:
         return out
 
 
+def ensemble_step(handles, states, n_steps=1, report=True):
+    """Advance every (handle, state) pair by n_steps concurrently
+    (xlbomd_ensemble_step); returns one list of reports per member."""
+    count = len(handles)
+    if len(states) != count:
+        raise XLBOMDError("one state per handle")
+    if count == 0:
+        return []
+    lib = handles[0].lib
+    hs = (C.c_void_p * count)(*[h.h for h in handles])
+    scs = (MDStateC * count)(*[s._c(h) for h, s in zip(handles, states)])
+    reps = (Report * max(count * n_steps, 1))() if report else None
+    st = lib.xlbomd_ensemble_step(hs, scs, int(count), int(n_steps), reps)
+    for k, (h, s) in enumerate(zip(handles, states)):
+        s.head, s.mu = scs[k].head, scs[k].mu
+    if st != 0:
+        msgs = "; ".join(f"member {k}: {h.lib.xlbomd_last_error(h.h).decode()}" for k, h in enumerate(handles)
+                         if h.lib.xlbomd_last_error(h.h))
+        raise XLBOMDError(f"ensemble_step failed: {STATUS.get(st, st)} ({msgs})")
+    if not report:
+        return None
+    return [[{k: getattr(reps[m * n_steps + j], k) for k, _ in Report._fields_} for j in range(n_steps)]
+            for m in range(count)]
+
+
 def spectral_bounds_noalloc(F, stream=None):
     """(lo, hi) enclosing the spectrum of the symmetric n x n FP64 device
     tensor F, from xlbomd_spectral_bounds_noalloc (no handle, no allocation)."""

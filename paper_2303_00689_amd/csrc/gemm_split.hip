@@ -500,14 +500,13 @@ __global__ __launch_bounds__(320) void k_gemm_split_lds(GemmArgs p, int T) {
 // cluster), BNB = 5 gives 160 x 160 tiles (symmetric outputs: 231 upper
 // tiles there), so either fills the 256 compute units in one round.
 //
-// The larger wave tiles cut the LDS bytes read per MFMA against 64 x 64
-// waves.  All four waves stream the FP32 panels (A rows and B rows x 32 k)
-// into LDS with buffer loads, two stages deep, and read every fragment of the
-// next panel into registers under the MFMAs of the current one.  The stages
-// are separate LDS arrays, so the loads into one stage carry no wait for the
-// reads of the other, and the one barrier per panel is also where the next
-// stage's loads are complete.  Each wave splits its fragments into BF16 parts
-// on read.
+// The larger wave tiles cut the bytes moved per MFMA against 64 x 64 waves.
+// Each wave loads its own A rows straight from global memory into registers
+// (the two waves sharing them both load them: L2 hits), and the four waves
+// stream the B panels (B rows x 32 k) into LDS with buffer loads, 3 or 4
+// stages deep, so LDS carries only B.  Every fragment of the next k panel is
+// loaded under the MFMAs of the current one.  Each wave splits its fragments
+// into BF16 parts on read.
 // BF16 parts of eight FP32 values, two at a time: v_cvt_pk_bf16_f32 rounds a
 // pair to nearest even, and each rounded part goes back to FP32 by a shift
 // or a mask of its half of the packed word.
@@ -553,27 +552,28 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles) or 5 (160)
-template <int MODE, int BNB>
+// BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles) or 5 (160);
+// STAGES k panels of B in LDS
+template <int MODE, int BNB, int STAGES>
 __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   // BF16 splits only: the FP16 split's second accumulator does not fit
   static_assert(MODE == 0 || MODE == 1, "large-tile kernel: BF16 splits only");
+  static_assert(STAGES >= 2 && STAGES <= 4, "2 to 4 LDS stages");
   constexpr int BW = 16 * BNB;           // wave tile edge
   constexpr int BT = 2 * BW;             // tile edge
-  constexpr int BSTAGE = 2 * BT * LROW;  // floats per stage (A rows, then B rows)
-  // the load swizzle below takes stage rows 8 j + lr of a wave's BW rows
-  static_assert((BW / 8) % 2 == 0, "wave row count must be a multiple of 16");
+  constexpr int BSTAGE = BT * LROW;      // floats per stage: BT rows of B x 32 k
+  constexpr int LPW = BT / 32;           // load instructions per wave per panel (8 rows each)
   const int n = p.n;
   int bi, bj;
   tile_of(blockIdx.x, T, p.sym, BIG_GROUP, bi, bj);
   const int i0 = bi * BT, j0 = bj * BT;
-  __shared__ float st0[BSTAGE];
-  __shared__ float st1[BSTAGE];
+  __shared__ float stg[STAGES][BSTAGE];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wm = (wave >> 1) * BW, wn = (wave & 1) * BW;
+  const int fr = lane & 15, fq = lane >> 4;  // fragment row, k group (8 values)
 
   f4 acc[BNB][BNB];
 #pragma unroll
@@ -587,40 +587,55 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   const int kt_per = n / TK;
   const int ktiles = kt_per * p.nprod;
 
-  // loads: wave w fills stage rows [BW w, BW w + BW) (waves 0, 1: A rows,
-  // 2, 3: B rows), eight rows per instruction; lane -> row lane / 8,
-  // physical chunk lane % 8
+  // B panels: buffer loads to LDS, the BT rows x 32 k of a panel shared by the
+  // four waves (BT / 4 rows each, eight per instruction; lane -> row lane / 8,
+  // physical chunk lane % 8 holding logical chunk swz(row, lane % 8)).  The
+  // lane's byte offset of each load row is computed once (n^2 FP32 values fit
+  // in 32 bits for n <= 32767) and the k panel is the scalar offset.
   const int lr = lane >> 3, lpc = lane & 7;
-  const bool ldA = wave < 2;
-  const int g0 = (ldA ? i0 : j0) + (wave & 1) * BW;
-  // Buffer loads to LDS: the lane's byte offset of each load row is computed
-  // once (n^2 FP32 values fit in 32 bits for n <= 32767) and the k panel is
-  // the scalar offset.  Stage row BW w + 8 j + lr has swizzle
-  // lpc ^ lr ^ (j & 1).
-  unsigned roff[BW / 8];
+  unsigned roff[LPW];
 #pragma unroll
-  for (int j = 0; j < BW / 8; ++j) {
-    int g = g0 + 8 * j + lr;
+  for (int j = 0; j < LPW; ++j) {
+    const int R = wave * (BT / 4) + 8 * j + lr;  // stage row
+    int g = j0 + R;
     g = g < n ? g : n - 1;
-    roff[j] = 4u * ((unsigned)g * (unsigned)n + 4u * (unsigned)(lpc ^ lr ^ (j & 1)));
+    roff[j] = 4u * ((unsigned)g * (unsigned)n + 4u * (unsigned)swz(R, lpc));
   }
   const int nbytes = (int)(4u * (unsigned)n * (unsigned)n);  // buffer range (n <= 32767)
-  auto issue = [&](int kt, float *stg) {
+  auto issueB = [&](int kt, float *st) {
     const int prod = kt / kt_per;
     const unsigned kb = 4u * (unsigned)((kt - prod * kt_per) * TK);
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<void *>(ldA ? p.A[prod] : p.B[prod]), (short)0, nbytes, BUF_DWORD3);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p.B[prod]), (short)0, nbytes, BUF_DWORD3);
 #pragma unroll
-    for (int j = 0; j < BW / 8; ++j)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&stg[(wave * BW + 8 * j) * LROW], 16, roff[j], kb,
-                                               0, 0);
+    for (int j = 0; j < LPW; ++j)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void_t *)&st[(wave * (BT / 4) + 8 * j) * LROW], 16,
+                                               roff[j], kb, 0, 0);
   };
-
-  const int fr = lane & 15, fq = lane >> 4;
-  // eight FP32 values of stage row r, k 8 fq .. 8 fq + 7
-  auto fetch = [&](const float *stg, int r, float (&x)[8]) {
-    const f4 lo = *(const f4 *)(stg + r * LROW + 4 * swz(r, 2 * fq));
-    const f4 hi = *(const f4 *)(stg + r * LROW + 4 * swz(r, 2 * fq + 1));
+  // A fragments straight from global memory into registers: row block r of
+  // this lane is row i0 + wm + 16 r + fr, k values 8 fq .. 8 fq + 7 of the panel
+  unsigned aoff[BNB];
+#pragma unroll
+  for (int r = 0; r < BNB; ++r) {
+    int g = i0 + wm + 16 * r + fr;
+    g = g < n ? g : n - 1;
+    aoff[r] = 4u * ((unsigned)g * (unsigned)n + 8u * (unsigned)fq);
+  }
+  auto loadA = [&](int kt, int r, float (&x)[8]) {
+    const int prod = kt / kt_per;
+    const char *base = (const char *)p.A[prod] + aoff[r] + 4 * (kt - prod * kt_per) * TK;
+    const f4 lo = *(const f4 *)base;
+    const f4 hi = *(const f4 *)(base + 16);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = lo[v];
+      x[4 + v] = hi[v];
+    }
+  };
+  // eight FP32 values of B stage row r, k 8 fq .. 8 fq + 7
+  auto fetch = [&](const float *st, int r, float (&x)[8]) {
+    const f4 lo = *(const f4 *)(st + r * LROW + 4 * swz(r, 2 * fq));
+    const f4 hi = *(const f4 *)(st + r * LROW + 4 * swz(r, 2 * fq + 1));
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       x[v] = lo[v];
@@ -642,52 +657,55 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   constexpr int RM = BNB * TERMS;                    // MFMAs per row block
   constexpr int SPLIT_VALU = (MODE == 1) ? 44 : 24;  // VALU instructions of one split8_pk
 
-  // Software pipeline over k panels with a full panel of lookahead: the LDS
-  // stages hold panels k (already in registers) and k + 1, and every fragment
-  // of panel k + 1 is read from LDS under the MFMAs of panel k, while panel
-  // k + 2 streams into the stage of panel k.  Registers: raw A of a panel
-  // (block r is refilled with the next panel's block r once split), split A
-  // of the row block being multiplied (a) and of the next one (an), split B
-  // of the current panel (b) and of the next (bn), raw B blocks of the next
-  // panel in flight (xb).  Per row block the next panel's reads go first,
-  // then the block's MFMAs interleaved with the splits of fragments read at
-  // least one row block earlier.  Per accumulator the MFMA sequence over k is
-  // fixed, so the result does not depend on this schedule.
+  // Software pipeline over k panels, a full panel ahead: panel p of B lives
+  // in stage p % STAGES, and while panel k is multiplied from registers, the
+  // next panel's A fragments come from global memory and its B fragments from
+  // LDS, and panel k + STAGES streams into the stage panel k has left.
+  // Registers: raw A of a panel (block r is refilled with the next panel's
+  // block r once split), split A of the row block being multiplied (a) and of
+  // the next one (an), split B of the current panel (b) and of the next (bn),
+  // raw B blocks of the next panel (xb).  Per row block the next panel's loads
+  // go first, then the block's MFMAs interleaved with the splits of fragments
+  // loaded at least one row block earlier.  Per accumulator the MFMA sequence
+  // over k is fixed, so the result does not depend on this schedule.
   float xa[BNB][8], xb[BNB][8];
   us8 b[BNB][3], bn[BNB][3], a[3];
-  issue(0, st0);
-  if (ktiles > 1) issue(1, st1);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+#pragma unroll
+  for (int s0 = 0; s0 < STAGES; ++s0)
+    if (s0 < ktiles) issueB(s0, stg[s0]);
+#pragma unroll
+  for (int r = 0; r < BNB; ++r) loadA(0, r, xa[r]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every prologue load has landed
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < BNB; ++c) {
     float x[8];
-    fetch(st0, BT + wn + 16 * c + fr, x);
+    fetch(stg[0], wn + 16 * c + fr, x);
     split8_pk<MODE>(x, b[c]);
   }
-#pragma unroll
-  for (int r = 0; r < BNB; ++r) fetch(st0, wm + 16 * r + fr, xa[r]);
   split8_pk<MODE>(xa[0], a);
-  // every read of stage 0 is done before any wave loads panel 2 into it (the
-  // compiler does not wait for buffer loads to LDS or count them at barriers)
+  // every read of stage 0 is done before any wave loads into it (the compiler
+  // does not wait for buffer loads to LDS or count them at barriers)
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
   __syncthreads();
   for (int kt = 0; kt < ktiles; ++kt) {
-    float *cur = (kt & 1) ? st1 : st0;  // panel kt, already in registers
-    float *nxt = (kt & 1) ? st0 : st1;  // panel kt + 1, landed
-    if (kt + 2 < ktiles) issue(kt + 2, cur);
+    float *nxt = stg[(kt + 1) % STAGES];  // panel kt + 1, landed
+    const bool steady = kt + STAGES < ktiles;
+    if (steady) issueB(kt + STAGES, stg[kt % STAGES]);
+    // the next panel's A (the last panel reloads itself: in bounds, unused)
+    const int ka = kt + 1 < ktiles ? kt + 1 : kt;
     __builtin_amdgcn_sched_barrier(0);
     static_for<BNB>([&](auto rc) {
       constexpr int r = decltype(rc)::value;
-      // the next panel's A block r and B block r + 1 (B blocks 0 and 1 in
-      // row block 0).  The last panel reads the other stage too (in bounds,
-      // values unused), so that no branch separates reads and uses.
-      constexpr int nreads = 2 + (r == 0 ? 2 : 0) + (r + 1 < BNB ? 2 : 0);
-      fetch(nxt, wm + 16 * r + fr, xa[r]);
-      if (r == 0) fetch(nxt, BT + wn + fr, xb[0]);
-      if (r + 1 < BNB) fetch(nxt, BT + wn + 16 * (r + 1) + fr, xb[r + 1 < BNB ? r + 1 : 0]);
+      // the next panel's A block r and B block r + 1 (B blocks 0 and 1 in row
+      // block 0); the last panel reads a stage not loaded again (in bounds,
+      // values unused), so that no branch separates the reads from their uses
+      constexpr int nreads = (r == 0 ? 2 : 0) + (r + 1 < BNB ? 2 : 0);
+      loadA(ka, r, xa[r]);
+      if (r == 0) fetch(nxt, wn + fr, xb[0]);
+      if (r + 1 < BNB) fetch(nxt, wn + 16 * (r + 1) + fr, xb[r + 1 < BNB ? r + 1 : 0]);
       // splits under this row block's MFMAs: the A block multiplied next (the
-      // next panel's block 0 in the last row block) and the B block(s) read
+      // next panel's block 0 in the last row block) and the B block(s) loaded
       // at least one row block earlier
       us8 an[3];
       split8_pk<MODE>(r + 1 < BNB ? xa[r + 1 < BNB ? r + 1 : 0] : xa[0], an);
@@ -697,7 +715,8 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
 #pragma unroll
       for (int c = 0; c < BNB; ++c) mma(r, c, a, b[c]);
       constexpr int per = (nsplit * SPLIT_VALU + RM - 1) / RM;
-      __builtin_amdgcn_sched_group_barrier(0x100, nreads, 0);  // DS read
+      __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);                    // VMEM read
+      if (nreads) __builtin_amdgcn_sched_group_barrier(0x100, nreads, 0);  // DS read
 #pragma unroll
       for (int q = 0; q < RM; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
@@ -711,9 +730,20 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
     for (int c = 0; c < BNB; ++c)
 #pragma unroll
       for (int q = 0; q < 3; ++q) b[c][q] = bn[c][q];
-    // panel kt + 2 has landed (this wave's loads) and every read of panel
-    // kt + 1 is done before the barrier hands the stages over
-    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+    // Panel kt + 2 must have landed before the next iteration reads it, and
+    // every read of panel kt + 1 must be done before its stage is reloaded.
+    // Loads complete in issue order: B(kt + 2) was issued at iteration
+    // kt + 2 - STAGES (earlier ones in the prologue, which waited for all),
+    // and after it came 2 BNB A loads per iteration and LPW B loads per later
+    // iteration.  Near the end, with fewer B loads after it, the wait keeps
+    // only this iteration's A loads in flight.
+    constexpr int NA = 2 * BNB + (STAGES - 2) * (LPW + 2 * BNB);
+    constexpr int NE = 2 * BNB;
+    static_assert(NA < 64, "vmcnt holds 6 bits");
+    if (steady)
+      __builtin_amdgcn_s_waitcnt((NA & 15) | ((NA >> 4) << 14) | 0x0070);  // vmcnt(NA) lgkmcnt(0)
+    else
+      __builtin_amdgcn_s_waitcnt((NE & 15) | ((NE >> 4) << 14) | 0x0070);  // vmcnt(NE) lgkmcnt(0)
     __syncthreads();
   }
 
@@ -747,10 +777,11 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   }
 }
 
+// 224-row tiles (BNB = 7) keep four B stages in LDS (115 KB), 160-row tiles three (61 KB)
 template <int MODE, int BNB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gemm_split_big(GemmArgs p,
                                                                                                    int T) {
-  gemm_split_big_body<MODE, BNB>(p, T);
+  gemm_split_big_body<MODE, BNB, BNB == 7 ? 4 : 3>(p, T);
 }
 
 // BF16x3, the response-chain mode of the mixed-precision step: two register

@@ -36,7 +36,7 @@ def ground(lib):
     h.set_geometry(torch.tensor(s.R, dtype=torch.float64, device=dev))
     n = s.n_orb
     X = torch.eye(n, dtype=torch.float64, device=dev) * (s.n_elec / n)
-    rep = h.scf(X, m=20, tol=1e-10, max_iter=100, history=400)
+    rep = h.scf(X, m=20, tol=1e-10, max_iter=100, history=10000)
     torch.cuda.synchronize()
     yield s, w, h, X, rep
     h.close()
