@@ -161,14 +161,15 @@ def run_ensemble(args, binding, torch, dev):
         hs.append(h)
         states.append(st)
         streams.append(strm)
-        snaps.append((st.R.clone(), st.V.clone(), st.A.clone(), st.X.clone(), st.Y.clone(), st.head, st.mu))
+        snaps.append((st.R.clone(), st.V.clone(), st.A.clone(), st.X.clone(), st.Y.clone(), st.head, st.mu,
+                      st.mu_prev))
     log(f"ensemble of {len(hs)} prepared ({time.perf_counter() - t:.1f} s)")
 
     def restore():
         for st, sn in zip(states, snaps):
             for dst, src in zip((st.R, st.V, st.A, st.X, st.Y), sn[:5]):
                 dst.copy_(src)
-            st.head, st.mu = sn[5], sn[6]
+            st.head, st.mu, st.mu_prev = sn[5], sn[6], sn[7]
         torch.cuda.synchronize()
 
     def timed(fn):
@@ -227,18 +228,18 @@ class Snapshot:
     def __init__(self, state):
         self.R, self.V, self.A = state.R.clone(), state.V.clone(), state.A.clone()
         self.X, self.Y = state.X.clone(), state.Y.clone()
-        self.head, self.mu = state.head, state.mu
+        self.head, self.mu, self.mu_prev = state.head, state.mu, state.mu_prev
         self.slot = (state.head + 6) % 7
 
     def new_state(self, binding):
         return binding.MDState(R=self.R.clone(), V=self.V.clone(), A=self.A.clone(), X=self.X.clone(),
-                               Y=self.Y.clone(), head=self.head, mu=self.mu)
+                               Y=self.Y.clone(), head=self.head, mu=self.mu, mu_prev=self.mu_prev)
 
     def restore_step(self, state):
         for dst, src in zip((state.R, state.V, state.A, state.X[self.slot], state.Y),
                             (self.R, self.V, self.A, self.X[self.slot], self.Y)):
             dst.copy_(src)
-        state.head, state.mu = self.head, self.mu
+        state.head, state.mu, state.mu_prev = self.head, self.mu, self.mu_prev
 
 
 def timed_reset_leg(torch, h, state, snap, steps, warmup):

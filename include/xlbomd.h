@@ -42,7 +42,8 @@ typedef enum {
   XLBOMD_E_NOCONV = -3,    /* chemical potential or SCF not converged              */
   XLBOMD_E_NONFINITE = -4, /* a NaN or Inf was detected in a result                */
   XLBOMD_E_STATE = -5,     /* call order violated (e.g. response before fermi_dm)  */
-  XLBOMD_E_NOMEM = -6      /* device allocation failed                             */
+  XLBOMD_E_NOMEM = -6,     /* device allocation failed                             */
+  XLBOMD_E_UNSTABLE = -7   /* an MD guard tripped: ||D0 - X|| or T_ion above limit */
 } xlbomd_status;
 
 /* Arithmetic of the recursive Fermi-operator and response GEMM chains.  The
@@ -105,12 +106,21 @@ typedef struct {
   double c[7];        /* eq. 29/35 damping c_k, k = 0..6                                 */
   double kernel_c;    /* m = 0: the original XL-BOMD kernel K = -c I (scaled identity,   */
                       /* Results, low-gap fullerene test: c = 1, or 0.9 tuned), c > 0    */
+  /* Per-step guards of xlbomd_step / xlbomd_step_langevin (0 = off): a step
+   * whose ||D0[X] - X||_F exceeds w0_limit, or whose ionic temperature exceeds
+   * T_ion_limit (K), ends the call with XLBOMD_E_UNSTABLE after that step
+   * (the instability the Results describe: the residual and the temperature
+   * run away).  A T_ion guard reads the velocities back every step. */
+  double w0_limit;
+  double T_ion_limit;
 } xlbomd_params;
 
 /* MD state of xlbomd_step, all DEVICE pointers owned by the caller.  The X
  * history is a ring of 7 matrices: X(t - k dt) lives in slot (head + k) % 7.
- * Every call taking a state returns XLBOMD_E_ARG, touching nothing, if a
- * pointer is null or head is outside [0, 7). */
+ * The state is all a trajectory carries from step to step: a copy of it (the
+ * buffers and the host fields) resumes the trajectory bit for bit, on the same
+ * or on a new handle.  Every call taking a state returns XLBOMD_E_ARG,
+ * touching nothing, if a pointer is null or head is outside [0, 7). */
 typedef struct {
   double *R;      /* n_atoms x 3, Angstrom                                  */
   double *V;      /* n_atoms x 3, Angstrom/fs                               */
@@ -119,6 +129,8 @@ typedef struct {
   double *Y;      /* n x n, kernel result Y(t) of eq. 34 at the current t   */
   int head;       /* host: ring slot of X(t)                                */
   double mu;      /* host: chemical potential of the last evaluation, eV    */
+  double mu_prev; /* host: the one before (NaN: none); the warm start of the */
+                  /* next evaluation extrapolates linearly from the two     */
 } xlbomd_md_state;
 
 /* Per-step report (host). */
@@ -132,7 +144,9 @@ typedef struct {
   double W0;      /* ||D0[X] - X||_F, spin-summed                             */
   double relres;  /* relative residual of the rank-m kernel                   */
   int rank;       /* Krylov rank used                                          */
-  int status;     /* XLBOMD_OK or the guard that tripped                       */
+  int status;     /* XLBOMD_OK, or the status that ended the call at this step */
+                  /* (XLBOMD_E_UNSTABLE: a guard; XLBOMD_E_NONFINITE: a NaN or */
+                  /* Inf in F, the residual or the energies)                  */
   int levels;     /* recursion levels L of the Fermi chain                      */
   int mu_passes;  /* exact chemical-potential shift passes (0: series shift)   */
 } xlbomd_report;
@@ -233,7 +247,10 @@ xlbomd_status xlbomd_integrate(xlbomd_handle h, xlbomd_md_state *st);
 
 /* One or more KSA-XL-BOMD NVE steps (eqs. 27-30, 35, 37): for each step
  * integrate, evaluate F, P0 and the kernel at the new state, forces, and the
- * closing half kick.  rep: host array of n_steps reports (nullable). */
+ * closing half kick.  rep: host array of n_steps reports (nullable).  A step
+ * that fails (a non-finite F or residual, a guard of xlbomd_params) ends the
+ * call with that status, written also into that step's report; the state is
+ * then that of the failing step, and later reports are untouched. */
 xlbomd_status xlbomd_step(xlbomd_handle h, xlbomd_md_state *st, int n_steps,
                           xlbomd_report *rep);
 
@@ -265,7 +282,8 @@ xlbomd_status xlbomd_ensemble_step(xlbomd_handle *h, xlbomd_md_state *st, int co
                                    xlbomd_report *rep);
 
 /* Initial state for xlbomd_step: evaluates P0, Y and the accelerations at
- * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5). */
+ * (st->R, X(t0)) with X(t0 - k dt) = X(t0) for all k (Methods, section 5);
+ * st->mu_prev is reset to NaN. */
 xlbomd_status xlbomd_md_init(xlbomd_handle h, xlbomd_md_state *st);
 
 /* Settings of xlbomd_scf.  Linear mixing X <- X + mix (P0[X] - X) runs first,
@@ -301,9 +319,11 @@ xlbomd_status xlbomd_scf(xlbomd_handle h, double *X, const xlbomd_scf_params *p,
                          int history_len, xlbomd_scf_report *rep);
 
 /* Diagnostic: C = A B (+ optional symmetric-output mode) with the response-chain
- * GEMM of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric).  In
- * split modes the operands are rounded to FP32 storage first, exactly as the
- * chains store their matrices.  For testing and timing the MFMA kernels. */
+ * GEMM of the handle's precision, on DEVICE n x n FP64 matrices (A symmetric, B
+ * any; sym_out only where A B is symmetric).  In split modes the operands are
+ * rounded to FP32 storage first, exactly as the chains store their matrices
+ * (B transposed on the way: the split kernels take their second operand by
+ * rows).  For testing and timing the MFMA kernels. */
 xlbomd_status xlbomd_matmul(xlbomd_handle h, const double *A, const double *B, double *Cout,
                             int sym_out, int reps);
 

@@ -21,7 +21,7 @@ PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3,
         "dm64_bf16x3": 4, "dm64_bf16x6": 5, "dm64_fp16x3": 6}
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_HIP", -3: "E_NOCONV", -4: "E_NONFINITE",
-          -5: "E_STATE", -6: "E_NOMEM"}
+          -5: "E_STATE", -6: "E_NOMEM", -7: "E_UNSTABLE"}
 
 # symbols declared in include/xlbomd.h
 SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb",
@@ -50,12 +50,13 @@ class System(C.Structure):
 class Params(C.Structure):
     _fields_ = [("prec", C.c_int), ("T_e", C.c_double), ("m", C.c_int), ("krylov_tol", C.c_double),
                 ("dt", C.c_double), ("kappa", C.c_double), ("alpha", C.c_double),
-                ("c", C.c_double * 7), ("kernel_c", C.c_double)]
+                ("c", C.c_double * 7), ("kernel_c", C.c_double), ("w0_limit", C.c_double),
+                ("T_ion_limit", C.c_double)]
 
 
 class MDStateC(C.Structure):
     _fields_ = [("R", C.c_void_p), ("V", C.c_void_p), ("A", C.c_void_p), ("X", C.c_void_p),
-                ("Y", C.c_void_p), ("head", C.c_int), ("mu", C.c_double)]
+                ("Y", C.c_void_p), ("head", C.c_int), ("mu", C.c_double), ("mu_prev", C.c_double)]
 
 
 class SCFParams(C.Structure):
@@ -119,7 +120,12 @@ def load():
 
 
 class XLBOMDError(RuntimeError):
-    pass
+    """A library call failed; .status holds its xlbomd_status (None for
+    argument checks of the binding itself)."""
+
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 def _ptr(t, n_elem=None, dtype=None):
@@ -136,18 +142,22 @@ def _ptr(t, n_elem=None, dtype=None):
 
 
 class MDState:
-    """Device state of xlbomd_step (R, V, A: N x 3; X: 7 x n x n ring; Y: n x n)."""
+    """Device state of xlbomd_step (R, V, A: N x 3; X: 7 x n x n ring; Y: n x n)
+    and its host fields (ring head, the last two chemical potentials)."""
 
-    def __init__(self, R, V, A, X, Y, head=0, mu=float("nan")):
+    def __init__(self, R, V, A, X, Y, head=0, mu=float("nan"), mu_prev=float("nan")):
         self.R, self.V, self.A, self.X, self.Y = R, V, A, X, Y
-        self.head, self.mu = head, mu
+        self.head, self.mu, self.mu_prev = head, mu, mu_prev
 
     def _c(self, h):
         import torch
         N, n = h.n_atoms, h.n
         f = torch.float64
         return MDStateC(_ptr(self.R, 3 * N, f), _ptr(self.V, 3 * N, f), _ptr(self.A, 3 * N, f),
-                        _ptr(self.X, 7 * n * n, f), _ptr(self.Y, n * n, f), self.head, self.mu)
+                        _ptr(self.X, 7 * n * n, f), _ptr(self.Y, n * n, f), self.head, self.mu, self.mu_prev)
+
+    def _back(self, sc):
+        self.head, self.mu, self.mu_prev = sc.head, sc.mu, sc.mu_prev
 
     def x_current(self):
         return self.X[self.head]
@@ -158,7 +168,8 @@ class Handle:
 
     def __init__(self, n_atoms, n_elec, onecenter, noise55, model, *, prec="fp64", T_e=3000.0,
                  m=4, dt=0.5, kappa=1.84, alpha=0.0055,
-                 c=(-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0), krylov_tol=0.0, kernel_c=1.0, stream=None):
+                 c=(-14.0, 36.0, -27.0, -2.0, 12.0, -6.0, 1.0), krylov_tol=0.0, kernel_c=1.0, w0_limit=0.0,
+                 T_ion_limit=0.0, stream=None):
         self.lib = load()
         self.n_atoms = int(n_atoms)
         self.n = 4 * self.n_atoms
@@ -179,7 +190,7 @@ class Handle:
                       self._noise.ctypes.data_as(C.POINTER(C.c_float)), mdl)
         prm = Params(PREC[prec] if isinstance(prec, str) else int(prec), float(T_e), int(m),
                      float(krylov_tol), float(dt), float(kappa), float(alpha), (C.c_double * 7)(*c),
-                     float(kernel_c))
+                     float(kernel_c), float(w0_limit), float(T_ion_limit))
         self.prec = prec
         self.m = int(m)
         h = C.c_void_p()
@@ -202,7 +213,7 @@ class Handle:
     def _check(self, st, what):
         if st != 0:
             msg = self.lib.xlbomd_last_error(self.h).decode()
-            raise XLBOMDError(f"{what}: {STATUS.get(st, st)}: {msg}")
+            raise XLBOMDError(f"{what}: {STATUS.get(st, st)}: {msg}", st)
 
     def _mat(self, t):
         import torch
@@ -252,21 +263,26 @@ class Handle:
     def integrate(self, state: MDState):
         sc = state._c(self)
         self._check(self.lib.xlbomd_integrate(self.h, C.byref(sc)), "integrate")
-        state.head, state.mu = sc.head, sc.mu
+        state._back(sc)
 
     def md_init(self, state: MDState):
         sc = state._c(self)
         self._check(self.lib.xlbomd_md_init(self.h, C.byref(sc)), "md_init")
-        state.head, state.mu = sc.head, sc.mu
+        state._back(sc)
 
-    def step(self, state: MDState, n_steps=1, report=True):
+    def step(self, state: MDState, n_steps=1, report=True, check=True):
+        """n_steps NVE steps; returns the per-step reports (report=True).  With
+        check=False a failing call returns (status, reports) instead of raising:
+        the failing step's report carries the status."""
         sc = state._c(self)
-        reps = (Report * max(n_steps, 1))() if report else None
-        self._check(self.lib.xlbomd_step(self.h, C.byref(sc), int(n_steps), reps), "step")
-        state.head, state.mu = sc.head, sc.mu
-        if not report:
-            return None
-        return [{k: getattr(r, k) for k, _ in Report._fields_} for r in reps[:n_steps]]
+        reps = (Report * max(n_steps, 1))() if report or not check else None
+        st = self.lib.xlbomd_step(self.h, C.byref(sc), int(n_steps), reps)
+        state._back(sc)
+        out = None if reps is None else [{k: getattr(r, k) for k, _ in Report._fields_} for r in reps[:n_steps]]
+        if not check:
+            return st, out
+        self._check(st, "step")
+        return out if report else None
 
     def step_langevin(self, state: MDState, xi, gamma, T_ion, report=True):
         """len(xi) / (3 n_atoms) Langevin steps; xi: device float64 standard normals."""
@@ -279,7 +295,7 @@ class Handle:
         reps = (Report * max(n_steps, 1))() if report else None
         self._check(self.lib.xlbomd_step_langevin(self.h, C.byref(sc), int(n_steps), float(gamma), float(T_ion),
                                                   C.c_void_p(xi.data_ptr()), reps), "step_langevin")
-        state.head, state.mu = sc.head, sc.mu
+        state._back(sc)
         if not report:
             return None
         return [{k: getattr(r, k) for k, _ in Report._fields_} for r in reps[:n_steps]]
@@ -336,7 +352,7 @@ def ensemble_step(handles, states, n_steps=1, report=True):
     reps = (Report * max(count * n_steps, 1))() if report else None
     st = lib.xlbomd_ensemble_step(hs, scs, int(count), int(n_steps), reps)
     for k, (h, s) in enumerate(zip(handles, states)):
-        s.head, s.mu = scs[k].head, scs[k].mu
+        s._back(scs[k])
     if st != 0:
         msgs = "; ".join(f"member {k}: {h.lib.xlbomd_last_error(h.h).decode()}" for k, h in enumerate(handles)
                          if h.lib.xlbomd_last_error(h.h))

@@ -242,7 +242,6 @@ struct xlbomd_ctx {
   int mu_passes = 0;
   bool chain_valid = false;
   double mu_chain = 0.0;
-  double mu_prev = NAN;   // chemical potential one MD step back (warm-start extrapolation)
   // Trace tolerance of the chemical-potential passes.  With FP32 storage of the
   // Fermi chain, Tr D and Tr D(I - D) carry the chain's rounding; in a strongly
   // gapped state Tr D(I - D) = sum f(1 - f) falls to that level and a Newton
@@ -438,7 +437,7 @@ inline void split_prec(int prec, int &dm, int &rs) {
 // depth L grows with log2 of the bound, so each factor of two saved is one
 // recursion level less in the density matrix and in every response.  The
 // Lanczos start vector (row 0 of lq) is written once at create.
-xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
+xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2], double *gersh = nullptr) {
   const int n = c->n;
   gershgorin(n, F, c->dscal + S_LOHI, c->red, c->s);
   const int K = std::min(LANCZOS_K, n);
@@ -447,6 +446,10 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2]) {
   xlbomd_status st = get_scalars2(c, S_LOHI, 2, g, S_LANC, 2 * K, ab);
   if (st) return st;
   if (!bounds_from_lanczos(g, ab, K, lohi)) return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
+  if (gersh) {
+    gersh[0] = g[0];
+    gersh[1] = g[1];
+  }
   return XLBOMD_OK;
 }
 
@@ -898,12 +901,13 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1, const double
   return XLBOMD_OK;
 }
 
-xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
+// One pass of the density matrix at given spectral bounds: chain, chemical-
+// potential shift (bisection with new chains when the warm start is far off),
+// first-order trace correction into P.  fx: S_FIX, mu_shift's own first-order
+// step, Tr P.
+xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], double &mu, double *P, double fx[3]) {
   const int n = c->n;
-  double lohi[2];
-  xlbomd_status st = spectral_bounds(c, F, lohi);
-  if (st) return st;
-  double mu = *mu_io;
+  xlbomd_status st;
   bool cold = !std::isfinite(mu);
   bool converged = false;
   for (int attempt = 0; attempt < 4 && !converged; ++attempt) {
@@ -951,8 +955,29 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
                          (const double *)c->M, c->dscal + S_FIX, P);
   }
   trace(n, P, c->dscal + S_TRP, 0, c->red, c->s);
-  double fx[3];
-  if ((st = get_scalars(c, S_FIX, 3, fx))) return st;  // S_FIX, first-order step of mu_shift, S_TRP
+  return get_scalars(c, S_FIX, 3, fx);  // S_FIX, first-order step of mu_shift, S_TRP
+}
+
+// Largest first-order trace correction (in units of beta dmu) that a sound
+// chain leaves: after the shift passes it is O((1 - c)^6) or O(dmu^2), below
+// ~1e-6.  A larger one means the chain itself is off, e.g. an eigenvalue of F
+// outside the Lanczos bounds that the chain's start polynomial and a-priori
+// Newton-Schulz counts were set for.
+constexpr double FIX_MAX = 1e-3;
+
+xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
+  double lohi[2], gersh[2];
+  xlbomd_status st = spectral_bounds(c, F, lohi, gersh);
+  if (st) return st;
+  double mu = *mu_io, fx[3];
+  if ((st = fermi_pass(c, F, lohi, mu, P, fx))) return st;
+  if (!c->is32 && !(std::fabs(fx[0]) <= FIX_MAX)) {
+    // once more on the rigorous Gershgorin interval, from the same warm start
+    mu = *mu_io;
+    if ((st = fermi_pass(c, F, gersh, mu, P, fx))) return st;
+    if (!(std::fabs(fx[0]) <= FIX_MAX))
+      return fail(c, XLBOMD_E_NOCONV, "density matrix inconsistent (first-order trace step %.3e)", fx[0]);
+  }
   if (c->fix_pending) {
     mu += fx[1] / c->beta;
     c->shift_c *= std::exp(-fx[1]);
@@ -1200,7 +1225,8 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   const double n = 4.0 * sys->n_atoms;
   if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
   if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6 ||
-      !(prm->kernel_c > 0.0) || !std::isfinite(prm->kernel_c))
+      !(prm->kernel_c > 0.0) || !std::isfinite(prm->kernel_c) || !(prm->w0_limit >= 0.0) ||
+      !(prm->T_ion_limit >= 0.0))
     return XLBOMD_E_ARG;
   xlbomd_ctx *c = new xlbomd_ctx();
   c->N = sys->n_atoms;
@@ -1404,9 +1430,9 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
   // P0 lives in f64[4] only until the Krylov call, which reuses it: keep a copy in Vk? use Wk slots
   // warm start: linear extrapolation of mu from the last two steps
   double mu = st->mu;
-  if (std::isfinite(st->mu) && std::isfinite(c->mu_prev)) mu = 2.0 * st->mu - c->mu_prev;
+  if (std::isfinite(st->mu) && std::isfinite(st->mu_prev)) mu = 2.0 * st->mu - st->mu_prev;
   if ((s = fermi(c, F, &mu, P0, true))) return s;
-  c->mu_prev = st->mu;
+  st->mu_prev = st->mu;
   st->mu = mu;
   if (S && (s = entropy(c, F, mu, S))) return s;
   // forces first (Krylov reuses f64[0..4])
@@ -1420,7 +1446,7 @@ static xlbomd_status evaluate_state(xlbomd_ctx *c, xlbomd_md_state *st, double e
 
 xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
   if (!c || !state_ok(st)) return XLBOMD_E_ARG;
-  c->mu_prev = NAN;
+  st->mu_prev = NAN;
   // replicate X(t0) into every history slot
   const double *X0 = st->X + (size_t)st->head * c->n2;
   for (int k = 1; k < 7; ++k)
@@ -1436,8 +1462,16 @@ xlbomd_status xlbomd_md_init(xlbomd_handle c, xlbomd_md_state *st) {
 static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, xlbomd_report *rep,
                               double c1, double c2, const double *xi) {
   if (!state_ok(st)) return XLBOMD_E_ARG;
+  const bool t_guard = c->prm.T_ion_limit > 0.0;
+  const int dof = std::max(3 * c->N - 3, 1);
+  std::vector<double> V;
   for (int k = 0; k < n_steps; ++k) {
     xlbomd_status s;
+    // a failing step leaves its status in its report
+    auto stop = [&](xlbomd_status why) {
+      if (rep) rep[k].status = why;
+      return why;
+    };
     if (xi) {
       const double *Xk[7];
       for (int j = 0; j < 7; ++j) Xk[j] = st->X + (size_t)((st->head + j) % 7) * c->n2;
@@ -1447,37 +1481,51 @@ static xlbomd_status md_steps(xlbomd_ctx *c, xlbomd_md_state *st, int n_steps, x
       baoab_pre(3 * c->N, st->R, st->V, st->A, c->prm.dt, c1, c2, xi + (size_t)3 * c->N * k, c->s);
       HIPCHK(c, hipGetLastError());
     } else if ((s = xlbomd_integrate(c, st))) {
-      return s;
+      return stop(s);
     }
     double e[3];
     int rank = 0;
     double rel = 0, w0 = 0, S = 0.0;
     // energies (a host round trip) only for a report
-    if ((s = evaluate_state(c, st, rep ? e : nullptr, &rank, &rel, &w0, rep ? &S : nullptr))) return s;
+    if ((s = evaluate_state(c, st, rep ? e : nullptr, &rank, &rel, &w0, rep ? &S : nullptr))) return stop(s);
     kick_drift(3 * c->N, st->R, st->V, st->A, c->prm.dt, 0, c->s);
-    if (rep) {
+    double ke = NAN;
+    if (rep || t_guard) {
       // kinetic energy from V (host copy of a few KB)
-      std::vector<double> V(3 * c->N);
+      V.resize(3 * c->N);
       HIPCHK(c, hipMemcpyAsync(V.data(), st->V, sizeof(double) * 3 * c->N, hipMemcpyDeviceToHost, c->s));
       HIPCHK(c, hipStreamSynchronize(c->s));
-      double ke = 0.0;
+      ke = 0.0;
       for (double v : V) ke += v * v;
       ke *= 0.5 * c->model.mass / ACC;
+    }
+    const double T_ion = 2.0 * ke / (dof * KB);
+    xlbomd_status status = XLBOMD_OK;
+    if (!std::isfinite(w0) || (rep && !(std::isfinite(e[0]) && std::isfinite(e[1]) && std::isfinite(e[2]) &&
+                                        std::isfinite(ke))))
+      status = fail(c, XLBOMD_E_NONFINITE, "non-finite residual or energies at step %d", k);
+    else if (c->prm.w0_limit > 0.0 && w0 > c->prm.w0_limit)
+      status = fail(c, XLBOMD_E_UNSTABLE, "||D0 - X|| = %.3e above its limit %.3e at step %d", w0,
+                    c->prm.w0_limit, k);
+    else if (t_guard && !(T_ion <= c->prm.T_ion_limit))
+      status = fail(c, XLBOMD_E_UNSTABLE, "T_ion = %.4g K above its limit %.4g K at step %d", T_ion,
+                    c->prm.T_ion_limit, k);
+    if (rep) {
       xlbomd_report &r = rep[k];
       r.KE = ke;
       r.TS = 2.0 * S / c->beta;  // -2 T_e S with S in units of k_B: 2 k_B T_e S = 2 S / beta
       r.U = e[0] + e[1] + e[2] - r.TS;
       r.E_tot = r.KE + r.U;
-      const int dof = std::max(3 * c->N - 3, 1);
-      r.T_ion = 2.0 * ke / (dof * KB);
+      r.T_ion = T_ion;
       r.mu = st->mu;
       r.W0 = w0;
       r.relres = rel;
       r.rank = rank;
-      r.status = XLBOMD_OK;
+      r.status = status;
       r.levels = c->L;
       r.mu_passes = c->mu_passes;
     }
+    if (status != XLBOMD_OK) return status;
   }
   HIPCHK(c, hipStreamSynchronize(c->s));
   return XLBOMD_OK;
@@ -1608,7 +1656,9 @@ xlbomd_status xlbomd_matmul(xlbomd_handle c, const double *A, const double *B, d
   void *o = Cout;
   if (c->rs32) {
     convert(n2, A, 0, c->w[0], 1, c->s);
-    convert(n2, B, 0, c->w[1], 1, c->s);
+    // the split kernels take their second operand by rows (op(B) = B^T), so
+    // they get B^T: A (B^T)^T = A B for any B
+    convert_t(c->n, B, (float *)c->w[1], c->s);
     a = c->w[0];
     b = c->w[1];
     o = c->w[2];

@@ -365,25 +365,33 @@ __global__ __launch_bounds__(256) void k_gersh_rows(int n, const double *F, doub
 }
 
 __global__ __launch_bounds__(256) void k_gersh_final(int n, const double *lohi, double *res) {
+  // fmin / fmax drop NaN operands, so a NaN row is counted apart and turns
+  // the result into NaN (the caller reports a non-finite matrix)
   __shared__ double smin[256], smax[256];
+  __shared__ int snan[256];
   double lo = INFINITY, hi = -INFINITY;
+  int bad = 0;
   for (int i = threadIdx.x; i < n; i += 256) {
-    lo = fmin(lo, lohi[2 * i]);
-    hi = fmax(hi, lohi[2 * i + 1]);
+    const double a = lohi[2 * i], b = lohi[2 * i + 1];
+    bad |= !(a == a) || !(b == b);
+    lo = fmin(lo, a);
+    hi = fmax(hi, b);
   }
   smin[threadIdx.x] = lo;
   smax[threadIdx.x] = hi;
+  snan[threadIdx.x] = bad;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
       smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      snan[threadIdx.x] |= snan[threadIdx.x + o];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    res[0] = smin[0];
-    res[1] = smax[0];
+    res[0] = snan[0] ? NAN : smin[0];
+    res[1] = snan[0] ? NAN : smax[0];
   }
 }
 

@@ -11,7 +11,9 @@ namespace xl {
 // out = alpha * sum_p op(A_p) op(B_p) + beta1 * C1 + beta2 * C2 + gamma * I
 // op(A) reads A as its transpose (A^T tiles are contiguous rows of A), which is
 // A itself for the symmetric operands of the Fermi-operator and response chains.
-// op(B) is B (btrans = 0) or B^T (btrans = 1).  sym = 1 computes only tiles with
+// op(B) is B (btrans = 0) or B^T (btrans = 1) in the FP64 kernels.  The split
+// kernels read B by rows whatever btrans says, i.e. op(B) = B^T: a caller
+// passes a symmetric B there (op(B) = B), or B^T to get A B.  sym = 1 computes only tiles with
 // tile_row <= tile_col and writes each one also to the mirrored position; it is
 // valid when the result is symmetric (products of commuting symmetric matrices,
 // A B + B A, and the final product of a response level).  out must not alias an

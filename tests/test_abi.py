@@ -53,7 +53,8 @@ def test_library_loads_without_gpu(built):
 
 # binding struct -> C struct name
 _STRUCTS = {"Model": "xlbomd_model", "System": "xlbomd_system", "Params": "xlbomd_params",
-            "MDStateC": "xlbomd_md_state", "Report": "xlbomd_report"}
+            "MDStateC": "xlbomd_md_state", "Report": "xlbomd_report", "SCFParams": "xlbomd_scf_params",
+            "SCFReport": "xlbomd_scf_report"}
 
 
 def test_binding_structs_match_header_layout(tmp_path):
@@ -95,17 +96,19 @@ def test_create_rejects_bad_arguments_before_any_device_call(built):
     oc = (C.c_double * 5)()
     nz = (C.c_float * 55)()
 
-    def create(n_atoms=2, n_elec=8.0, T_e=3000.0, m=4):
+    def create(n_atoms=2, n_elec=8.0, T_e=3000.0, m=4, w0_limit=0.0, T_ion_limit=0.0):
         sysc = binding.System(n_atoms=n_atoms, n_elec=n_elec,
                               onecenter=C.cast(oc, C.POINTER(C.c_double)),
                               noise55=C.cast(nz, C.POINTER(C.c_float)))
-        prm = binding.Params(prec=0, T_e=T_e, m=m, dt=0.5, kappa=1.84, alpha=0.0055, kernel_c=1.0)
+        prm = binding.Params(prec=0, T_e=T_e, m=m, dt=0.5, kappa=1.84, alpha=0.0055, kernel_c=1.0,
+                             w0_limit=w0_limit, T_ion_limit=T_ion_limit)
         h = C.c_void_p(1234)
         st = lib.xlbomd_create(C.byref(sysc), C.byref(prm), None, C.byref(h))
         return st, h.value
 
     for kw in (dict(n_atoms=0), dict(n_atoms=-3), dict(n_atoms=8192), dict(n_elec=0.0),
-               dict(n_elec=16.0), dict(n_elec=float("nan")), dict(T_e=0.0), dict(m=-1), dict(m=33)):
+               dict(n_elec=16.0), dict(n_elec=float("nan")), dict(T_e=0.0), dict(m=-1), dict(m=33),
+               dict(w0_limit=-1.0), dict(T_ion_limit=float("nan"))):
         st, h = create(**kw)
         assert st == -1, kw
         assert h is None, kw

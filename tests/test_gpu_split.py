@@ -60,7 +60,9 @@ def test_split_matmul(binding, mode, n_atoms, sym):
     rng = np.random.default_rng(n_atoms + 7)
     A = rng.uniform(-0.5, 0.5, (n, n))
     A = 0.5 * (A + A.T)
-    B = A @ A / n + np.eye(n) if sym else 0.5 * (lambda M: M + M.T)(rng.uniform(-0.5, 0.5, (n, n)))
+    # full outputs take a non-symmetric B (the split kernels read B by rows; the
+    # call passes B transposed so that the product is A B)
+    B = A @ A / n + np.eye(n) if sym else rng.uniform(-0.5, 0.5, (n, n))
     dev = torch.device("cuda:0")
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
     h.matmul(torch.tensor(A, device=dev), torch.tensor(B, device=dev), C, sym_out=bool(sym))
@@ -89,7 +91,9 @@ def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
     rng = np.random.default_rng(n_atoms + 11)
     A = rng.uniform(-0.5, 0.5, (n, n))
     A = 0.5 * (A + A.T)
-    B = A @ A / n + np.eye(n) if sym else 0.5 * (lambda M: M + M.T)(rng.uniform(-0.5, 0.5, (n, n)))
+    # full outputs take a non-symmetric B (the split kernels read B by rows; the
+    # call passes B transposed so that the product is A B)
+    B = A @ A / n + np.eye(n) if sym else rng.uniform(-0.5, 0.5, (n, n))
     dev = torch.device("cuda:0")
     C = torch.empty((n, n), dtype=torch.float64, device=dev)
     h.matmul(torch.tensor(A, device=dev), torch.tensor(B, device=dev), C, sym_out=bool(sym))
