@@ -219,7 +219,7 @@ struct xlbomd_ctx {
   // device buffers
   double *R = nullptr, *onecenter = nullptr, *j55 = nullptr;
   float *noise_t = nullptr;
-  double *pk = nullptr, *part = nullptr, *pk3 = nullptr, *fpart = nullptr, *epart = nullptr;
+  double *part = nullptr, *pk3 = nullptr, *fpart = nullptr, *epart = nullptr;
   double *dscal = nullptr, *red = nullptr, *frc = nullptr;
   double *lq = nullptr, *lw = nullptr;  // Lanczos vectors ((K+1) x n) and product
   const double **dptr = nullptr;  // device pointer arrays (for lincomb / orth)
@@ -368,7 +368,7 @@ double pair_pass_bytes(xlbomd_ctx *c) {
 
 void fock_t(xlbomd_ctx *c, const double *P, double *F, int include_h) {
   const int e = prof_begin(c);
-  fock(pairsys(c), P, F, include_h, c->pk, c->part, c->s);
+  fock(pairsys(c), P, F, include_h, c->part, c->s);
   prof_end(c, e, PC_FOCK, pair_pass_bytes(c));
 }
 
@@ -445,7 +445,7 @@ xlbomd_status spectral_bounds(xlbomd_ctx *c, const double *F, double lohi[2], do
   double g[2], ab[2 * LANCZOS_K];
   xlbomd_status st = get_scalars2(c, S_LOHI, 2, g, S_LANC, 2 * K, ab);
   if (st) return st;
-  if (!bounds_from_lanczos(g, ab, K, lohi)) return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
+  if (!bounds_from_lanczos(g, ab, K, n, lohi)) return fail(c, XLBOMD_E_NONFINITE, "non-finite Fock matrix");
   if (gersh) {
     gersh[0] = g[0];
     gersh[1] = g[1];
@@ -904,8 +904,9 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1, const double
 // One pass of the density matrix at given spectral bounds: chain, chemical-
 // potential shift (bisection with new chains when the warm start is far off),
 // first-order trace correction into P.  fx: S_FIX, mu_shift's own first-order
-// step, Tr P.
-xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], double &mu, double *P, double fx[3]) {
+// step, Tr P; trd: Tr D before the first-order correction.
+xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], double &mu, double *P, double fx[3],
+                         double trdm[2]) {
   const int n = c->n;
   xlbomd_status st;
   bool cold = !std::isfinite(mu);
@@ -955,28 +956,37 @@ xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], d
                          (const double *)c->M, c->dscal + S_FIX, P);
   }
   trace(n, P, c->dscal + S_TRP, 0, c->red, c->s);
-  return get_scalars(c, S_FIX, 3, fx);  // S_FIX, first-order step of mu_shift, S_TRP
+  // Tr M, Tr D; S_FIX, first-order step of mu_shift, S_TRP
+  HIPCHK(c, hipMemcpyAsync(trdm, c->dscal + S_TRM, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  return get_scalars2(c, S_TRD, 1, trdm + 1, S_FIX, 3, fx);
 }
 
-// Largest first-order trace correction (in units of beta dmu) that a sound
-// chain leaves: after the shift passes it is O((1 - c)^6) or O(dmu^2), below
-// ~1e-6.  A larger one means the chain itself is off, e.g. an eigenvalue of F
-// outside the Lanczos bounds that the chain's start polynomial and a-priori
+// A sound chain leaves (a) an electron-count defect |N_occ - Tr D| for the
+// first-order trace correction of O((1 - c)^6) or O(dmu^2) times
+// Tr D(I - D), far below DEFECT_MAX N_occ, and (b) every eigenvalue of D in
+// [0, 1], so Tr D(I - D) >= 0 up to rounding (of the storage: trace_tol with
+// FP32).  A chain that fails either is off, e.g. for an eigenvalue of F
+// outside the spectral bounds that the chain's start polynomial and a-priori
 // Newton-Schulz counts were set for.
-constexpr double FIX_MAX = 1e-3;
+constexpr double DEFECT_MAX = 1e-6;
+bool chain_sound(const xlbomd_ctx *c, const double tm[2]) {
+  return std::fabs(c->n_occ - tm[1]) <= DEFECT_MAX * c->n_occ + c->trace_tol &&
+         tm[0] >= -(1e-9 * c->n_occ + 4.0 * c->trace_tol);
+}
 
 xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
   double lohi[2], gersh[2];
   xlbomd_status st = spectral_bounds(c, F, lohi, gersh);
   if (st) return st;
-  double mu = *mu_io, fx[3];
-  if ((st = fermi_pass(c, F, lohi, mu, P, fx))) return st;
-  if (!c->is32 && !(std::fabs(fx[0]) <= FIX_MAX)) {
+  double mu = *mu_io, fx[3], tm[2] = {0.0, 0.0};  // tm: Tr M, Tr D
+  if ((st = fermi_pass(c, F, lohi, mu, P, fx, tm))) return st;
+  if (!chain_sound(c, tm)) {
     // once more on the rigorous Gershgorin interval, from the same warm start
     mu = *mu_io;
-    if ((st = fermi_pass(c, F, gersh, mu, P, fx))) return st;
-    if (!(std::fabs(fx[0]) <= FIX_MAX))
-      return fail(c, XLBOMD_E_NOCONV, "density matrix inconsistent (first-order trace step %.3e)", fx[0]);
+    if ((st = fermi_pass(c, F, gersh, mu, P, fx, tm))) return st;
+    if (!chain_sound(c, tm))
+      return fail(c, XLBOMD_E_NOCONV, "density matrix inconsistent (Tr D - N_occ %.3e, Tr D(I-D) %.3e)",
+                  tm[1] - c->n_occ, tm[0]);
   }
   if (c->fix_pending) {
     mu += fx[1] / c->beta;
@@ -989,7 +999,10 @@ xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bo
     const double tr = fx[2];
     if (!std::isfinite(tr)) return fail(c, XLBOMD_E_NONFINITE, "non-finite density matrix");
     if (std::fabs(tr - c->n_elec) > 1e-9 * c->n_elec + 4.0 * c->trace_tol)
-      return fail(c, XLBOMD_E_NOCONV, "trace %.15g differs from N_e %.15g", tr, c->n_elec);
+      return fail(c, XLBOMD_E_NOCONV,
+                  "trace %.15g differs from N_e %.15g (Tr D %.15g, Tr D(I-D) %.3e, first-order step %.3e, "
+                  "%d levels, %d mu passes)",
+                  tr, c->n_elec, tm[1], tm[0], fx[0], c->L, c->mu_passes);
   }
   return XLBOMD_OK;
 }
@@ -1169,7 +1182,6 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   f(c->onecenter);
   f(c->j55);
   f(c->noise_t);
-  f(c->pk);
   f(c->part);
   f(c->pk3);
   f(c->fpart);
@@ -1256,8 +1268,7 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
   A((void **)&c->onecenter, sizeof(double) * 5 * N);
   A((void **)&c->j55, sizeof(double) * 55);
   A((void **)&c->noise_t, sizeof(float) * std::max<size_t>(noise_tile_floats(N), 1));
-  A((void **)&c->pk, sizeof(double) * 10 * N);
-  A((void **)&c->part, sizeof(double) * 10 * (size_t)N * (T + 1));
+  A((void **)&c->part, sizeof(double) * 10 * (size_t)N * T);
   A((void **)&c->pk3, sizeof(double) * 30 * N);
   A((void **)&c->fpart, sizeof(double) * std::max<size_t>(force_partial_doubles(N), 1));
   A((void **)&c->epart, sizeof(double) * (energy_partial_doubles(N) + 8));

@@ -86,9 +86,8 @@ struct PairSys {
 };
 void repack_noise(int n_atoms, const float *noise_host_layout_dev, float *noise_t, hipStream_t s);
 size_t noise_tile_floats(int n_atoms);
-// F = [h +] G(P); partial: scratch of n_tiles * n_atoms * 10 doubles; pk: n_atoms * 10
-void fock(const PairSys &ps, const double *P, double *F, int include_h, double *pk,
-          double *partial, hipStream_t s);
+// F = [h +] G(P); partial: scratch of n_atoms * n_tiles * 10 doubles
+void fock(const PairSys &ps, const double *P, double *F, int include_h, double *partial, hipStream_t s);
 void hcore(const PairSys &ps, double *H, double *partial, hipStream_t s);
 // forces (n_atoms x 3) and energy parts e[0..2] = Tr[hP0], Tr[(P0-X/2)G(X)], Vnn (device)
 void forces(const PairSys &ps, const double *P0, const double *X, double *frc, double *e,

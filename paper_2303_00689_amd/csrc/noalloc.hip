@@ -70,6 +70,6 @@ extern "C" xlbomd_status xlbomd_spectral_bounds_noalloc(const double *F, int n, 
       hipMemcpyAsync(abh, ab, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return XLBOMD_E_HIP;
-  if (!xl::bounds_from_lanczos(g, abh, K, lohi)) return XLBOMD_E_NONFINITE;
+  if (!xl::bounds_from_lanczos(g, abh, K, n, lohi)) return XLBOMD_E_NONFINITE;
   return XLBOMD_OK;
 }

@@ -51,19 +51,6 @@ __global__ void k_repack(int N, int T, const float *src, float *dst) {
     dst[((size_t)tp * 55 + k) * 256 + slot] = valid ? src[p * 55 + k] : 0.0f;
 }
 
-// packed diagonal blocks (off-diagonal entries doubled); optional -z at ss
-__global__ void k_pack_diag(int N, int n, const double *P, double zsub, double *pk) {
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= N) return;
-  for (int r = 0; r < 10; ++r) {
-    const int m = PM[r], q = PN[r];
-    double v = P ? P[(size_t)(4 * A + m) * n + 4 * A + q] : 0.0;
-    if (m != q) v *= 2.0;
-    if (r == 0) v -= zsub;
-    pk[A * 10 + r] = v;
-  }
-}
-
 struct PairGeo {
   double r, l[3], gamma, dgamma, t, dt;
 };
@@ -84,10 +71,24 @@ __device__ inline PairGeo pair_geo(const PairSys &ps, int A, int B) {
   return g;
 }
 
-// F off-diagonal atom blocks and Coulomb partials.
-__global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const double *P,
-                                                     const double *pk, int include_h, double *F,
-                                                     double *part) {
+// F off-diagonal atom blocks and Coulomb partials.  A workgroup takes one
+// 16 x 16 atom-tile pair (ta <= tb), one thread per atom pair.
+//   1. the packed diagonal density blocks of its 32 atoms (off-diagonal
+//      entries doubled, -zsub at ss for h alone) into LDS;
+//   2. per pair the 10 x 10 two-centre block W_AB in registers, the exchange
+//      block G_AB = -1/2 sum P_AB W_AB and the Coulomb sums of A over B's
+//      packed density and of B over A's;
+//   3. the Coulomb sums reduced per atom over the tile's 16 partners, one
+//      partial per (atom, partner tile): part[(atom * T + tile) * 10 + r];
+//   4. the 64 x 64 block of F in LDS, written to F row by row and, transposed,
+//      to the mirrored position, 512 contiguous bytes per row.  On a diagonal
+//      tile pair (ta == tb) only blocks of distinct atoms are written; the
+//      diagonal atom blocks are k_fock_diag's.
+constexpr int FT = 4 * TA;       // F rows (and columns) of a tile: 64
+constexpr int FTP = FT + 1;      // padded LDS row of the staged block (doubles)
+
+__global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const double *P, double zsub,
+                                                     int include_h, double *F, double *part) {
   const int N = ps.n_atoms, T = ps.n_tiles;
   const int tp = blockIdx.x;
   int ta, tb;
@@ -96,8 +97,26 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
   const int A = ta * TA + al, B = tb * TA + bl;
   const bool valid = A < N && B < N && (ta < tb || al < bl);
 
-  __shared__ double shA[10][256];
-  __shared__ double shB[10][256];
+  // LDS, reused by the phases: packed diagonals (phase 1-2), Coulomb sums
+  // (phase 3), the staged F block (phase 4)
+  __shared__ double sh[2 * 10 * 256];
+  double *spk = sh + 2 * 10 * 256 - 32 * 10;  // [32][10]: A atoms 0..15, B atoms 16..31 (top of sh)
+  double *shA = sh, *shB = sh + 10 * 256;     // [10][256] each
+  double *ft = sh;                            // [FT][FTP]
+
+  for (int v = slot; v < 320; v += 256) {
+    const int q = v / 10, r = v % 10;
+    const int X = q < TA ? ta * TA + q : tb * TA + (q - TA);
+    double x = 0.0;
+    if (X < N) {
+      const int m = PM[r], c = PN[r];
+      x = P ? P[(size_t)(4 * X + m) * n + 4 * X + c] : 0.0;
+      if (m != c) x *= 2.0;
+      if (r == 0) x -= zsub;
+    }
+    spk[q * 10 + r] = x;
+  }
+  __syncthreads();
 
   double cA[10], cB[10], G[4][4];
 #pragma unroll
@@ -116,8 +135,8 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
       for (int j = 0; j < 4; ++j) Pab[i][j] = P ? P[(size_t)(4 * A + i) * n + 4 * B + j] : 0.0;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-      pA[r] = pk[A * 10 + r];
-      pB[r] = pk[B * 10 + r];
+      pA[r] = spk[al * 10 + r];
+      pB[r] = spk[(TA + bl) * 10 + r];
     }
     const float *nz = ps.noise_t + (size_t)tp * 55 * 256 + slot;
 #pragma unroll
@@ -158,35 +177,63 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
         for (int i = 0; i < 3; ++i) G[1 + i][1 + j] += t * g.l[i] * g.l[j];
       }
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        F[(size_t)(4 * A + i) * n + 4 * B + j] = G[i][j];
-        F[(size_t)(4 * B + j) * n + 4 * A + i] = G[i][j];
-      }
-    }
   }
+  __syncthreads();  // every read of the packed diagonals is done
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    shA[r][slot] = cA[r];
-    shB[r][slot] = cB[r];
+    shA[r * 256 + slot] = cA[r];
+    shB[r * 256 + slot] = cB[r];
   }
   __syncthreads();
   if (slot < 160) {
     const int x = slot / 10, r = slot % 10;
     double row = 0.0, col = 0.0;
     for (int q = 0; q < TA; ++q) {
-      row += shA[r][x * TA + q];  // atom ta*16+x as A, over partners b
-      col += shB[r][q * TA + x];  // atom tb*16+x as B, over partners a
+      row += shA[r * 256 + x * TA + q];  // atom ta*16+x as A, over partners b
+      col += shB[r * 256 + q * TA + x];  // atom tb*16+x as B, over partners a
     }
     if (ta == tb) {
       const int X = ta * TA + x;
-      if (X < N) part[((size_t)ta * N + X) * 10 + r] = row + col;
+      if (X < N) part[((size_t)X * T + ta) * 10 + r] = row + col;
     } else {
       const int XA = ta * TA + x, XB = tb * TA + x;
-      if (XA < N) part[((size_t)tb * N + XA) * 10 + r] = row;
-      if (XB < N) part[((size_t)ta * N + XB) * 10 + r] = col;
+      if (XA < N) part[((size_t)XA * T + tb) * 10 + r] = row;
+      if (XB < N) part[((size_t)XB * T + ta) * 10 + r] = col;
+    }
+  }
+  __syncthreads();  // the Coulomb sums are read; the block is staged over them
+  // On a diagonal tile pair the pairs a < b fill the upper blocks and their
+  // transposes the lower ones (each LDS word written by one thread only); the
+  // diagonal atom blocks are left out below.
+  if (ta != tb || valid) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ft[(4 * al + i) * FTP + 4 * bl + j] = G[i][j];
+        if (ta == tb) ft[(4 * bl + j) * FTP + 4 * al + i] = G[i][j];
+      }
+  }
+  __syncthreads();
+  // 8 threads per row, two consecutive columns per store: 128 contiguous
+  // bytes of a row per store instruction, for the block and for its transpose
+  // (a column of the staged block)
+  const int k8 = slot & 7;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int row = pass * 32 + (slot >> 3);
+    const int ra = ta * TA + row / 4;  // atom of block row `row` (tile ta)
+    const int rb = tb * TA + row / 4;  // atom of transposed row `row` (tile tb)
+    const size_t ga = ((size_t)4 * ta * TA + row) * n + (size_t)4 * tb * TA;
+    const size_t gb = ((size_t)4 * tb * TA + row) * n + (size_t)4 * ta * TA;
+#pragma unroll
+    for (int s8 = 0; s8 < 4; ++s8) {
+      const int cc = 16 * s8 + 2 * k8;  // two consecutive columns of one atom
+      const int ca = tb * TA + cc / 4, cb = ta * TA + cc / 4;
+      if (ra < N && ca < N && (ta != tb || ra != ca))
+        *(double2 *)(F + ga + cc) = double2{ft[row * FTP + cc], ft[row * FTP + cc + 1]};
+      if (ta != tb && rb < N && cb < N)
+        *(double2 *)(F + gb + cc) = double2{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]};
     }
   }
 }
@@ -209,26 +256,47 @@ __device__ inline void onecenter_G(const double *oc, const double Pd[4][4], doub
   }
 }
 
-__global__ void k_fock_diag(PairSys ps, int n, const double *P, int include_h, const double *part,
-                            double *F) {
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  const int N = ps.n_atoms;
+// Diagonal atom blocks: the one-centre part (eq. 6 with the one-centre
+// integrals), the two-centre Coulomb sums over all partners, and h's on-site
+// terms.  One wavefront per atom: lane l adds the partials of partner tiles
+// l, l + 64, ... in that order, then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(256) void k_fock_diag(PairSys ps, int n, const double *P, int include_h,
+                                                   const double *part, double *F) {
+  const int N = ps.n_atoms, T = ps.n_tiles;
+  const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (A >= N) return;
   double coul[10];
+#pragma unroll
   for (int r = 0; r < 10; ++r) coul[r] = 0.0;
-  for (int t = 0; t < ps.n_tiles; ++t)
-    for (int r = 0; r < 10; ++r) coul[r] += part[((size_t)t * N + A) * 10 + r];
-  double Pd[4][4], G1[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) Pd[i][j] = P ? P[(size_t)(4 * A + i) * n + 4 * A + j] : 0.0;
-  onecenter_G(ps.onecenter + 5 * A, Pd, G1);
-  for (int r = 0; r < 10; ++r) {
-    const int m = PM[r], q = PN[r];
-    double v = G1[m][q] + coul[r];
-    if (include_h && m == q) v += (m == 0) ? ps.eps_s : ps.eps_p;
-    F[(size_t)(4 * A + m) * n + 4 * A + q] = v;
-    if (m != q) F[(size_t)(4 * A + q) * n + 4 * A + m] = v;
+  for (int t = lane; t < T; t += 64) {
+    const double *pp = part + ((size_t)A * T + t) * 10;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) coul[r] += pp[r];
   }
+#pragma unroll
+  for (int r = 0; r < 10; ++r)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) coul[r] += __shfl_xor(coul[r], o, 64);
+  if (lane >= 16) return;
+  // lane 4 i + j writes element (i, j) of the block, the value of the upper
+  // element (lo, hi) for both (i, j) and (j, i): like the pair blocks, the
+  // diagonal blocks take P's upper triangle, so F is symmetric for any P
+  const int i = lane >> 2, j = lane & 3;
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  double Pd[4][4], G1[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Pd[a][b] = P ? P[(size_t)(4 * A + a) * n + 4 * A + b] : 0.0;
+  onecenter_G(ps.onecenter + 5 * A, Pd, G1);
+  double c = 0.0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r)
+    if (PM[r] == lo && PN[r] == hi) c = coul[r];
+  double v = G1[lo][hi] + c;
+  if (include_h && i == j) v += (i == 0) ? ps.eps_s : ps.eps_p;
+  F[(size_t)(4 * A + i) * n + 4 * A + j] = v;
 }
 
 // ---- forces and pair energies
@@ -430,24 +498,19 @@ void repack_noise(int n_atoms, const float *src, float *dst, hipStream_t s) {
   hipLaunchKernelGGL(k_repack, dim3(T * (T + 1) / 2), dim3(256), 0, s, n_atoms, T, src, dst);
 }
 
-void fock(const PairSys &ps, const double *P, double *F, int include_h, double *pk, double *part,
-          hipStream_t s) {
+void fock(const PairSys &ps, const double *P, double *F, int include_h, double *part, hipStream_t s) {
   const int N = ps.n_atoms, n = 4 * N, T = ps.n_tiles;
-  hipLaunchKernelGGL(k_pack_diag, dim3((N + 127) / 128), dim3(128), 0, s, N, n, P,
-                     include_h ? ps.z_core : 0.0, pk);
   if (N > 1)
-    hipLaunchKernelGGL(k_fock_pairs, dim3(T * (T + 1) / 2), dim3(256), 0, s, ps, n, P, pk, include_h,
-                       F, part);
+    hipLaunchKernelGGL(k_fock_pairs, dim3(T * (T + 1) / 2), dim3(256), 0, s, ps, n, P,
+                       include_h ? ps.z_core : 0.0, include_h, F, part);
   else
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)10 * N * T, part);
-  hipLaunchKernelGGL(k_fock_diag, dim3((N + 127) / 128), dim3(128), 0, s, ps, n, P, include_h, part, F);
+  hipLaunchKernelGGL(k_fock_diag, dim3((N + 3) / 4), dim3(256), 0, s, ps, n, P, include_h, part, F);
 }
 
 void hcore(const PairSys &ps, double *H, double *part, hipStream_t s) {
   // h = F(P = 0) with the core attraction carried by the packed "-z at ss" density
-  const int N = ps.n_atoms;
-  double *pk = part + (size_t)ps.n_tiles * N * 10;
-  fock(ps, nullptr, H, 1, pk, part, s);
+  fock(ps, nullptr, H, 1, part, s);
 }
 
 size_t force_partial_doubles(int n_atoms) {

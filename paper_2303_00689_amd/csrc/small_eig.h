@@ -75,12 +75,15 @@ inline bool tridiag_eig_last(int k, const double *d, const double *e, double *ev
   return true;
 }
 
-// Spectral bounds from the Gershgorin interval g[0..1] and K Lanczos steps
-// ab[2 j] = alpha_j, ab[2 j + 1] = beta_j: the extreme Ritz values widened by
-// their residual bounds beta_k |s_k| and by 1e-3 of the Ritz spread, clipped
-// to the Gershgorin interval (kept alone if the Lanczos data are not finite
-// or the small solve fails).  Returns false if g is not finite.
-inline bool bounds_from_lanczos(const double g[2], const double *ab, int K, double lohi[2]) {
+// Spectral bounds of a symmetric n x n matrix from its Gershgorin interval
+// g[0..1] and K Lanczos steps ab[2 j] = alpha_j, ab[2 j + 1] = beta_j: the
+// extreme Ritz values widened by their residual bounds beta_k |s_k| and by
+// 1e-3 of the Ritz spread, clipped to the Gershgorin interval.  The
+// Gershgorin interval is kept alone if the Lanczos data are not finite, if
+// the small solve fails, or if the Krylov space closed (beta_j ~ 0) before
+// spanning all n dimensions: its Ritz values are then eigenvalues, but the
+// eigenvalues outside it are not seen.  Returns false if g is not finite.
+inline bool bounds_from_lanczos(const double g[2], const double *ab, int K, int n, double lohi[2]) {
   if (!std::isfinite(g[0]) || !std::isfinite(g[1])) return false;
   lohi[0] = g[0];
   lohi[1] = g[1];
@@ -90,7 +93,10 @@ inline bool bounds_from_lanczos(const double g[2], const double *ab, int K, doub
   for (int j = 0; j < K; ++j) {
     if (!std::isfinite(ab[2 * j]) || !std::isfinite(ab[2 * j + 1])) return true;  // keep Gershgorin
     if (ab[2 * j + 1] <= 1e-12 * scale) {
-      k = j + 1;  // invariant subspace: the Ritz values are eigenvalues
+      // invariant subspace: the Ritz values are eigenvalues, and all of them
+      // only if the subspace is the whole space
+      if (j + 1 < n) return true;
+      k = j + 1;
       break;
     }
   }

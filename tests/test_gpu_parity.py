@@ -450,3 +450,21 @@ def test_state_arguments_are_checked_before_any_work(lib):
     with pytest.raises(lib.XLBOMDError):
         case.h.step_langevin(state, torch.zeros((1, s.n_atoms, 3), dtype=torch.float64), 0.01, 300.0)
     case.h.close()
+
+
+def test_fock_reads_the_upper_triangle(case):
+    """F is symmetric for any P: every block of G(P) takes P's upper triangle
+    (the MD history X carries an antisymmetric part at rounding level, and a
+    non-symmetric F would break the chains, which rely on symmetric operands).
+    A non-symmetric P gives, bit for bit, the F of its upper triangle mirrored."""
+    s = case.sys
+    n = s.n_orb
+    P = case.rng.standard_normal((n, n))
+    Pu = np.triu(P) + np.triu(P, 1).T
+    F1 = torch.empty((n, n), dtype=torch.float64, device=case.dev)
+    F2 = torch.empty_like(F1)
+    case.h.fock(case.t(P), F1, include_h=True)
+    case.h.fock(case.t(Pu), F2, include_h=True)
+    torch.cuda.synchronize()
+    assert torch.equal(F1, F2)
+    assert torch.equal(F1, F1.T)
