@@ -177,7 +177,12 @@ class Handle:
         if self._oc.shape != (self.n_atoms, 5):
             raise XLBOMDError("onecenter must be (n_atoms, 5)")
         npair = self.n_atoms * (self.n_atoms - 1) // 2
-        self._noise = np.ascontiguousarray(noise55, dtype=np.float32) if npair else np.zeros((0, 55), np.float32)
+        # the ABI takes the noise blocks in FP32: values that FP32 does not hold
+        # exactly are refused rather than rounded
+        noise = np.asarray(noise55) if npair else np.zeros((0, 55), np.float32)
+        self._noise = np.ascontiguousarray(noise, dtype=np.float32)
+        if noise.dtype != np.float32 and not np.array_equal(self._noise.astype(noise.dtype), noise):
+            raise XLBOMDError("noise55 holds values that FP32 does not represent exactly")
         if self._noise.shape != (npair, 55):
             raise XLBOMDError("noise55 must be (n_pair, 55)")
         mdl = Model()

@@ -112,3 +112,15 @@ def test_create_rejects_bad_arguments_before_any_device_call(built):
         st, h = create(**kw)
         assert st == -1, kw
         assert h is None, kw
+
+
+def test_binding_refuses_noise_that_fp32_does_not_hold(built):
+    """The ABI takes the two-centre noise in FP32; the binding refuses FP64
+    noise that would be rounded (before any device call)."""
+    import numpy as np
+    from paper_2303_00689_amd import binding
+    from synth import carbon_cluster
+    s = carbon_cluster(3, 1)
+    bad = s.noise.astype(np.float64) + 1e-12
+    with pytest.raises(binding.XLBOMDError):
+        binding.Handle(s.n_atoms, s.n_elec, s.onecenter, bad, s.params)
