@@ -111,23 +111,19 @@ def cpu_baseline(sys_, w, X, threads=0):
 
 
 def kernel_traffic(kclass):
-    """HBM bytes per launch of a kernel class from the committed counter
-    summary (two rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, scaled by the
-    same counters on a plain copy), or None when the summary is missing or was
-    taken on a different version of the kernel's source."""
+    """HBM bytes per launch of a kernel class (one Fock build for "fock") from
+    the committed counter summary: two rocprofv3 --pmc runs, FETCH_SIZE and
+    WRITE_SIZE, scaled by the same counters on a plain copy.  None when the
+    summary is missing, has no record for the class, or was taken on a
+    different version of the kernel's source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_c840.json")
-    if kclass.startswith("gemm_f64"):
-        kclass = "gemm_f64"
-    elif kclass.startswith("gemm_"):
-        kclass = "gemm_split"
-    src = {"gemm_f64": "gemm_f64.hip", "gemm_split": "gemm_split.hip", "fock": "pairs.hip"}.get(kclass)
-    if not src or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kclass)
     if not rec:
         return None
-    with open(os.path.join(ROOT, "paper_2303_00689_amd", "csrc", src), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2303_00689_amd", "csrc", rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
     return rec["hbm_bytes_per_launch"]
