@@ -307,12 +307,21 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
     P = torch.empty_like(F)
     f64 = torch.empty((sys_.n_atoms, 3), dtype=torch.float64, device=dev)
 
-    def run(h, Xstart, evaluate=False):
+    def run(h, Xstart, evaluate=False, label=""):
+        # stops at the first step whose status is not OK (a non-finite value,
+        # or a guard of the handle)
         st = md_start(binding, torch, sys_, Xstart, dev)
         h.md_init(st)
-        frc, X, E, same = [], [], [], []
-        for _ in range(steps):
-            E.append(h.step(st, 1, report=True)[0]["E_tot"])
+        frc, X, E, same, rec = [], [], [], [], []
+        stop = None
+        for k in range(steps):
+            status, reps = h.step(st, 1, report=True, check=False)
+            if status != 0:
+                stop = {"step": k + 1, "status": binding.STATUS.get(status, status)}
+                break
+            r = reps[0]
+            E.append(r["E_tot"])
+            rec.append((r["T_ion"], r["W0"], r["relres"], r["levels"], r["mu_passes"]))
             fs = st.A * conv
             frc.append(fs.clone())
             X.append(st.x_current().clone())
@@ -323,36 +332,102 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
                 hev.fermi_dm(F, P, mu=st.mu)
                 hev.forces(P, Xc, f64)
                 same.append(float((f64 - fs).abs().max()))
-        return frc, X, E, same
+            if (k + 1) % 50 == 0:
+                log(f"    {label} step {k + 1}: E_tot {r['E_tot']:.6f} T_ion {r['T_ion']:.0f} K W0 {r['W0']:.3g}")
+        return frc, X, E, same, rec, stop
 
     def drift(E):
+        if len(E) < 2:
+            return None
         tfs = w["dt"] * np.arange(1, len(E) + 1)
         return float(np.polyfit(tfs, np.array(E), 1)[0]) * 1000.0 / sys_.n_atoms
 
-    fs_, Xs_, Es_, same = run(hs, X0, evaluate=True)
+    fs_, Xs_, Es_, same, rs_, stop_s = run(hs, X0, evaluate=True, label="split")
     log("  split trajectory with FP64 re-evaluation done")
-    f6_, X6_, E6_, _ = run(h64, X0)
+    f6_, X6_, E6_, _, r6_, stop_6 = run(h64, X0, label="fp64")
     log("  FP64 trajectory done")
-    d1 = float(torch.linalg.norm(Xs_[0] - X6_[0]))
+    # the perturbation: the first step's split-vs-FP64 difference of X (1e-12
+    # of X0 if either run stopped at its first step)
+    d1 = (float(torch.linalg.norm(Xs_[0] - X6_[0])) if Xs_ and X6_
+          else 1e-12 * float(torch.linalg.norm(X0)))
     rng = np.random.default_rng(29)
     pert = rng.standard_normal((n, n))
     pert = pert + pert.T
     pert *= d1 / np.linalg.norm(pert)
-    fp_, Xp_, Ep_, _ = run(h64, X0 + torch.tensor(pert, dtype=torch.float64, device=dev))
+    fp_, Xp_, Ep_, _, rp_, stop_p = run(h64, X0 + torch.tensor(pert, dtype=torch.float64, device=dev),
+                                        label="fp64 perturbed")
     log("  perturbed FP64 trajectory done")
     for h in (hs, h64, hev):
         h.close()
     fdiff = lambda a, b: [float((x - y).abs().max()) for x, y in zip(a, b)]
     xdiff = lambda a, b: [float(torch.linalg.norm(x - y)) for x, y in zip(a, b)]
+    traj = lambda E, rec, stop: {"steps_run": len(E), "stopped": stop, "E_tot": E,
+                                 "T_ion_K": [x[0] for x in rec], "W0": [x[1] for x in rec],
+                                 "relres": [x[2] for x in rec], "levels": [x[3] for x in rec],
+                                 "mu_passes": [x[4] for x in rec]}
     return {
         "steps": steps,
-        "same_state_force_err_eV_per_A": {"max": max(same), "per_step": same},
+        "same_state_force_err_eV_per_A": {"max": max(same) if same else None, "per_step": same},
         "divergence": {
             "split_vs_fp64": {"force_maxabs_eV_per_A": fdiff(fs_, f6_), "X_fro": xdiff(Xs_, X6_)},
             "fp64_vs_fp64_perturbed": {"perturbation_fro": d1, "force_maxabs_eV_per_A": fdiff(fp_, f6_),
                                        "X_fro": xdiff(Xp_, X6_)}},
         "drift_eV_per_ps_per_atom": {"split": drift(Es_), "fp64": drift(E6_), "fp64_perturbed": drift(Ep_)},
+        "trajectories": {"split": traj(Es_, rs_, stop_s), "fp64": traj(E6_, r6_, stop_6),
+                         "fp64_perturbed": traj(Ep_, rp_, stop_p)},
     }
+
+
+def initial_scf(binding, torch, sys_, w, dev, n_mix, n_newton):
+    """X0 for MD: xlbomd_scf from the uniform density, linear mixing
+    X <- X + 0.04 (D0[X] - X) for n_mix steps, then up to n_newton rank-12
+    Newton-Krylov steps, with an FP64 density matrix; the report carries the
+    residual ||D0[X0] - X0||_F reached."""
+    n = sys_.n_orb
+    t = time.perf_counter()
+    hi = binding.handle_for(sys_, w, prec="dm64_bf16x3")
+    hi.set_geometry(torch.tensor(sys_.R, dtype=torch.float64, device=dev))
+    X0 = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
+    init = hi.scf(X0, m=12, tol=1e-10, max_iter=n_newton, mix=0.04, mix_tol=0.0, max_mix=n_mix,
+                  allow_noconv=True)
+    hi.close()
+    torch.cuda.synchronize()
+    init["seconds"] = time.perf_counter() - t
+    log(f"initial SCF: {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps, "
+        f"residual {init['residual']:.3e} ({init['seconds']:.1f} s)")
+    return X0, init
+
+
+def run_study_lowgap(args, binding, torch, np, dev):
+    """The low-gap stress trajectory: the split mode against FP64 over
+    --study-steps NVE steps from the same start (compare_legs), plus the
+    steps/s of both modes with every timed step restarting from that start."""
+    from synth import workload
+    sys_, w = workload("c840_lowgap")
+    X0, init = initial_scf(binding, torch, sys_, w, dev, args.init_mix, args.init_newton)
+    R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
+    timed = {}
+    for prec in (args.study_prec, "fp64"):
+        h = binding.handle_for(sys_, w, prec=prec)
+        h.set_geometry(R0)
+        st = md_start(binding, torch, sys_, X0, dev)
+        h.md_init(st)
+        el, _ = timed_reset_leg(torch, h, st, Snapshot(st), 5, 1)
+        h.close()
+        timed[prec] = {"steps_per_s": 5 / el, "ms_per_step": 1e3 * el / 5}
+        log(f"  timed {prec}: {5 / el:.2f} steps/s")
+    cmp = compare_legs(binding, torch, np, sys_, w, args.study_prec, X0, args.study_steps, dev)
+    fe = cmp["same_state_force_err_eV_per_A"]["max"]
+    print(json.dumps({
+        "study": "c840_lowgap",
+        "workload": (f"840-atom carbon cluster (seeded random packing, {sys_.params.j_pattern} J), hopping x0.6, "
+                     f"s-p split 4 eV, T_e {w['T_e']:.0f} K, Krylov rank {w['m']}, dt {w['dt']} fs; MD from the "
+                     f"SCF iterate after {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps "
+                     f"(residual {init['residual']:.3g})"),
+        "precision": args.study_prec, "steps": args.study_steps, "init": init,
+        "timed_reset_steps": timed,
+        "force_err_vs_fp64_eV_per_A": fe, "force_err_ok": fe is not None and fe <= 1e-4,
+        "split_vs_fp64": cmp}))
 
 
 def main():
@@ -375,6 +450,12 @@ def main():
                     help="instead: the ragged ensemble of this many clusters (20-300 atoms, 3000 K, "
                          "rank 4) through xlbomd_ensemble_step, against the same members stepped one "
                          "after another")
+    ap.add_argument("--study", default="", choices=["", "lowgap"],
+                    help="instead: the low-gap trajectory study (840 atoms, hopping x0.6, s-p split 4 eV, "
+                         "10000 K, rank 8): --study-steps NVE steps of --study-prec against FP64 from the "
+                         "same start, with drift and force error; prints one JSON line of its own")
+    ap.add_argument("--study-steps", type=int, default=200)
+    ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -404,26 +485,18 @@ def main():
     if args.ensemble:
         run_ensemble(args, binding, torch, dev)
         return
+    if args.study:
+        run_study_lowgap(args, binding, torch, np, dev)
+        return
     sys_, w = workload(args.workload)
     n = sys_.n_orb
 
-    # ---- initial state (untimed): xlbomd_scf from the uniform density --
-    # linear mixing X <- X + 0.04 (D0[X] - X), then rank-12 Newton-Krylov
-    # steps -- with an FP64 density matrix.  The seeded cluster's SCF is stiff
-    # (it stalls near 0.3 even with rank-30 Newton steps), so MD starts from
-    # this partially converged density and its residual is reported.
-    t = time.perf_counter()
+    # ---- initial state (untimed): xlbomd_scf from the uniform density.  The
+    # seeded cluster's SCF is stiff (it stalls near 0.3 even with rank-30
+    # Newton steps), so MD starts from this partially converged density and
+    # its residual is reported.
+    X0, init = initial_scf(binding, torch, sys_, w, dev, args.init_mix, args.init_newton)
     R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
-    hi = binding.handle_for(sys_, w, prec="dm64_bf16x3")
-    hi.set_geometry(R0)
-    X0 = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
-    init = hi.scf(X0, m=12, tol=1e-10, max_iter=args.init_newton, mix=0.04, mix_tol=0.0,
-                  max_mix=args.init_mix, allow_noconv=True)
-    hi.close()
-    torch.cuda.synchronize()
-    init["seconds"] = time.perf_counter() - t
-    log(f"initial SCF: {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps, "
-        f"residual {init['residual']:.3e} ({init['seconds']:.1f} s)")
 
     def prepared(prec):
         h = binding.handle_for(sys_, w, prec=prec)

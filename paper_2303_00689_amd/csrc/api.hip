@@ -911,11 +911,14 @@ xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], d
   xlbomd_status st;
   bool cold = !std::isfinite(mu);
   bool converged = false;
+  double bracket = 0.4 / c->beta;
   for (int attempt = 0; attempt < 4 && !converged; ++attempt) {
     if (cold) {
-      // bisection on Tr D(mu) with full chains until the bracket is within 0.4/beta
+      // bisection on Tr D(mu) with full chains until the bracket is within
+      // 0.4/beta; a retry after the shift passes ran out bisects 10x tighter,
+      // so that they start closer
       double a = lohi[0], b = lohi[1];
-      while (b - a > 0.4 / c->beta) {
+      while (b - a > bracket) {
         const double mid = 0.5 * (a + b);
         if ((st = run_chain(c, F, mid, lohi[0], lohi[1]))) return st;
         trace(n, c->D, c->dscal + S_TRD, c->is32, c->red, c->s);
@@ -928,6 +931,7 @@ xlbomd_status fermi_pass(xlbomd_ctx *c, const double *F, const double lohi[2], d
       }
       mu = 0.5 * (a + b);
       cold = false;
+      bracket *= 0.1;
     }
     if ((st = run_chain(c, F, mu, lohi[0], lohi[1]))) return st;
     double dmu = 0.0;

@@ -1,0 +1,233 @@
+"""100 NVE steps of the 100-atom cluster (T_e = 5000 K, rank-4 Krylov kernel,
+dt = 0.5 fs) in FP64 on the GPU against the oracle, step for step.
+
+Both sides start from the same state: the oracle's density after a fixed
+number of linear-mixing steps from the uniform density (X0), the history
+filled with X0 (Methods, section 5).  The seeded cluster's SCF stalls, so X0
+is not D_min, and from such a start eq. 35 over-relaxes: the trajectory heats
+by orders of magnitude within tens of steps and is chaotic, so two correct
+implementations that round differently part ways at a rate set by the
+trajectory, not by either of them.  The test therefore checks:
+
+* every step: the oracle's step (eqs. 27-30, 35) from the GPU's own state
+  before it reproduces the GPU's state after it -- positions, the new X,
+  accelerations, the Krylov kernel Y and the shadow energy E_tot -- to the
+  parity bars of a single MD step;
+* the first step of the two free trajectories from X0 agrees to rounding;
+* the drift of E_tot (eq. 26's constant of motion) of both trajectories,
+  and their divergence next to an oracle twin started from X0 plus a 1e-12
+  relative symmetric perturbation, are printed.
+
+The Krylov kernel Y is the least-squares solution over a Krylov space of J
+(eq. 34).  To first order, a relative error e in the responses W_k = J V_k
+moves Y by up to A cond(O) e, where O_ij = <W_i, W_j> is the overlap matrix
+of the normal equations and A is the product over k of
+||W_k|| / ||W_k - sum_j <V_j, W_k> V_j||: the growth of e through each new
+basis direction V_{k+1}, which is W_k orthogonalised against V_1..V_k.  The
+responses are held to 1e-10 (the parity of the canonical response), so Y is
+held to max(1e-10, 1e-10 A cond(O)) of max|Y|, with A and cond(O) taken from
+the oracle's own V_k and W_k at that step; the measured Y error over
+A cond(O), the implied response difference, is printed.
+
+A second run takes the 10-atom cluster of the first workload (T_e 3000 K,
+rank 3) from its SCF ground state (Methods, section 5: X(t0 - k dt) = D_min)
+through the same checks.  The seeded clusters do not hold still even from
+there: the random packing releases potential energy into the ions within a
+few fs, and the SCF map of the heated cluster turns unstable, where D0[X]
+moves faster than X can follow and E_tot stops being conserved.  The run
+prints E_tot over the early steps, where it is conserved, and the whole run.
+"""
+
+import json
+
+import numpy as np
+import pytest
+
+from synth import workload
+from oracle import dynamics, model, density
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+N_MIX = 100
+STEPS = 100
+TOL = 1e-10
+
+
+def t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def mixed_start(s, st):
+    """X after N_MIX steps X <- X + 0.04 (D0[X] - X) from N_e / n I (oracle)."""
+    n = s.n_orb
+    X = np.eye(n) * (s.n_elec / n)
+    h = model.hcore(s.R, s.onecenter, s.noise, s.params)
+    for _ in range(N_MIX):
+        F = h + model.two_electron(X, s.R, s.onecenter, s.noise, s.params)
+        X = X + 0.04 * (density.density_matrix(F, s.n_elec, st.beta)["P"] - X)
+    return X
+
+
+def oracle_run(s, st, X0):
+    o = dynamics.init_state(s, st, X0)
+    out = []
+    for _ in range(STEPS):
+        o, rep = dynamics.md_step(o, s, st)
+        out.append(dict(R=o.R.copy(), X=o.Xhist[0].copy(), E=rep["E_tot"], T=rep["T_ion"], W0=rep["W0"]))
+    return out
+
+
+class KrylovSpy:
+    """Wraps the oracle's Krylov kernel (arithmetic unchanged) to keep the
+    V_k and W_k = J V_k of its last call; amplification() is A cond(O)."""
+
+    def __init__(self, mp):
+        self.V, self.W = [], []
+        inner_fn = dynamics.krylov.krylov_kernel
+
+        def spy(X, P0, jac, m, tol=0.0, **kw):
+            self.V, self.W = [], []
+
+            def jac2(V):
+                w = jac(V)
+                self.V.append(V.copy())
+                self.W.append(w)
+                return w
+            return inner_fn(X, P0, jac2, m, tol, **kw)
+        mp.setattr(dynamics.krylov, "krylov_kernel", spy)
+
+    def amplification(self):
+        if not self.W:
+            return 1.0
+        O = np.array([[np.sum(a * b) for b in self.W] for a in self.W])
+        A = 1.0
+        for k in range(len(self.W) - 1):
+            r = self.W[k].copy()
+            for _ in range(2):
+                for v in self.V[:k + 1]:
+                    r = r - np.sum(v * r) * v
+            A *= np.linalg.norm(self.W[k]) / np.linalg.norm(r)
+        return float(A * np.linalg.cond(O))
+
+
+def gpu_as_oracle_state(state, step):
+    """The oracle's MDState holding the GPU's state (X(t - k dt) in ring slot
+    (head + k) % 7)."""
+    X = state.X.cpu().numpy()
+    return dynamics.MDState(R=state.R.cpu().numpy(), V=state.V.cpu().numpy(), A=state.A.cpu().numpy(),
+                            Xhist=[X[(state.head + k) % 7].copy() for k in range(7)], Y=state.Y.cpu().numpy(),
+                            mu=state.mu, step=step)
+
+
+def step_by_step(binding, s, w, st, X0, spy, steps):
+    """GPU trajectory from X0; after every step, the oracle's step from the
+    GPU's state before it.  Returns (gpu records, stop, worst errors)."""
+    n = s.n_orb
+    h = binding.handle_for(s, w)
+    worst = {q: (0.0, 0) for q in ("R", "X", "A", "Y", "E", "Y_over_amp")}
+    gpu, stop = [], None
+    try:
+        h.set_geometry(t(s.R))
+        state = binding.MDState(R=t(s.R), V=t(s.V), A=torch.zeros((s.n_atoms, 3), dtype=torch.float64, device=DEV),
+                                X=torch.stack([t(X0)] * 7), Y=torch.zeros((n, n), dtype=torch.float64, device=DEV))
+        h.md_init(state)
+        for k in range(steps):
+            before = gpu_as_oracle_state(state, k)
+            status, reps = h.step(state, 1, check=False)
+            if status != 0:
+                stop = (k + 1, binding.STATUS.get(status, status), h.lib.xlbomd_last_error(h.h).decode())
+                break
+            rep = reps[0]
+            o, orep = dynamics.md_step(before, s, st)
+            amp = spy.amplification()
+            err = dict(R=rel(state.R.cpu().numpy(), o.R), X=rel(state.x_current().cpu().numpy(), o.Xhist[0]),
+                       A=rel(state.A.cpu().numpy(), o.A), Y=rel(state.Y.cpu().numpy(), o.Y),
+                       E=abs(rep["E_tot"] - orep["E_tot"]) / abs(orep["E_tot"]))
+            err["Y_over_amp"] = err["Y"] / amp
+            err["Y_bar"] = max(TOL, 1e-10 * amp)
+            for q in worst:
+                if err[q] > worst[q][0]:
+                    worst[q] = (err[q], k + 1)
+            gpu.append(dict(R=state.R.cpu().numpy(), X=state.x_current().cpu().numpy(), E=rep["E_tot"],
+                            T=rep["T_ion"], W0=rep["W0"], relres=rep["relres"], amp=amp, err=err))
+    finally:
+        h.close()
+    return gpu, stop, worst
+
+
+def check_steps(gpu, stop, worst):
+    assert stop is None, stop
+    # one step from the same state: the parity bars of a single MD step
+    assert worst["R"][0] <= 1e-12, worst["R"]
+    for q in ("X", "A", "E"):
+        assert worst[q][0] <= TOL, (q, worst[q])
+    bad = [(k + 1, r["err"]["Y"], r["amp"]) for k, r in enumerate(gpu) if r["err"]["Y"] > r["err"]["Y_bar"]]
+    assert not bad, bad[:5]
+
+
+def dist(a, b):
+    return dict(R=float(np.abs(a["R"] - b["R"]).max()), X=float(np.linalg.norm(a["X"] - b["X"])),
+                E=float(abs(a["E"] - b["E"])))
+
+
+def run_case(binding, monkeypatch, name, X0, note):
+    s, w = workload(name)
+    st = dynamics.Settings(T_e=w["T_e"], m=w["m"], dt=w["dt"])
+    n = s.n_orb
+    res0 = np.linalg.norm(dynamics.evaluate(s.R, X0, s, st, with_kernel=False)["P0"] - X0)
+    print(f"{name}: start {note}, residual {res0:.3e}", flush=True)
+    spy = KrylovSpy(monkeypatch)
+    gpu, stop, worst = step_by_step(binding, s, w, st, X0, spy, STEPS)
+    print(f"{name}: GPU steps {len(gpu)}, stop {stop}; worst one-step errors {worst}", flush=True)
+
+    orc = oracle_run(s, st, X0)
+    rng = np.random.default_rng(31)
+    pert = rng.standard_normal((n, n))
+    pert = pert + pert.T
+    pert *= 1e-12 * np.linalg.norm(X0) / np.linalg.norm(pert)
+    twin = oracle_run(s, st, X0 + pert)
+
+    steps = len(gpu)
+    tfs = w["dt"] * np.arange(1, steps + 1)
+    E_g = np.array([r["E"] for r in gpu])
+    E_o = np.array([r["E"] for r in orc[:steps]])
+    early = min(10, steps)
+    shown = [k for k in (1, 2, 5, 10, 20, 30, 40, 50, 60, 70, 80, 90, 100) if k <= steps]
+    print(f"{name} summary " + json.dumps({
+        "start": note, "start_residual": float(res0), "gpu_stop": stop,
+        "worst_one_step_rel_err": {q: {"err": v, "step": k} for q, (v, k) in worst.items()},
+        "drift_eV_per_ps_per_atom": {"gpu": float(np.polyfit(tfs, E_g, 1)[0]) * 1000.0 / s.n_atoms,
+                                     "oracle": float(np.polyfit(tfs, E_o, 1)[0]) * 1000.0 / s.n_atoms},
+        "E_tot_ptp_eV": {"first_10_gpu": float(np.ptp(E_g[:early])), "first_10_oracle": float(np.ptp(E_o[:early])),
+                         "all_gpu": float(np.ptp(E_g)), "all_oracle": float(np.ptp(E_o))},
+        "steps": [{"step": k, "T_ion_K": round(gpu[k - 1]["T"], 1), "W0": gpu[k - 1]["W0"],
+                   "relres": gpu[k - 1]["relres"], "A_cond_O": gpu[k - 1]["amp"], "Y_err": gpu[k - 1]["err"]["Y"],
+                   "E_tot_gpu": gpu[k - 1]["E"], "E_tot_oracle": orc[k - 1]["E"],
+                   "gpu_vs_oracle": dist(gpu[k - 1], orc[k - 1]), "twin_vs_oracle": dist(twin[k - 1], orc[k - 1])}
+                  for k in shown]}), flush=True)
+
+    check_steps(gpu, stop, worst)
+    # the free trajectories from X0: the first step agrees to rounding
+    d1 = dist(gpu[0], orc[0])
+    assert d1["R"] <= 1e-12 * np.abs(orc[0]["R"]).max()
+    assert d1["X"] <= TOL * np.linalg.norm(orc[0]["X"])
+    assert d1["E"] <= TOL * abs(orc[0]["E"])
+
+
+def test_c100_trajectory_head_to_head(monkeypatch):
+    from paper_2303_00689_amd import binding
+    s, w = workload("c100")
+    st = dynamics.Settings(T_e=w["T_e"], m=w["m"], dt=w["dt"])
+    run_case(binding, monkeypatch, "c100", mixed_start(s, st), f"{N_MIX} linear-mixing steps")
+
+
+def test_c10_trajectory_from_the_ground_state(monkeypatch):
+    from paper_2303_00689_amd import binding
+    s, w = workload("c10")
+    st = dynamics.Settings(T_e=w["T_e"], m=w["m"], dt=w["dt"])
+    run_case(binding, monkeypatch, "c10", dynamics.scf(s, st, m=30), "SCF ground state")
