@@ -293,6 +293,9 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
       trajectories whose starts differ by a symmetric perturbation as large as
       the first step's split-vs-FP64 difference of X: what any perturbation of
       that size does on this trajectory.
+    kernel_at_start: at the shared start, ||Y_split - Y_fp64|| / ||W0||, the
+      split arithmetic's error in the Krylov kernel (eq. 34), beside the
+      relative residual the FP64 kernel itself leaves at rank m.
     drift: slope of E_tot (eq. 26) over the trajectory, eV/ps/atom."""
     mass = sys_.params.mass
     conv = mass / ACC
@@ -312,6 +315,7 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
         # or a guard of the handle)
         st = md_start(binding, torch, sys_, Xstart, dev)
         h.md_init(st)
+        Y_init.append(st.Y.clone())
         frc, X, E, same, rec = [], [], [], [], []
         stop = None
         for k in range(steps):
@@ -342,6 +346,14 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
         tfs = w["dt"] * np.arange(1, len(E) + 1)
         return float(np.polyfit(tfs, np.array(E), 1)[0]) * 1000.0 / sys_.n_atoms
 
+    # the Krylov kernel at the shared start: the split mode's Y against FP64's,
+    # beside the FP64 kernel's own truncation residual at the method's rank
+    Y_init = []
+    hev.fock(X0, F, True)
+    hev.fermi_dm(F, P)
+    Ytmp = torch.empty_like(F)
+    rank0, relres0 = hev.krylov_kernel(X0, P, w["m"], Ytmp)
+    nW0 = float(torch.linalg.norm(P - X0))
     fs_, Xs_, Es_, same, rs_, stop_s = run(hs, X0, evaluate=True, label="split")
     log("  split trajectory with FP64 re-evaluation done")
     f6_, X6_, E6_, _, r6_, stop_6 = run(h64, X0, label="fp64")
@@ -367,6 +379,8 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
                                  "mu_passes": [x[4] for x in rec]}
     return {
         "steps": steps,
+        "kernel_at_start": {"Y_split_vs_fp64_over_W0": float(torch.linalg.norm(Y_init[0] - Y_init[1])) / nW0,
+                            "fp64_krylov_relres": relres0, "rank": rank0, "W0_fro": nW0},
         "same_state_force_err_eV_per_A": {"max": max(same) if same else None, "per_step": same},
         "divergence": {
             "split_vs_fp64": {"force_maxabs_eV_per_A": fdiff(fs_, f6_), "X_fro": xdiff(Xs_, X6_)},
@@ -572,6 +586,8 @@ def main():
         cmp = compare_legs(binding, torch, np, sys_, w, args.prec, X0, args.compare_steps, dev)
         out["force_err_vs_fp64_eV_per_A"] = cmp["same_state_force_err_eV_per_A"]["max"]
         out["force_err_ok"] = out["force_err_vs_fp64_eV_per_A"] <= 1e-4
+        out["split_kernel_err_over_W0"] = cmp["kernel_at_start"]["Y_split_vs_fp64_over_W0"]
+        out["fp64_krylov_relres"] = cmp["kernel_at_start"]["fp64_krylov_relres"]
         out["split_vs_fp64"] = cmp
 
     if not args.no_cpu_baseline:

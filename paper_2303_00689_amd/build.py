@@ -2,12 +2,16 @@
 
 Every .hip file under csrc/ is compiled with hipcc for gfx950 and linked into
 paper_2303_00689_amd/libxlbomd.so.  Packed FP32 instructions are disabled for
-all device code (-packed-fp32-ops).
+all device code (-packed-fp32-ops).  The compiler's per-kernel resource report
+is checked: a kernel that needs per-lane scratch memory fails the build (the
+runtime reserves scratch for every wave slot of the device and every hardware
+queue, so a large per-lane size can exhaust it when many streams are used).
 """
 
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -20,7 +24,7 @@ ARCH = "gfx950"
 
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result", "-Wno-unused-value"]
+         "-Wno-unused-result", "-Wno-unused-value", "-Rpass-analysis=kernel-resource-usage"]
 
 
 def sources():
@@ -33,7 +37,26 @@ def _compile(src: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    spills = scratch_kernels(r.stderr)
+    if spills:
+        raise RuntimeError(f"kernels in {src} use per-lane scratch memory: " +
+                           ", ".join(f"{k} ({b} B/lane)" for k, b in spills))
     return obj
+
+
+def scratch_kernels(report: str):
+    """(kernel, bytes per lane) for every kernel of a kernel-resource-usage
+    report whose scratch size is not zero."""
+    out, name = [], None
+    for line in report.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            out.append((name, int(m.group(1))))
+    return out
 
 
 def build(verbose: bool = False) -> str:

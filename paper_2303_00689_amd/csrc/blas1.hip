@@ -468,38 +468,55 @@ __global__ void k_mu_newton(const double *t01, double n_occ, double beta, double
 // pivoting) and resid2 = ||sum W_i c_i - W0||^2 = c^T O c - 2 c^T rhs + ||W0||^2
 // (the last term is read from resid2[1] on entry).
 // k_rank (device, may be null): a basis that broke down at rank r >= 0 solves
-// only the leading r x r system (the remaining coefficients are zero)
-__global__ void k_krylov_solve(int k, const double *O, const double *rhs, double *coef, double *resid2,
-                               const double *k_rank) {
-  if (threadIdx.x != 0) return;
+// only the leading r x r system (the remaining coefficients are zero).
+// One wavefront; the augmented matrix lives in LDS (no per-lane scratch).
+// Lane 0 picks each pivot and does the back substitution; in each
+// elimination, lane r updates row r, so every entry sees the operations of a
+// sequential elimination in the same order.
+__global__ __launch_bounds__(64) void k_krylov_solve(int k, const double *O, const double *rhs, double *coef,
+                                                     double *resid2, const double *k_rank) {
+  __shared__ double a[32][33];
+  __shared__ double x[32];
+  __shared__ int piv_s, sing_s;
+  const int t = threadIdx.x;
   const int kfull = k;
   if (k_rank && *k_rank >= 0.0 && (int)*k_rank < k) k = (int)*k_rank;
-  double a[32][33];
-  for (int i = 0; i < k; ++i) {
-    for (int j = 0; j < k; ++j) a[i][j] = O[i * 32 + j];
-    a[i][k] = rhs[i];
+  for (int idx = t; idx < k * (k + 1); idx += 64) {
+    const int i = idx / (k + 1), j = idx - i * (k + 1);
+    a[i][j] = j < k ? O[i * 32 + j] : rhs[i];
   }
-  int singular = 0;
+  if (t == 0) sing_s = 0;
+  __syncthreads();
   for (int c = 0; c < k; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < k; ++r)
-      if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+    if (t == 0) {
+      int piv = c;
+      for (int r = c + 1; r < k; ++r)
+        if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+      piv_s = piv;
+    }
+    __syncthreads();
+    const int piv = piv_s;
     if (piv != c)
-      for (int j = 0; j <= k; ++j) {
-        const double t = a[c][j];
+      for (int j = t; j <= k; j += 64) {
+        const double tmp = a[c][j];
         a[c][j] = a[piv][j];
-        a[piv][j] = t;
+        a[piv][j] = tmp;
       }
+    __syncthreads();
+    // every lane reads the same pivot, so the exit is uniform
     if (a[c][c] == 0.0) {
-      singular = 1;
+      if (t == 0) sing_s = 1;
       break;
     }
-    for (int r = c + 1; r < k; ++r) {
-      const double f = a[r][c] / a[c][c];
-      for (int j = c; j <= k; ++j) a[r][j] -= f * a[c][j];
+    if (t > c && t < k) {
+      const double f = a[t][c] / a[c][c];
+      for (int j = c; j <= k; ++j) a[t][j] -= f * a[c][j];
     }
+    __syncthreads();
   }
-  double x[32];
+  __syncthreads();
+  if (t != 0) return;
+  const int singular = sing_s;
   for (int i = k - 1; i >= 0; --i) {
     double s = singular ? 0.0 : a[i][k];
     if (!singular) {

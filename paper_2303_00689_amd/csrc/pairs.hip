@@ -290,11 +290,18 @@ __global__ __launch_bounds__(256) void k_fock_diag(PairSys ps, int n, const doub
 #pragma unroll
     for (int b = 0; b < 4; ++b) Pd[a][b] = P ? P[(size_t)(4 * A + a) * n + 4 * A + b] : 0.0;
   onecenter_G(ps.onecenter + 5 * A, Pd, G1);
-  double c = 0.0;
+  // (lo, hi) differ by lane: pick by compare-and-select with constant
+  // indices, so that G1 and coul stay in registers
+  double c = 0.0, g = 0.0;
 #pragma unroll
   for (int r = 0; r < 10; ++r)
     if (PM[r] == lo && PN[r] == hi) c = coul[r];
-  double v = G1[lo][hi] + c;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b)
+      if (a == lo && b == hi) g = G1[a][b];
+  double v = g + c;
   if (include_h && i == j) v += (i == 0) ? ps.eps_s : ps.eps_p;
   F[(size_t)(4 * A + i) * n + 4 * A + j] = v;
 }
