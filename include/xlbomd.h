@@ -271,8 +271,12 @@ xlbomd_status xlbomd_step_langevin(xlbomd_handle h, xlbomd_md_state *st, int n_s
 /* Steps of an ensemble of independent trajectories (systems of uneven
  * sizes): member i advances h[i] with st[i] by n_steps exactly as
  * xlbomd_step does, and the members run concurrently, each from a host
- * thread of its own (at most 16 threads) on its handle's stream.  Create the
- * handles on distinct streams so that their GPU work overlaps.
+ * thread of its own (at most 16 threads, taking members in index order) on
+ * its handle's stream.  Create the
+ * handles on distinct streams so that their GPU work overlaps.  Streams share
+ * the process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 by default), and
+ * kernels on one queue run in order: set it to 16 before the first HIP call
+ * so that the 16 members in flight each have one.
  *   h, st   host arrays of count distinct handles and their states
  *   rep     host, count x n_steps reports, member-major (nullable)
  * Returns XLBOMD_E_ARG for a repeated handle; otherwise the status of the
@@ -340,6 +344,36 @@ xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
  * product runs), [8] Fock build and [9] forces (work = algorithmic HBM bytes:
  * 220 per atom pair plus 16 n^2). */
 xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
+
+/* GEMM tile table (process-wide): which kernel family runs an n x n product of
+ * the Fermi and response chains.  Families: 1 = small tiles (FP64 64 x 64;
+ * split 128 x 128), 2 = large tiles (FP64 128 x 128, and 128 x 64 over the
+ * upper triangle for symmetric outputs, n % 16 == 0, 128 <= n <= 23170;
+ * BF16x3 / BF16x6 224 x 224, and 160 x 160 for symmetric outputs,
+ * n % 32 == 0, 128 <= n <= 32767), 0 = the library's built-in rule.
+ *   rows    HOST, count x 4 ints {prec, sym, n_max, family}: prec is the
+ *           arithmetic of the product, numbered as the precision enum's first
+ *           four values: 0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3; sym 0 full / 1
+ *           symmetric output; n_max >= 1
+ *   count   0..XLBOMD_TILE_TABLE_MAX; 0 clears the table
+ * A product of order n uses the family of the row with the smallest n_max >= n
+ * among those of its prec and sym (the first given, on ties), when that family
+ * can run n; otherwise the built-in rule.  The rows are copied.  In FP64 the
+ * families give the same bits on and above the diagonal (a symmetric
+ * output's lower triangle is computed by one and mirrored by the other); in
+ * split precision each stays within the split arithmetic's error budget.  Set the table before stepping: changing it while
+ * other calls run leaves their products to either table.  Returns
+ * XLBOMD_E_ARG (table unchanged) for a malformed row or count. */
+#define XLBOMD_TILE_TABLE_MAX 256
+xlbomd_status xlbomd_set_tile_table(const int *rows, int count);
+
+/* Autotuning: the average time, in microseconds, of reps products C = A B of
+ * order n in arithmetic prec (0..3 as above) with output kind sym, run by
+ * kernel family `family` (1 or 2) on `stream` (hipStream_t, may be null),
+ * after one warm-up product.  Allocates and frees its own operands (for
+ * offline tuning, not for a stepping loop).  Returns XLBOMD_E_ARG if the
+ * family cannot run n, XLBOMD_E_HIP if an allocation or launch fails. */
+xlbomd_status xlbomd_time_gemm(int n, int prec, int sym, int family, int reps, void *stream, double *us);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,78 @@
+"""GEMM tile autotuner: times both kernel families of the Fermi and response
+chains over a grid of orders, per arithmetic and output kind, and writes the
+tile table the binding installs with the library (xlbomd_set_tile_table).
+
+    python -m paper_2303_00689_amd.autotune [--out PATH] [--reps K]
+
+For each (precision, output kind) and each order n of the grid, both families
+are timed when both can run n (FP64 large tiles need n % 16 == 0, split large
+tiles n % 32 == 0, both n >= 128; FP16x3 has one family), and the faster one
+is kept; runs of equal choices merge into one row covering (previous n, n].
+Orders between grid points take the next grid point's row; orders a row's
+family cannot run, and orders past the grid, take the library's built-in rule.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_2303_00689_amd import binding  # noqa: E402
+
+PRECS = {0: "fp64", 1: "bf16x3", 2: "bf16x6"}
+# the ensemble's orbital counts (4 x 20..300 atoms) in steps of 32, then the
+# larger single systems up to 4096
+GRID = list(range(128, 1281, 32)) + [1536, 2048, 2560, 3072, 3360, 4096]
+
+
+def tune(reps: int, grid=GRID, log=print):
+    rows, timings = [], []
+    for prec, pname in PRECS.items():
+        for sym in (0, 1):
+            choice = []
+            for n in grid:
+                t_small = binding.time_gemm(n, prec, sym, binding.GEMM_SMALL, reps)
+                t_large = binding.time_gemm(n, prec, sym, binding.GEMM_LARGE, reps)
+                fam = binding.GEMM_SMALL if t_large is None or t_small <= t_large else binding.GEMM_LARGE
+                choice.append((n, fam))
+                timings.append({"prec": pname, "sym": sym, "n": n, "small_us": t_small, "large_us": t_large,
+                                "family": fam})
+            log(f"{pname} sym={sym}: " + " ".join(f"{n}:{'L' if f == 2 else 's'}" for n, f in choice))
+            # merge runs of one family into rows covering (previous n_max, n_max]
+            for k, (n, fam) in enumerate(choice):
+                if k + 1 < len(choice) and choice[k + 1][1] == fam:
+                    continue
+                rows.append([prec, sym, n, fam])
+    return rows, timings
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--out", default=binding.TILE_TABLE_PATH)
+    ap.add_argument("--reps", type=int, default=20)
+    args = ap.parse_args()
+    os.environ["XLBOMD_TILE_TABLE"] = "none"   # time the families, not an older table
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("autotune needs a GPU")
+    t = time.perf_counter()
+    rows, timings = tune(args.reps)
+    if len(rows) > binding.TILE_TABLE_MAX:
+        raise SystemExit(f"{len(rows)} rows exceed the table's {binding.TILE_TABLE_MAX}")
+    out = {"device": torch.cuda.get_device_name(0), "reps": args.reps,
+           "seconds": time.perf_counter() - t,
+           "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6), sym, n_max, family (1 small, 2 large)]",
+           "rows": rows, "timings": timings}
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"wrote {len(rows)} rows to {args.out} ({out['seconds']:.1f} s)")
+
+
+if __name__ == "__main__":
+    main()

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import json
 import os
 
 import numpy as np
@@ -29,7 +30,15 @@ SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb
            "xlbomd_dm_response", "xlbomd_krylov_kernel", "xlbomd_forces", "xlbomd_integrate",
            "xlbomd_step", "xlbomd_step_langevin", "xlbomd_ensemble_step", "xlbomd_md_init", "xlbomd_scf",
            "xlbomd_matmul",
-           "xlbomd_profile", "xlbomd_profile_read", "xlbomd_spectral_bounds_noalloc"]
+           "xlbomd_profile", "xlbomd_profile_read", "xlbomd_spectral_bounds_noalloc",
+           "xlbomd_set_tile_table", "xlbomd_time_gemm"]
+
+# GEMM kernel families of the tile table (xlbomd_set_tile_table)
+GEMM_AUTO, GEMM_SMALL, GEMM_LARGE = 0, 1, 2
+TILE_TABLE_MAX = 256
+# the tile table the autotuner wrote (autotune.py), loaded with the library;
+# XLBOMD_TILE_TABLE names another file, or "none" for the built-in rule
+TILE_TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_table.json")
 
 # largest n of xlbomd_spectral_bounds_noalloc (XLBOMD_SPECTRAL_BOUNDS_NOALLOC_MAX_N)
 SPECTRAL_BOUNDS_NOALLOC_MAX_N = 16384
@@ -112,11 +121,53 @@ def load():
     lib.xlbomd_profile.argtypes = [vp, i]
     lib.xlbomd_profile_read.argtypes = [vp, pd]
     lib.xlbomd_spectral_bounds_noalloc.argtypes = [vp, i, vp, pd]
+    lib.xlbomd_set_tile_table.argtypes = [pi, i]
+    lib.xlbomd_time_gemm.argtypes = [i, i, i, i, i, vp, pd]
     for name in SYMBOLS:
         if name not in ("xlbomd_last_error", "xlbomd_n_orb"):
             getattr(lib, name).restype = i
     _lib = lib
+    install_tile_table()
     return lib
+
+
+def install_tile_table():
+    """Install the default tile table: the file XLBOMD_TILE_TABLE names, else
+    the autotuner's tile_table.json beside this module; none (the built-in
+    rule) if XLBOMD_TILE_TABLE is "none" or the file is absent."""
+    path = os.environ.get("XLBOMD_TILE_TABLE", TILE_TABLE_PATH)
+    rows = []
+    if path != "none" and os.path.exists(path):
+        with open(path) as f:
+            rows = json.load(f)["rows"]
+    set_tile_table(rows)
+
+
+def set_tile_table(rows):
+    """Install the GEMM tile table: rows of (prec, sym, n_max, family), prec
+    0..3 = FP64, BF16x3, BF16x6, FP16x3 (xlbomd_set_tile_table); [] clears it."""
+    lib = load()
+    flat = [int(v) for r in rows for v in r]
+    if len(flat) != 4 * len(rows):
+        raise XLBOMDError("tile table rows must have 4 entries")
+    arr = (C.c_int * max(len(flat), 1))(*flat)
+    st = lib.xlbomd_set_tile_table(arr, len(rows))
+    if st != 0:
+        raise XLBOMDError(f"set_tile_table: {STATUS.get(st, st)}", st)
+
+
+def time_gemm(n, prec, sym, family, reps=5, stream=None):
+    """Microseconds per n x n product of kernel family `family` (xlbomd_time_gemm),
+    or None if the family cannot run n."""
+    lib = load()
+    us = C.c_double(0.0)
+    st = lib.xlbomd_time_gemm(int(n), int(prec), int(sym), int(family), int(reps), C.c_void_p(stream or 0),
+                              C.byref(us))
+    if st == -1:
+        return None
+    if st != 0:
+        raise XLBOMDError(f"time_gemm: {STATUS.get(st, st)}", st)
+    return us.value
 
 
 class XLBOMDError(RuntimeError):

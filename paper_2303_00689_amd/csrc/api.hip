@@ -2,6 +2,7 @@
 // hot path.  Every arithmetic step runs in the kernels of gemm_*.hip,
 // blas1.hip and pairs.hip; this file only sequences them, keeps the chain
 // cache and moves a few scalars between host and device.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -1559,8 +1560,9 @@ xlbomd_status xlbomd_ensemble_step(xlbomd_handle *h, xlbomd_md_state *st, int co
     for (int j = 0; j < i; ++j)
       if (h[j] == h[i]) return XLBOMD_E_ARG;  // a handle's workspace serves one member
   }
-  // members are taken in index order by up to 16 host threads; each runs
-  // xlbomd_step on its own handle (and so its own stream and workspace)
+  // members are taken in index order by up to 16 host threads (the caller
+  // chooses the order); each runs xlbomd_step on its own handle (and so its
+  // own stream and workspace), so a member's result does not depend on it
   std::vector<xlbomd_status> status(count, XLBOMD_OK);
   std::atomic<int> next(0);
   auto worker = [&]() {

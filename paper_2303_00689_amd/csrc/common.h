@@ -28,7 +28,20 @@ struct GemmArgs {
   void *out;
   double alpha, beta1, beta2, gamma;
   int sym;
+  int family;              // GEMM_AUTO: the tile table, else the built-in rule
 };
+// Kernel families of an n x n product.  FP64: GEMM_SMALL = 64 x 64 tiles,
+// GEMM_LARGE = 128 x 128 (128 x 64 over the upper triangle for symmetric
+// outputs; n % 16 == 0, n <= 23170).  Split: GEMM_SMALL = 128 x 128 tiles,
+// GEMM_LARGE = 224 x 224 full / 160 x 160 symmetric (BF16x3 and BF16x6 only;
+// n % 32 == 0, n <= 32767).  A family that cannot run n falls back to the
+// built-in rule.
+enum { GEMM_AUTO = 0, GEMM_SMALL = 1, GEMM_LARGE = 2 };
+// The tile table's family for a product of order n (prec 0 = FP64, 1..3 as
+// below), or GEMM_AUTO when no row matches.
+int table_family(int prec, int sym, int n);
+// Whether family fam can run an n x n product in precision prec.
+bool family_runs(int prec, int fam, int n);
 void gemm_f64(const GemmArgs &a, hipStream_t s);
 // Split-precision GEMM on FP32 storage (prec: 1 = BF16x3, 2 = BF16x6, 3 = FP16x3).
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s);

@@ -367,8 +367,12 @@ __global__ __launch_bounds__(256, 3) void k_gemm_f64_half(GemmArgs p, int TI, in
 }  // namespace
 
 void gemm_f64(const GemmArgs &a, hipStream_t s) {
-  // 128-row tiles from n = 1024 on (n % 16 == 0; the buffer range limits n to 23170)
-  if (a.n % 16 == 0 && a.n >= 1024 && a.n <= 23170) {
+  // the requested family, else the tile table's, else 128-row tiles from
+  // n = 1024 on (n % 16 == 0; the buffer range limits n to 23170)
+  int fam = a.family != GEMM_AUTO ? a.family : table_family(0, a.sym, a.n);
+  if (!family_runs(0, fam, a.n)) fam = GEMM_AUTO;
+  const bool large = fam == GEMM_AUTO ? (a.n % 16 == 0 && a.n >= 1024 && a.n <= 23170) : fam == GEMM_LARGE;
+  if (large) {
     const int TI = (a.n + FT - 1) / FT;
     if (a.sym) {
       // symmetric outputs: 128 x 64 tiles, twice as many for an even load over the CUs

@@ -798,11 +798,14 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   // n % 32 == 0 and pay once they give at least 3/4 of a workgroup per
   // compute unit (192 of the 256); below that the 128-row tiles fill the chip
   // better
+  // the requested family, else the tile table's, else the rule above
   const int edge = a.sym ? 160 : 224;
   const int T = (a.n + edge - 1) / edge;
   const int blocks = tile_count(T, a.sym);
-  const bool big = (a.n % 32 == 0) && a.n <= 32767 && blocks >= 192;
-  if (big && (prec == 1 || prec == 2)) {
+  int fam = a.family != GEMM_AUTO ? a.family : table_family(prec, a.sym, a.n);
+  if (!family_runs(prec, fam, a.n)) fam = GEMM_AUTO;
+  const bool big = fam == GEMM_AUTO ? (family_runs(prec, GEMM_LARGE, a.n) && blocks >= 192) : fam == GEMM_LARGE;
+  if (big) {
     if (a.sym) {
       if (prec == 2)
         hipLaunchKernelGGL((k_gemm_split_big<1, 5>), dim3(blocks), dim3(256), 0, s, a, T);
