@@ -245,19 +245,21 @@ class Snapshot:
         state.head, state.mu, state.mu_prev = self.head, self.mu, self.mu_prev
 
 
-def timed_reset_leg(torch, h, state, snap, steps, warmup):
+def timed_reset_leg(torch, h, state, snap, steps, warmup, report=False):
     """Steps/s with every step restarting from the prepared state (restore
-    inside the timed region), and the per-class profile of the timed steps."""
+    inside the timed region), and the per-class profile of the timed steps.
+    report=True times steps that also fill the per-step report (energies,
+    with the entropy from the eigenvalues of F)."""
     for k in range(warmup):
         snap.restore_step(state)
-        h.step(state, 1, report=False)
+        h.step(state, 1, report=report)
         log(f"  warmup step {k + 1} done")
     h.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         snap.restore_step(state)
-        h.step(state, 1, report=False)
+        h.step(state, 1, report=report)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = h.profile_read()
@@ -460,6 +462,8 @@ def main():
     ap.add_argument("--workload", default="c840")
     ap.add_argument("--fp64-steps", type=int, default=10, help="timed steps of the FP64 leg (0: skip)")
     ap.add_argument("--free-steps", type=int, default=20, help="steps of the free NVE trajectory leg (0: skip)")
+    ap.add_argument("--report-steps", type=int, default=5,
+                    help="timed steps with the per-step report on, entropy included (0: skip)")
     ap.add_argument("--compare-steps", type=int, default=20,
                     help="MD steps of the untimed split-vs-FP64 accuracy legs (0: skip)")
     ap.add_argument("--init-mix", type=int, default=300, help="linear-mixing steps of the initial SCF")
@@ -571,6 +575,13 @@ def main():
                           "frac": fock_gbs / HBM_PEAK_GBS, "traffic": kernel_traffic("fock"),
                           "launches": fk["launches"], "avg_launch_us": 1e3 * fk["ms"] / max(fk["launches"], 1)},
     }
+
+    # ---- the same steps with the per-step report on (entropy eigensolve)
+    if args.report_steps:
+        el_r, _ = timed_reset_leg(torch, h, state, snap, args.report_steps, 1, report=True)
+        out["report_on"] = {"steps_per_s": args.report_steps / el_r, "ms_per_step": 1e3 * el_r / args.report_steps,
+                            "steps": args.report_steps, "warmup": 1}
+        log("report-on steps done")
 
     # ---- free NVE trajectory of the same mode from the same state
     if args.free_steps:
