@@ -94,7 +94,14 @@ def loewner_matrix(eps: np.ndarray, f: np.ndarray, beta: float) -> np.ndarray:
 
 def response(F: np.ndarray, F1: np.ndarray, n_elec: float, beta: float, dm: dict | None = None) -> np.ndarray:
     """Spin-summed canonical response P1 = 2 dD0/dlambda of D0[F + lambda F1]
-    (eq. 36), Tr P1 = 0."""
+    (eq. 36), Tr P1 = 0.
+
+    For a symmetric F1 the response is symmetric; the result is returned as
+    D1 + D1^T, so that rounding leaves it exactly symmetric.  (An
+    antisymmetric residue of rounding size would otherwise be amplified by the
+    Jacobian's large eigenvalues on antisymmetric matrices when a Krylov basis
+    (eq. 34) is built from repeated responses, and the basis would leave the
+    symmetric matrices the method works on.)"""
     if dm is None:
         dm = density_matrix(F, n_elec, beta)
     C, eps, f = dm["C"], dm["eps"], dm["f"]
@@ -104,4 +111,4 @@ def response(F: np.ndarray, F1: np.ndarray, n_elec: float, beta: float, dm: dict
     sw = np.sum(w)
     if sw > 0.0:
         D1 = D1 - (np.trace(D1) / sw) * ((C * w) @ C.T)
-    return 2.0 * D1
+    return D1 + D1.T

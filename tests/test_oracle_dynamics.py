@@ -70,6 +70,24 @@ def _assembled_jacobian(sys_, X, beta):
     return P0, jac, J, coords, mat
 
 
+def test_krylov_breaks_down_at_the_grade_of_the_symmetric_space():
+    # a 1-atom system: its symmetric 4 x 4 matrices span 10 dimensions, so a
+    # rank-16 request must end at rank <= 10 (breakdown), where Y solves
+    # J Y = W0 on that space exactly; the basis stays symmetric throughout
+    # (W0 = P0 - X carries the rounding asymmetry of P0, which the symmetric
+    # responses pass on without growth)
+    sys_ = carbon_cluster(1, 21)
+    beta = density.beta_of(3000.0)
+    X = _start_density(sys_, np.random.default_rng(41))
+    P0, jac, J, coords, mat = _assembled_jacobian(sys_, X, beta)
+    Yref = mat(np.linalg.solve(J, coords(P0 - X)))
+    Y, rank, rel = krylov.krylov_kernel(X, P0, jac, 16)
+    assert rank <= 10, rank
+    assert rel < 1e-12
+    assert np.abs(Y - Y.T).max() <= 1e-14 * np.abs(Y).max()
+    np.testing.assert_allclose(Y, Yref, atol=1e-10 * np.abs(Yref).max())
+
+
 def test_krylov_early_stop_is_the_first_rank_below_tol():
     # Eq. 34 over span{V_1..V_k} = span{W0, J W0, .., J^(k-1) W0} with
     # M = (W^T W)^-1 is the least-squares solution of J Y = W0 over that
