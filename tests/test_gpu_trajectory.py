@@ -12,7 +12,9 @@ trajectory, not by either of them.  The test therefore checks:
 * every step: the oracle's step (eqs. 27-30, 35) from the GPU's own state
   before it reproduces the GPU's state after it -- positions, the new X,
   accelerations, the Krylov kernel Y and the shadow energy E_tot -- to the
-  parity bars of a single MD step;
+  parity bars of a single MD step (E_tot = KE + U relative to the larger of
+  |E_tot|, KE and |U|: in a runaway E_tot passes through zero, and the
+  rounding of a sum scales with its largest part);
 * the first step of the two free trajectories from X0 agrees to rounding;
 * the drift of E_tot (eq. 26's constant of motion) of both trajectories,
   and their divergence next to an oracle twin started from X0 plus a 1e-12
@@ -147,12 +149,13 @@ def step_by_step(binding, s, w, st, X0, spy, steps):
             amp = spy.amplification()
             err = dict(R=rel(state.R.cpu().numpy(), o.R), X=rel(state.x_current().cpu().numpy(), o.Xhist[0]),
                        A=rel(state.A.cpu().numpy(), o.A), Y=rel(state.Y.cpu().numpy(), o.Y),
-                       E=abs(rep["E_tot"] - orep["E_tot"]) / abs(orep["E_tot"]))
+                       E=abs(rep["E_tot"] - orep["E_tot"]) / max(abs(orep["E_tot"]), orep["KE"], abs(orep["U"])))
             err["Y_over_amp"] = err["Y"] / amp
             err["Y_bar"] = max(TOL, 1e-10 * amp)
             for q in worst:
                 if err[q] > worst[q][0]:
                     worst[q] = (err[q], k + 1)
+            err["E_parts"] = (orep["E_tot"], orep["KE"], orep["U"], rep["E_tot"])
             gpu.append(dict(R=state.R.cpu().numpy(), X=state.x_current().cpu().numpy(), E=rep["E_tot"],
                             T=rep["T_ion"], W0=rep["W0"], relres=rep["relres"], amp=amp, err=err))
     finally:
@@ -184,6 +187,9 @@ def run_case(binding, monkeypatch, name, X0, note):
     spy = KrylovSpy(monkeypatch)
     gpu, stop, worst = step_by_step(binding, s, w, st, X0, spy, STEPS)
     print(f"{name}: GPU steps {len(gpu)}, stop {stop}; worst one-step errors {worst}", flush=True)
+    if gpu and worst["E"][1] > 0:
+        print(f"{name}: at the worst E_tot step, oracle E_tot, KE, U and GPU E_tot: "
+              f"{gpu[worst['E'][1] - 1]['err']['E_parts']}", flush=True)
 
     orc = oracle_run(s, st, X0)
     rng = np.random.default_rng(31)
