@@ -65,9 +65,10 @@ enum Slot {
   S_TOTAL = 1352
 };
 
-__global__ void k_canon(const double *trR, const double *trM, double *out) {
+// s = -scale tr / Tr M, the chemical-potential term of the canonical response
+__global__ void k_canon(const double *tr, const double *trM, double scale, double *out) {
   if (threadIdx.x) return;
-  *out = (*trM > 0.0) ? -(*trR) / (*trM) : 0.0;
+  *out = (*trM > 0.0) ? -scale * (*tr) / (*trM) : 0.0;
 }
 
 // first-order chemical-potential correction of the stored chain result:
@@ -572,14 +573,18 @@ xlbomd_status run_chain(xlbomd_ctx *c, const double *F, double mu, double lo, do
       mm(c, Si, Si, E, -16.0 * b, 1, Si, -(4.0 * a + 8.0 * b), nullptr, 0.0, 1.0 - a - b);
       // Z1 = Z0 (I + E0), Z0 = (a + b) I + 4 b S
       mm(c, Si, E, Za, 4.0 * b, 1, Si, 4.0 * b, E, a + b, a + b);
-      // steps of order 2 (Z + Z E) where that reaches eps, else of order 3
-      // (Z + Z E' with E' = E E + E: three products for e^3)
+      // steps of order 2 (Z + Z E) where that reaches the level's target,
+      // else of order 3 (Z + Z E' with E' = E E + E: three products for e^3).
+      // The later levels amplify this level's error by up to 2^(L-1-i) for
+      // states near mu; eps is set for up to five of them, and deeper chains
+      // (cold systems) tighten the target of their early levels to match.
+      const double eps_i = eps * std::ldexp(1.0, std::min(0, 5 - (L - 1 - i)));
       void *E2 = c->w[5];
       double el = e0 * e0;
-      for (int it = 0; it < 8 && el > eps; ++it) {
+      for (int it = 0; it < 8 && el > eps_i; ++it) {
         mm(c, Si, Za, E, -4.0, 1, Za, -1.0, nullptr, 0.0, 1.0);   // E = I - T Z
         const void *Ec = E;
-        if (el * el > eps) {
+        if (el * el > eps_i) {
           mm(c, E, E, E2, 1.0, 1, E, 1.0);                        // E' = E E + E
           Ec = E2;
           el = el * el * el;
@@ -893,9 +898,23 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1, const double
   // the z-parts of all levels and the chemical-potential shift: W K W
   mr(c, Wr, Y1, G, 1.0, 0);
   mr(c, Wr, G, H, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
-  // canonical projection: R - (Tr R / Tr M) M
-  trace(n, H, c->dscal + S_TRR, i32, c->red, s);
-  hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM,
+  // canonical projection: R - (Tr R / Tr M) M.  An FP64 response takes Tr R
+  // from the exact trace of the fixed-mu derivative, Tr f'(F)[F1] =
+  // -beta <M, F1> = 2^(L+1) <M, V1> (V1 = sc F1): a product of two accurate
+  // matrices, where the trace of the computed R sums n rounded diagonal
+  // entries, which the division by Tr M (small when few states lie near mu)
+  // amplifies.  A split response keeps the trace of its own R: its error
+  // along M (the FP32 chain's own chemical potential) then cancels, and
+  // Tr P1 = 0 holds to rounding.
+  double tr_scale = 1.0;
+  if (c->prec_rs == XLBOMD_FP64) {
+    const void *a[1] = {Mr}, *b[1] = {V1};
+    dots((int)c->n2, 1, a, b, c->dscal + S_TRR, i32, c->red, s);
+    tr_scale = std::ldexp(1.0, L + 1);
+  } else {
+    trace(n, H, c->dscal + S_TRR, i32, c->red, s);
+  }
+  hipLaunchKernelGGL(k_canon, dim3(1), dim3(64), 0, s, c->dscal + S_TRR, c->dscal + S_TRM, tr_scale,
                      c->dscal + S_CAN);
   // P1 = 2 (R + s M), s = -Tr R / Tr M, straight into the caller's FP64 buffer
   canon_out((int)c->n2, H, Mr, c->dscal + S_CAN, sub, P1, i32, s);

@@ -187,6 +187,51 @@ def test_hot_cluster_density_and_response(lib, T_e):
         case.h.close()
 
 
+@pytest.mark.parametrize("name,T_e", [("c10", 300.0), ("c10", 1000.0), ("c100", 500.0)])
+def test_cold_cluster_density_response_and_kernel(lib, name, T_e):
+    # Toward the T_e -> 0 limit: the chain needs more doubling levels (beta
+    # max|eps - mu| / 2 in the hundreds), D is nearly idempotent and mu sits
+    # in a gap where the electron count fixes it only loosely: to
+    # dmu = 1e-11 N / (dN/dmu), dN/dmu = 2 beta sum f (1 - f), the bound the
+    # mu checks above use.  D, its response and the Krylov kernel move with
+    # mu by at most beta dmu relative, so they are held to 1e-10 + beta dmu
+    # (at 500 K for 100 atoms 6e-9; the errors found: a mu offset of 3e-11 eV,
+    # D 8e-11 along D (I - D), the response 5e-10).
+    case = Case(lib, name, T_e=T_e)
+    try:
+        s = case.sys
+        F = case.t(case.F)
+        P = torch.empty_like(F)
+        mu, _ = case.h.fermi_dm(F, P)
+        Pg = case.np(P)
+        f = case.dm["f"]
+        dmu = 1e-11 * s.n_elec / (2.0 * case.beta * np.sum(f * (1.0 - f)))
+        bar = TOL + case.beta * dmu
+        assert abs(mu - case.dm["mu"]) <= dmu + 1e-12
+        print(f"{name} at {T_e:.0f} K: sum f(1-f) = {np.sum(f * (1 - f)):.2e}, mu offset {mu - case.dm['mu']:.1e} eV "
+              f"(bound {dmu:.1e}), bar {bar:.1e}; P error {_rel(Pg, case.dm['P']):.1e}")
+        assert _rel(Pg, case.dm["P"]) <= bar
+        V = case.rng.standard_normal((s.n_orb, s.n_orb))
+        V = V + V.T
+        F1 = model.two_electron(V, s.R, s.onecenter, s.noise, s.params)
+        P1 = torch.empty_like(F)
+        case.h.dm_response(case.t(F1), P1)
+        ref = density.response(case.F, F1, s.n_elec, case.beta, case.dm)
+        e1 = _rel(case.np(P1), ref)
+        m = case.w["m"]
+        Y = torch.empty_like(F)
+        rank, rel = case.h.krylov_kernel(case.t(case.X), P, m, Y)
+        Yref, rref, relref = krylov.krylov_kernel(case.X, case.dm["P"], _oracle_jac(case), m)
+        eY = _rel(case.np(Y), Yref)
+        print(f"  response error {e1:.1e}, Krylov Y error {eY:.1e}, rank {rank} / {rref}")
+        assert e1 <= bar
+        assert rank == rref
+        assert eY <= bar
+        assert rel == pytest.approx(relref, rel=1e-9 + bar, abs=1e-12)
+    finally:
+        case.h.close()
+
+
 def _oracle_jac(case):
     s = case.sys
 
