@@ -245,6 +245,30 @@ class Snapshot:
         state.head, state.mu, state.mu_prev = self.head, self.mu, self.mu_prev
 
 
+class ReportLog:
+    """--reports-jsonl: the per-step reports (xlbomd_report) of the untimed
+    trajectories, one JSON object per step: the leg, its precision, the step
+    number (from 1) and the report's fields, the status by name."""
+
+    def __init__(self, path, binding, workload):
+        self.f = open(path, "w") if path else None
+        self.binding, self.workload, self.lines = binding, workload, 0
+
+    def write(self, leg, prec, step, rep):
+        if self.f is None:
+            return
+        rec = {"workload": self.workload, "leg": leg, "precision": prec, "step": step}
+        rec.update({k: v for k, v in rep.items() if k != "status"})
+        rec["status"] = self.binding.STATUS.get(rep["status"], rep["status"])
+        self.f.write(json.dumps(rec) + "\n")
+        self.lines += 1
+
+    def close(self):
+        if self.f is not None:
+            self.f.close()
+            log(f"wrote {self.lines} step reports")
+
+
 def timed_reset_leg(torch, h, state, snap, steps, warmup, report=False):
     """Steps/s with every step restarting from the prepared state (restore
     inside the timed region), and the per-class profile of the timed steps.
@@ -290,7 +314,7 @@ def md_start(binding, torch, sys_, X0, dev):
                            head=0, mu=float("nan"))
 
 
-def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
+def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev, reports=None):
     """Untimed accuracy of the split mode against FP64 over `steps` MD steps.
 
     same_state: along the split trajectory, the forces the split step used
@@ -305,7 +329,8 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
     kernel_at_start: at the shared start, ||Y_split - Y_fp64|| / ||W0||, the
       split arithmetic's error in the Krylov kernel (eq. 34), beside the
       relative residual the FP64 kernel itself leaves at rank m.
-    drift: slope of E_tot (eq. 26) over the trajectory, eV/ps/atom."""
+    drift: slope of E_tot (eq. 26) over the trajectory, eV/ps/atom.
+    reports: a ReportLog that receives every step report of the three runs."""
     mass = sys_.params.mass
     conv = mass / ACC
     hs = binding.handle_for(sys_, w, prec=prec)
@@ -329,6 +354,8 @@ def compare_legs(binding, torch, np, sys_, w, prec, X0, steps, dev):
         stop = None
         for k in range(steps):
             status, reps = h.step(st, 1, report=True, check=False)
+            if reports is not None:
+                reports.write(label, h.prec, k + 1, reps[0])
             if status != 0:
                 stop = {"step": k + 1, "status": binding.STATUS.get(status, status)}
                 break
@@ -439,7 +466,9 @@ def run_study_lowgap(args, binding, torch, np, dev):
         h.close()
         timed[prec] = {"steps_per_s": 5 / el, "ms_per_step": 1e3 * el / 5}
         log(f"  timed {prec}: {5 / el:.2f} steps/s")
-    cmp = compare_legs(binding, torch, np, sys_, w, args.study_prec, X0, args.study_steps, dev)
+    reports = ReportLog(args.reports_jsonl, binding, "c840_lowgap")
+    cmp = compare_legs(binding, torch, np, sys_, w, args.study_prec, X0, args.study_steps, dev, reports)
+    reports.close()
     fe = cmp["same_state_force_err_eV_per_A"]["max"]
     print(json.dumps({
         "study": "c840_lowgap",
@@ -483,6 +512,9 @@ def main():
                          "same start, with drift and force error; prints one JSON line of its own")
     ap.add_argument("--study-steps", type=int, default=200)
     ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
+    ap.add_argument("--reports-jsonl", default="", metavar="PATH",
+                    help="write every per-step report of the untimed trajectories (free NVE leg, split-vs-FP64 "
+                         "legs, the study's) to PATH, one JSON object per step")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration)")
     args = ap.parse_args()
@@ -521,6 +553,7 @@ def main():
         return
     sys_, w = workload(args.workload)
     n = sys_.n_orb
+    reports = ReportLog(args.reports_jsonl, binding, args.workload)
 
     # ---- initial state (untimed): xlbomd_scf from the uniform density.  The
     # seeded cluster's SCF is stiff (it stalls near 0.3 even with rank-30
@@ -586,6 +619,8 @@ def main():
     # ---- free NVE trajectory of the same mode from the same state
     if args.free_steps:
         el, reps = free_leg(binding, torch, h, snap, args.free_steps)
+        for k, r in enumerate(reps):
+            reports.write("free_trajectory", args.prec, k + 1, r)
         out["free_trajectory"] = {"steps_per_s": args.free_steps / el, "ms_per_step": 1e3 * el / args.free_steps,
                                   "steps": args.free_steps,
                                   "levels": [r["levels"] for r in reps], "mu_passes": [r["mu_passes"] for r in reps],
@@ -607,13 +642,14 @@ def main():
 
     # ---- untimed accuracy of the split mode against FP64
     if args.compare_steps and args.prec != "fp64":
-        cmp = compare_legs(binding, torch, np, sys_, w, args.prec, X0, args.compare_steps, dev)
+        cmp = compare_legs(binding, torch, np, sys_, w, args.prec, X0, args.compare_steps, dev, reports)
         out["force_err_vs_fp64_eV_per_A"] = cmp["same_state_force_err_eV_per_A"]["max"]
         out["force_err_ok"] = out["force_err_vs_fp64_eV_per_A"] <= 1e-4
         out["split_kernel_err_over_W0"] = cmp["kernel_at_start"]["Y_split_vs_fp64_over_W0"]
         out["fp64_krylov_relres"] = cmp["kernel_at_start"]["fp64_krylov_relres"]
         out["split_vs_fp64"] = cmp
 
+    reports.close()
     if not args.no_cpu_baseline:
         log("timing the oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(sys_, w, X0.cpu().numpy(), args.cpu_threads)

@@ -1260,7 +1260,13 @@ xlbomd_status xlbomd_create(const xlbomd_system *sys, const xlbomd_params *prm, 
     return XLBOMD_E_ARG;
   const double n = 4.0 * sys->n_atoms;
   if (!(sys->n_elec > 0.0) || !(sys->n_elec < 2.0 * n)) return XLBOMD_E_ARG;
-  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prm->prec < 0 || prm->prec > 6 ||
+  // the precision is read as the int a C caller stores: in C++ a load of an
+  // enum outside its enumerators' range is undefined, and the range test on
+  // such a load may be dropped
+  static_assert(sizeof(xlbomd_precision) == sizeof(int), "precision is an int-sized enum");
+  int prec_raw;
+  std::memcpy(&prec_raw, &prm->prec, sizeof prec_raw);
+  if (!(prm->T_e > 0.0) || prm->m < 0 || prm->m > MMAX || prec_raw < 0 || prec_raw > 6 ||
       !(prm->kernel_c > 0.0) || !std::isfinite(prm->kernel_c) || !(prm->w0_limit >= 0.0) ||
       !(prm->T_ion_limit >= 0.0))
     return XLBOMD_E_ARG;

@@ -98,10 +98,10 @@ extern "C" xlbomd_status xlbomd_time_gemm(int n, int prec, int sym, int family, 
       }
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (A) hipFree(A);
-  if (B) hipFree(B);
-  if (Cm) hipFree(Cm);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (A) (void)hipFree(A);
+  if (B) (void)hipFree(B);
+  if (Cm) (void)hipFree(Cm);
   return st;
 }
