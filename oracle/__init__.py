@@ -31,6 +31,13 @@ Parity status per function:
                                                              kernel when J = -I; unstable where KSA is not)
   dynamics.ou_coefficients / dynamics.langevin_step          pinned (Maxwell-Boltzmann variance; gamma = 0
                                                              is md_step; thermalisation to the bath T)
+  overlap.overlap, overlap.overlap_derivative_blocks         pinned (symmetry, rotation covariance, finite
+                                                             differences)
+  overlap.lowdin, overlap.density_matrix, overlap.response   pinned (Z^T S Z = I; the generalized
+                                                             eigenproblem; another Z of eq. 21; finite
+                                                             differences)
+  overlap.pulay_forces                                       pinned (finite differences of the grand
+                                                             potential through S at fixed F)
 """
 
-from . import model, density, krylov, dynamics  # noqa: F401
+from . import model, density, krylov, dynamics, overlap  # noqa: F401

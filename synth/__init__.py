@@ -8,6 +8,7 @@ test take their inputs from here and do all of the arithmetic themselves.
 
 from .clusters import (  # noqa: F401
     ModelParams,
+    OverlapModel,
     System,
     carbon_cluster,
     ensemble_sizes,

@@ -83,6 +83,18 @@ class ModelParams:
                         dtype=np.float64)
 
 
+@dataclass(frozen=True)
+class OverlapModel:
+    """Constants of the synthetic overlap of a non-orthogonal basis: the radial
+    factor s(R) = s0 * exp(-(R - r0) / lam) of the off-site blocks (Angstrom).
+    At these values the overlap of the seeded clusters has eigenvalues in
+    about [0.74, 1.38]."""
+
+    s0: float = 0.08
+    r0: float = 1.4
+    lam: float = 0.4
+
+
 @dataclass
 class System:
     """One synthetic cluster: everything both sides need as input."""
