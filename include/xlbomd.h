@@ -240,6 +240,60 @@ xlbomd_status xlbomd_krylov_kernel(xlbomd_handle h, const double *X, const doubl
 xlbomd_status xlbomd_forces(xlbomd_handle h, const double *P0, const double *X,
                             double *forces, double *energy);
 
+/* ---------------------------------------------------------------------------
+ * Non-orthogonal basis (Methods section 3, eqs. 17-21; eqs. 36, 37, 39, 41).
+ * Single-point electronic calls for a basis with overlap S != I.  The MD
+ * path (xlbomd_step and its integrator) is orthogonal only: with S != I the
+ * extended variable X = D S is not symmetric.
+ *
+ * The overlap is the model's synthetic one: S_AA = I and, for A != B, the
+ * angular structure of the hopping block (s-s: s; s_A-p_B: s l;
+ * p_A-s_B: -s l; p_A-p_B: s l l^T, l = (R_B - R_A)/R) with
+ * s(R) = s0 exp(-(R - r0)/lam). */
+typedef struct {
+  double s0;   /* overlap at r0 (dimensionless), finite */
+  double r0;   /* Angstrom, finite                      */
+  double lam;  /* decay length, Angstrom, > 0           */
+} xlbomd_overlap_model;
+
+/* S(R) at the handle's positions into S (DEVICE n x n).  XLBOMD_E_ARG for
+ * null pointers or constants out of range; XLBOMD_E_STATE before
+ * xlbomd_set_geometry. */
+xlbomd_status xlbomd_overlap(xlbomd_handle h, const xlbomd_overlap_model *ov, double *S);
+
+/* Z = S^(-1/2), the symmetric (Loewdin) choice of eq. 21 (Z^T S Z = I), by a
+ * coupled Newton-Schulz iteration on the FP64 GEMMs.  S: DEVICE n x n,
+ * symmetric positive definite; Z: DEVICE n x n output, not aliasing S;
+ * iterations: host out, nullable.  XLBOMD_E_ARG if the spectral lower bound
+ * of S is not positive, XLBOMD_E_NOCONV after 60 iterations.  The first
+ * non-orthogonal call on a handle allocates four FP64 n x n work matrices. */
+xlbomd_status xlbomd_lowdin(xlbomd_handle h, const double *S, double *Z, int *iterations);
+
+/* Spin-summed P = 2 Z D0_perp Z^T (eq. 20) with D0_perp the Fermi matrix
+ * (eq. 19) of F_perp = Z^T F Z (eq. 18), mu fixed by Tr D0_perp = N_occ
+ * (equivalently Tr P S = N_e).  F: DEVICE n x n symmetric; Z: DEVICE n x n,
+ * any Z with Z^T S Z = I; mu: host in/out as in xlbomd_fermi_dm; P: DEVICE
+ * n x n output, not aliasing F or Z; entropy: host out, nullable.  The
+ * chain of F_perp is cached for xlbomd_dm_response_nonorth.  The transforms
+ * are FP64; the chain runs in the handle's precision. */
+xlbomd_status xlbomd_fermi_dm_nonorth(xlbomd_handle h, const double *F, const double *Z, double *mu, double *P,
+                                      double *entropy);
+
+/* Canonical response of eq. 36: P1 = Z P1_perp Z^T, P1_perp the response of
+ * the cached chain to Z^T F1 Z (Tr P1 S = 0).  Z must be the one of the last
+ * xlbomd_fermi_dm_nonorth.  F1: DEVICE n x n symmetric; P1: DEVICE n x n
+ * output, not aliasing F1 or Z.  XLBOMD_E_STATE if no chain is cached. */
+xlbomd_status xlbomd_dm_response_nonorth(xlbomd_handle h, const double *F1, const double *Z, double *P1);
+
+/* Pulay force term of eq. 41: forces[I] = + Tr[Z Z^T F P S_{R_I}] for the
+ * spin-summed P (the gradient term is -2 Tr[Z Z^T F D S_{R_I}], D = P / 2),
+ * into forces (DEVICE n_atoms x 3, eV/Angstrom, overwritten).  F, P: DEVICE
+ * n x n symmetric; Z: as above.  With xlbomd_forces(P0 = P, X = the density
+ * G is built from) it gives the eq. 37 forces for S != I.  Deterministic: one
+ * wavefront per atom in a fixed order. */
+xlbomd_status xlbomd_pulay_forces(xlbomd_handle h, const xlbomd_overlap_model *ov, const double *F,
+                                  const double *P, const double *Z, double *forces);
+
 /* damped X-Verlet of eq. 35 on the ring st->X using st->Y, and the
  * leapfrog position update of eqs. 27-28 (positions and half-step velocities);
  * advances st->head.  Used by xlbomd_step; exposed for testing. */

@@ -31,7 +31,9 @@ SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb
            "xlbomd_step", "xlbomd_step_langevin", "xlbomd_ensemble_step", "xlbomd_md_init", "xlbomd_scf",
            "xlbomd_matmul",
            "xlbomd_profile", "xlbomd_profile_read", "xlbomd_spectral_bounds_noalloc",
-           "xlbomd_set_tile_table", "xlbomd_time_gemm"]
+           "xlbomd_set_tile_table", "xlbomd_time_gemm",
+           "xlbomd_overlap", "xlbomd_lowdin", "xlbomd_fermi_dm_nonorth", "xlbomd_dm_response_nonorth",
+           "xlbomd_pulay_forces"]
 
 # GEMM kernel families of the tile table (xlbomd_set_tile_table)
 GEMM_AUTO, GEMM_SMALL, GEMM_LARGE = 0, 1, 2
@@ -42,6 +44,10 @@ TILE_TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile
 
 # largest n of xlbomd_spectral_bounds_noalloc (XLBOMD_SPECTRAL_BOUNDS_NOALLOC_MAX_N)
 SPECTRAL_BOUNDS_NOALLOC_MAX_N = 16384
+
+
+class OverlapModelC(C.Structure):
+    _fields_ = [("s0", C.c_double), ("r0", C.c_double), ("lam", C.c_double)]
 
 
 class Model(C.Structure):
@@ -123,6 +129,12 @@ def load():
     lib.xlbomd_spectral_bounds_noalloc.argtypes = [vp, i, vp, pd]
     lib.xlbomd_set_tile_table.argtypes = [pi, i]
     lib.xlbomd_time_gemm.argtypes = [i, i, i, i, i, vp, pd]
+    ovp = C.POINTER(OverlapModelC)
+    lib.xlbomd_overlap.argtypes = [vp, ovp, vp]
+    lib.xlbomd_lowdin.argtypes = [vp, vp, vp, pi]
+    lib.xlbomd_fermi_dm_nonorth.argtypes = [vp, vp, vp, pd, vp, pd]
+    lib.xlbomd_dm_response_nonorth.argtypes = [vp, vp, vp, vp]
+    lib.xlbomd_pulay_forces.argtypes = [vp, ovp, vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("xlbomd_last_error", "xlbomd_n_orb"):
             getattr(lib, name).restype = i
@@ -315,6 +327,36 @@ class Handle:
         self._check(self.lib.xlbomd_forces(self.h, self._mat(P0), self._mat(X),
                                            _ptr(frc, 3 * self.n_atoms, torch.float64), e), "forces")
         return list(e)
+
+    # ---- non-orthogonal basis (ov: any object with s0, r0, lam)
+    @staticmethod
+    def _ov(ov):
+        return C.byref(OverlapModelC(float(ov.s0), float(ov.r0), float(ov.lam)))
+
+    def overlap(self, ov, S):
+        self._check(self.lib.xlbomd_overlap(self.h, self._ov(ov), self._mat(S)), "overlap")
+
+    def lowdin(self, S, Z):
+        """Z = S^(-1/2); returns the Newton-Schulz iteration count."""
+        it = C.c_int(0)
+        self._check(self.lib.xlbomd_lowdin(self.h, self._mat(S), self._mat(Z), C.byref(it)), "lowdin")
+        return it.value
+
+    def fermi_dm_nonorth(self, F, Z, P, mu=float("nan")):
+        m = C.c_double(mu)
+        S = C.c_double(0.0)
+        self._check(self.lib.xlbomd_fermi_dm_nonorth(self.h, self._mat(F), self._mat(Z), C.byref(m), self._mat(P),
+                                                     C.byref(S)), "fermi_dm_nonorth")
+        return m.value, S.value
+
+    def dm_response_nonorth(self, F1, Z, P1):
+        self._check(self.lib.xlbomd_dm_response_nonorth(self.h, self._mat(F1), self._mat(Z), self._mat(P1)),
+                    "dm_response_nonorth")
+
+    def pulay_forces(self, ov, F, P, Z, frc):
+        import torch
+        self._check(self.lib.xlbomd_pulay_forces(self.h, self._ov(ov), self._mat(F), self._mat(P), self._mat(Z),
+                                                 _ptr(frc, 3 * self.n_atoms, torch.float64)), "pulay_forces")
 
     def integrate(self, state: MDState):
         sc = state._c(self)

@@ -256,6 +256,9 @@ struct xlbomd_ctx {
   double *f64[6] = {};
   double *Vk[MMAX] = {}, *Wk[MMAX] = {};
   int kalloc = 0;
+  // non-orthogonal basis: four FP64 n x n work matrices, allocated by the
+  // first call that needs them
+  double *no_w[4] = {};
   // entropy diagnostic: FP64 eigenvalues of F (library eigenvalue solve)
   hipsolverHandle_t solver = nullptr;
   double *eig = nullptr, *eig_work = nullptr;
@@ -1188,6 +1191,71 @@ xlbomd_status entropy(xlbomd_ctx *c, const double *F, double mu, double *S) {
   return get_scalars(c, S_ENT, 1, S);
 }
 
+// ------------------------------------------------------ non-orthogonal basis
+// Methods section 3: F_perp = Z^T F Z (eq. 18), the Fermi matrix of F_perp
+// (eq. 19), D0 = Z D0_perp Z^T (eq. 20) for any Z with Z^T S Z = I (eq. 21);
+// the response transforms the same way (eq. 36); the Pulay term is eq. 41.
+// Every transform is an FP64 GEMM (out = A^T op(B)): with U = Z^T M,
+// Z^T M Z = Z^T U^T for a symmetric M, and with V = M Z^T, Z M Z^T = V^T Z^T.
+xlbomd_status ensure_nonorth(xlbomd_ctx *c) {
+  for (auto &p : c->no_w)
+    if (!p && !dev_alloc((void **)&p, c->n2 * 8))
+      return fail(c, XLBOMD_E_NOMEM, "non-orthogonal work matrices: allocation failed");
+  return XLBOMD_OK;
+}
+
+// out = Z^T M Z for a symmetric M (U: work)
+void congruence_t(xlbomd_ctx *c, const double *Z, const double *M, double *U, double *out) {
+  mm_p(c, XLBOMD_FP64, Z, M, U, 1.0, 0);
+  mm_p(c, XLBOMD_FP64, Z, U, out, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+}
+// out = Z M Z^T for a symmetric M (U: work)
+void congruence(xlbomd_ctx *c, const double *Z, const double *M, double *U, double *out) {
+  mm_p(c, XLBOMD_FP64, M, Z, U, 1.0, 0, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+  mm_p(c, XLBOMD_FP64, U, Z, out, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 1);
+}
+
+// Z = S^(-1/2), the symmetric choice of eq. 21, by the coupled Newton-Schulz
+// iteration (Higham, "Functions of Matrices", SIAM 2008, section 6.3), which
+// takes only products of matrices that commute with S: with Y_0 = S / c and
+// Z_0 = I, D_k = (I - Z_k Y_k) / 2, Y_{k+1} = Y_k + Y_k D_k, Z_{k+1} = Z_k + D_k Z_k,
+// Z_k -> (S / c)^(-1/2).  c is the middle of the spectral bounds of S, so the
+// eigenvalues of S / c lie in (0, 2) and ||I - S / c|| < 1.  The GEMM writes
+// D directly, so ||D||_F has no cancellation; after the update that follows a
+// ||2 D||_F <= 1e-8 sqrt(n) the error is of order the square of that.
+xlbomd_status lowdin(xlbomd_ctx *c, const double *S, double *Z, int *iters) {
+  xlbomd_status st = ensure_nonorth(c);
+  if (st) return st;
+  double lohi[2];
+  if ((st = spectral_bounds(c, S, lohi))) return st;
+  if (!(lohi[0] > 0.0))
+    return fail(c, XLBOMD_E_ARG, "overlap matrix not positive definite (spectral lower bound %.3e)", lohi[0]);
+  const int n = c->n, n2 = (int)c->n2;
+  const double sc = 0.5 * (lohi[0] + lohi[1]);
+  double *Y[2] = {c->no_w[0], c->no_w[1]}, *Zk[2] = {Z, c->no_w[3]}, *D = c->no_w[2];
+  axpby(n2, 1.0 / sc, S, 0.0, nullptr, Y[0], 0, c->s);
+  axpbyI_dev(n, nullptr, 0.0, nullptr, nullptr, 0.0, nullptr, nullptr, 1.0, Zk[0], 0, c->s);
+  const double tol = 1e-8 * std::sqrt((double)n);
+  int cur = 0, it = 0;
+  for (;; ++it) {
+    if (it == 60) return fail(c, XLBOMD_E_NOCONV, "Newton-Schulz inverse square root: no convergence");
+    mm_p(c, XLBOMD_FP64, Zk[cur], Y[cur], D, -0.5, 1, nullptr, 0.0, nullptr, 0.0, 0.5);
+    const void *dd[1] = {D};
+    dots(n2, 1, dd, dd, c->dscal + S_DOTS, 0, c->red, c->s);
+    mm_p(c, XLBOMD_FP64, Y[cur], D, Y[1 - cur], 1.0, 1, Y[cur], 1.0);
+    mm_p(c, XLBOMD_FP64, D, Zk[cur], Zk[1 - cur], 1.0, 1, Zk[cur], 1.0);
+    cur = 1 - cur;
+    double e2;
+    if ((st = get_scalars(c, S_DOTS, 1, &e2))) return st;
+    const double e = 2.0 * std::sqrt(e2);
+    if (!std::isfinite(e)) return fail(c, XLBOMD_E_NONFINITE, "non-finite Newton-Schulz residual");
+    if (e <= tol) break;
+  }
+  axpby(n2, 1.0 / std::sqrt(sc), Zk[cur], 0.0, nullptr, Z, 0, c->s);
+  if (iters) *iters = it + 1;
+  return XLBOMD_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1246,6 +1314,7 @@ xlbomd_status xlbomd_destroy(xlbomd_handle c) {
   f(c->eig);
   f(c->eig_work);
   f(c->eig_info);
+  for (auto &p : c->no_w) f(p);
   delete c;
   return XLBOMD_OK;
 }
@@ -1443,6 +1512,71 @@ xlbomd_status xlbomd_forces(xlbomd_handle c, const double *P0, const double *X, 
 }
 
 // an MD state with every buffer present and its ring slot inside the history
+static bool overlap_ok(const xlbomd_overlap_model *ov) {
+  return ov && std::isfinite(ov->s0) && std::isfinite(ov->r0) && ov->lam > 0.0 && std::isfinite(ov->lam);
+}
+
+xlbomd_status xlbomd_overlap(xlbomd_handle c, const xlbomd_overlap_model *ov, double *S) {
+  if (!c || !S || !overlap_ok(ov)) return c ? fail(c, XLBOMD_E_ARG, "bad overlap arguments") : XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  overlap_matrix(c->N, c->R, OverlapSys{ov->s0, ov->r0, ov->lam}, S, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_lowdin(xlbomd_handle c, const double *S, double *Z, int *iterations) {
+  if (!c || !S || !Z || S == Z) return c ? fail(c, XLBOMD_E_ARG, "bad lowdin arguments") : XLBOMD_E_ARG;
+  xlbomd_status st = lowdin(c, S, Z, iterations);
+  if (st) return st;
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_fermi_dm_nonorth(xlbomd_handle c, const double *F, const double *Z, double *mu, double *P,
+                                      double *entropy) {
+  if (!c || !F || !Z || !mu || !P || P == F || P == Z)
+    return c ? fail(c, XLBOMD_E_ARG, "bad fermi_dm_nonorth arguments") : XLBOMD_E_ARG;
+  xlbomd_status st = ensure_nonorth(c);
+  if (st) return st;
+  double *U = c->no_w[0], *Fp = c->no_w[1], *Pp = c->no_w[2];
+  congruence_t(c, Z, F, U, Fp);
+  if ((st = fermi(c, Fp, mu, Pp, true))) return st;
+  if (entropy && (st = ::entropy(c, Fp, *mu, entropy))) return st;
+  congruence(c, Z, Pp, U, P);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_dm_response_nonorth(xlbomd_handle c, const double *F1, const double *Z, double *P1) {
+  if (!c || !F1 || !Z || !P1 || P1 == F1 || P1 == Z)
+    return c ? fail(c, XLBOMD_E_ARG, "bad dm_response_nonorth arguments") : XLBOMD_E_ARG;
+  if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");
+  xlbomd_status st = ensure_nonorth(c);
+  if (st) return st;
+  double *U = c->no_w[0], *F1p = c->no_w[1], *P1p = c->no_w[2];
+  congruence_t(c, Z, F1, U, F1p);
+  if ((st = response(c, F1p, P1p))) return st;
+  congruence(c, Z, P1p, U, P1);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
+xlbomd_status xlbomd_pulay_forces(xlbomd_handle c, const xlbomd_overlap_model *ov, const double *F,
+                                  const double *P, const double *Z, double *frc) {
+  if (!c || !F || !P || !Z || !frc || !overlap_ok(ov))
+    return c ? fail(c, XLBOMD_E_ARG, "bad pulay_forces arguments") : XLBOMD_E_ARG;
+  if (!c->geom) return fail(c, XLBOMD_E_STATE, "positions not set");
+  xlbomd_status st = ensure_nonorth(c);
+  if (st) return st;
+  double *U = c->no_w[0], *FSi = c->no_w[1], *Qt = c->no_w[2];
+  mm_p(c, XLBOMD_FP64, Z, F, U, 1.0, 0);                                           // Z^T F
+  mm_p(c, XLBOMD_FP64, U, Z, FSi, 1.0, 0, nullptr, 0.0, nullptr, 0.0, 0.0, 1);     // F Z Z^T = F S^-1
+  mm_p(c, XLBOMD_FP64, P, FSi, Qt, 1.0, 0);                                        // P F S^-1 = Q^T
+  pulay_forces(c->N, c->R, OverlapSys{ov->s0, ov->r0, ov->lam}, Qt, frc, c->s);
+  HIPCHK(c, hipGetLastError());
+  return XLBOMD_OK;
+}
+
 static bool state_ok(const xlbomd_md_state *st) {
   return st && st->R && st->V && st->A && st->X && st->Y && st->head >= 0 && st->head < 7;
 }

@@ -108,6 +108,17 @@ void forces(const PairSys &ps, const double *P0, const double *X, double *frc, d
 size_t force_partial_doubles(int n_atoms);
 size_t energy_partial_doubles(int n_atoms);
 
+// ------------------------------------------------- non-orthogonal basis
+// radial constants of the synthetic overlap s(R) = s0 exp(-(R - r0)/lam)
+struct OverlapSys {
+  double s0, r0, lam;
+};
+// S (4 n_atoms square, row-major): unit atom blocks, hopping-shaped off-site blocks
+void overlap_matrix(int n_atoms, const double *R, const OverlapSys &ov, double *S, hipStream_t s);
+// frc (n_atoms x 3) = Tr[Q S_{R_I}] for Q = S^-1 F P, given as Qt = Q^T
+void pulay_forces(int n_atoms, const double *R, const OverlapSys &ov, const double *Qt, double *frc,
+                  hipStream_t s);
+
 // ------------------------------------------------------------- scalar kernels
 // Chemical-potential and Krylov scalar steps (one thread), see the .hip file.
 // tol_n: a trace within tol_n of n_occ takes no shift (dmu = 0)

@@ -54,7 +54,7 @@ def test_library_loads_without_gpu(built):
 # binding struct -> C struct name
 _STRUCTS = {"Model": "xlbomd_model", "System": "xlbomd_system", "Params": "xlbomd_params",
             "MDStateC": "xlbomd_md_state", "Report": "xlbomd_report", "SCFParams": "xlbomd_scf_params",
-            "SCFReport": "xlbomd_scf_report"}
+            "SCFReport": "xlbomd_scf_report", "OverlapModelC": "xlbomd_overlap_model"}
 
 
 def test_binding_structs_match_header_layout(tmp_path):

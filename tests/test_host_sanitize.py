@@ -30,7 +30,7 @@ from test_host_eig import _cases
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2303_00689_amd", "csrc")
-SOURCES = ["api.hip", "blas1.hip", "gemm_f64.hip", "gemm_split.hip", "noalloc.hip", "pairs.hip", "tiles.hip"]
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))   # every source of the library
 HIPCC = "/opt/rocm/bin/hipcc"
 E_ARG = -1
 
@@ -183,6 +183,14 @@ static int api_mode() {
   REPORT("matmul", xlbomd_matmul(nullptr, buf, buf + 16, buf + 32, 0, 1));
   REPORT("profile", xlbomd_profile(nullptr, 1));
   REPORT("profile_read", xlbomd_profile_read(nullptr, buf));
+  xlbomd_overlap_model ov = {0.08, 1.4, 0.4}, bad_ov = {0.08, 1.4, 0.0};
+  REPORT("overlap", xlbomd_overlap(nullptr, &ov, buf));
+  REPORT("overlap_null_model", xlbomd_overlap(nullptr, nullptr, buf));
+  REPORT("lowdin", xlbomd_lowdin(nullptr, buf, buf + 16, ibuf));
+  REPORT("fermi_dm_nonorth", xlbomd_fermi_dm_nonorth(nullptr, buf, buf + 16, buf + 32, buf + 48, nullptr));
+  REPORT("dm_response_nonorth", xlbomd_dm_response_nonorth(nullptr, buf, buf + 16, buf + 32));
+  REPORT("pulay_forces", xlbomd_pulay_forces(nullptr, &ov, buf, buf + 16, buf + 32, buf + 48));
+  REPORT("pulay_forces_bad_model", xlbomd_pulay_forces(nullptr, &bad_ov, buf, buf + 16, buf + 32, buf + 48));
   double us = 0.0;
   REPORT("time_gemm_n_0", xlbomd_time_gemm(0, 0, 0, 1, 1, nullptr, &us));
   REPORT("time_gemm_prec_4", xlbomd_time_gemm(256, 4, 0, 1, 1, nullptr, &us));
@@ -383,7 +391,7 @@ def test_spectral_bounds_hold_the_spectrum(driver):
 
 def test_every_entry_point_rejects_bad_arguments_before_hip(driver):
     lines = [ln for ln in run(driver, "api") if ln.strip()]
-    assert len(lines) == 56          # every call of the driver reported
+    assert len(lines) == 63          # every call of the driver reported
     for line in lines:
         name, st = line.split()
         assert int(st) == E_ARG, f"{name} returned {st}"
