@@ -482,6 +482,71 @@ def run_study_lowgap(args, binding, torch, np, dev):
         "split_vs_fp64": cmp}))
 
 
+def run_study_nonorth(args, binding, torch, np, dev):
+    """The non-orthogonal basis at 840 atoms (Methods section 3; eq. 41): the
+    time of each call beside its orthogonal counterpart on the same F, with
+    the overlap of the synthetic model, from the SCF iterate MD starts from.
+    Each call is timed over --study-steps repetitions after one warm-up
+    (torch synchronisation around the loop); the FP64 GEMM classes of the
+    Loewdin iteration come from the handle's HIP-event profile."""
+    from synth import OverlapModel, workload
+    sys_, w = workload("c840")
+    n = sys_.n_orb
+    X0, init = initial_scf(binding, torch, sys_, w, dev, args.init_mix, args.init_newton)
+    ov = OverlapModel()
+    h = binding.handle_for(sys_, w, prec="fp64")
+    h.set_geometry(torch.tensor(sys_.R, dtype=torch.float64, device=dev))
+    mat = lambda: torch.empty((n, n), dtype=torch.float64, device=dev)
+    S, Z, F, P, P1, F1 = mat(), mat(), mat(), mat(), mat(), mat()
+    frc = torch.empty((sys_.n_atoms, 3), dtype=torch.float64, device=dev)
+    h.fock(X0, F, True)
+    h.fock(X0 - torch.diag(torch.diagonal(X0)), F1, False)     # a symmetric G(V) as the perturbation
+    reps = max(args.study_steps, 1)
+    iters = {}
+
+    def timed(name, fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        log(f"  {name}: {ms:.3f} ms")
+        return ms
+
+    out = {"overlap_ms": timed("overlap", lambda: h.overlap(ov, S))}
+    out["lowdin_ms"] = timed("lowdin", lambda: iters.__setitem__("z", h.lowdin(S, Z)))
+    h.profile(True)
+    h.lowdin(S, Z)
+    torch.cuda.synchronize()
+    prof = h.profile_read()
+    h.profile(False)
+    # the density matrix alone (no entropy eigensolve), warm-started from the last mu as in MD
+    mu = h.fermi_dm(F, P, entropy=False)[0]
+    out["fermi_dm_ms"] = timed("fermi_dm", lambda: h.fermi_dm(F, P, mu=mu, entropy=False))
+    mu_no = h.fermi_dm_nonorth(F, Z, P, entropy=False)[0]
+    out["fermi_dm_nonorth_ms"] = timed("fermi_dm_nonorth", lambda: h.fermi_dm_nonorth(F, Z, P, mu=mu_no,
+                                                                                      entropy=False))
+    out["dm_response_ms"] = None
+    out["dm_response_nonorth_ms"] = timed("dm_response_nonorth", lambda: h.dm_response_nonorth(F1, Z, P1))
+    h.fermi_dm(F, P, mu=mu, entropy=False)
+    out["dm_response_ms"] = timed("dm_response", lambda: h.dm_response(F1, P1))
+    h.fermi_dm_nonorth(F, Z, P, mu=mu_no, entropy=False)
+    out["pulay_forces_ms"] = timed("pulay_forces", lambda: h.pulay_forces(ov, F, P, Z, frc))
+    out["forces_ms"] = timed("forces", lambda: h.forces(P, X0, frc))
+    h.close()
+    gemm = [k for k in prof if k.startswith("gemm_f64") and prof[k]["launches"]]
+    print(json.dumps({
+        "study": "nonorth_c840",
+        "workload": (f"840-atom carbon cluster, 3360x3360, T_e {w['T_e']:.0f} K, FP64 chains; overlap "
+                     f"s0 {ov.s0} r0 {ov.r0} lam {ov.lam} (eigenvalues about 0.74-1.38); F from the SCF iterate "
+                     f"after {init['mix_steps']} mixing + {init['newton_steps']} Newton-Krylov steps"),
+        "reps": reps, "lowdin_iterations": iters.get("z"), **out,
+        "lowdin_gemm_roofline": gemm_roofline(prof, gemm, out["lowdin_ms"] * 1e-3) if gemm else None,
+        "lowdin_kernel_classes": class_summary(prof, 1)}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,10 +571,13 @@ def main():
                          "after another")
     ap.add_argument("--hw-queues", type=int, default=16, choices=range(1, 33), metavar="1..32",
                     help="hardware queues of the process in the ensemble mode (GPU_MAX_HW_QUEUES)")
-    ap.add_argument("--study", default="", choices=["", "lowgap"],
+    ap.add_argument("--study", default="", choices=["", "lowgap", "nonorth"],
                     help="instead: the low-gap trajectory study (840 atoms, hopping x0.6, s-p split 4 eV, "
                          "10000 K, rank 8): --study-steps NVE steps of --study-prec against FP64 from the "
-                         "same start, with drift and force error; prints one JSON line of its own")
+                         "same start, with drift and force error; or the non-orthogonal calls at 840 atoms "
+                         "(overlap, Loewdin Z, density matrix, response, Pulay forces), each timed over "
+                         "--study-steps repetitions beside its orthogonal counterpart; prints one JSON line of "
+                         "its own")
     ap.add_argument("--study-steps", type=int, default=200)
     ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
     ap.add_argument("--reports-jsonl", default="", metavar="PATH",
@@ -548,8 +616,11 @@ def main():
     if args.ensemble:
         run_ensemble(args, binding, torch, dev)
         return
-    if args.study:
+    if args.study == "lowgap":
         run_study_lowgap(args, binding, torch, np, dev)
+        return
+    if args.study == "nonorth":
+        run_study_nonorth(args, binding, torch, np, dev)
         return
     sys_, w = workload(args.workload)
     n = sys_.n_orb

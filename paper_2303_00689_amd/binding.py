@@ -298,11 +298,12 @@ class Handle:
     def fock(self, P, F, include_h=True):
         self._check(self.lib.xlbomd_fock(self.h, self._mat(P), self._mat(F), int(bool(include_h))), "fock")
 
-    def fermi_dm(self, F, P, mu=float("nan")):
+    def fermi_dm(self, F, P, mu=float("nan"), entropy=True):
+        """(mu, S/k_B); entropy=False skips the entropy's eigenvalue solve (S = nan)."""
         m = C.c_double(mu)
-        S = C.c_double(0.0)
-        self._check(self.lib.xlbomd_fermi_dm(self.h, self._mat(F), C.byref(m), self._mat(P), C.byref(S)),
-                    "fermi_dm")
+        S = C.c_double(float("nan"))
+        self._check(self.lib.xlbomd_fermi_dm(self.h, self._mat(F), C.byref(m), self._mat(P),
+                                             C.byref(S) if entropy else None), "fermi_dm")
         return m.value, S.value
 
     def spectral_bounds(self, F):
@@ -342,11 +343,12 @@ class Handle:
         self._check(self.lib.xlbomd_lowdin(self.h, self._mat(S), self._mat(Z), C.byref(it)), "lowdin")
         return it.value
 
-    def fermi_dm_nonorth(self, F, Z, P, mu=float("nan")):
+    def fermi_dm_nonorth(self, F, Z, P, mu=float("nan"), entropy=True):
+        """(mu, S/k_B) as fermi_dm."""
         m = C.c_double(mu)
-        S = C.c_double(0.0)
+        S = C.c_double(float("nan"))
         self._check(self.lib.xlbomd_fermi_dm_nonorth(self.h, self._mat(F), self._mat(Z), C.byref(m), self._mat(P),
-                                                     C.byref(S)), "fermi_dm_nonorth")
+                                                     C.byref(S) if entropy else None), "fermi_dm_nonorth")
         return m.value, S.value
 
     def dm_response_nonorth(self, F1, Z, P1):

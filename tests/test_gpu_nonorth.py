@@ -62,8 +62,10 @@ def run_case(lib, s, T_e, ov, seed=0, m=3, check_response=True):
         h.fock(t(X), F, include_h=True)
         Fref = model.fock(X, s.R, s.onecenter, s.noise, s.params)
         P = torch.empty_like(S)
-        mu, _ = h.fermi_dm_nonorth(F, Z, P)
+        mu, ent = h.fermi_dm_nonorth(F, Z, P)
         dm = overlap.density_matrix(Fref, Zref, s.n_elec, beta)
+        # the entropy of eq. 4 from the occupations of F_perp's levels
+        assert ent == pytest.approx(density.entropy(dm["f"]), rel=1e-9, abs=1e-9)
         Pg = P.cpu().numpy()
         eP = rel(Pg, dm["P"])
         f = dm["f"]
