@@ -4,10 +4,11 @@ tile table the binding installs with the library (xlbomd_set_tile_table).
 
     python -m paper_2303_00689_amd.autotune [--out PATH] [--reps K]
 
-For each (precision, output kind) and each order n of the grid, both families
-are timed when both can run n (FP64 large tiles need n % 16 == 0, split large
-tiles n % 32 == 0, both n >= 128; FP16x3 has one family), and the faster one
-is kept; runs of equal choices merge into one row covering (previous n, n].
+For each (precision, output kind) and each order n of the grid, every family
+that can run n is timed (FP64: small and large tiles, large needing
+n % 16 == 0; BF16x3 and BF16x6: small, large and medium tiles, the last two
+needing n % 32 == 0; all large and medium tiles n >= 128; FP16x3 has one
+family), and the fastest is kept; runs of equal choices merge into one row covering (previous n, n].
 Orders between grid points take the next grid point's row; orders a row's
 family cannot run, and orders past the grid, take the library's built-in rule.
 """
@@ -36,14 +37,18 @@ def tune(reps: int, grid=GRID, log=print):
     for prec, pname in PRECS.items():
         for sym in (0, 1):
             choice = []
+            fams = {"small": binding.GEMM_SMALL, "large": binding.GEMM_LARGE}
+            if prec in (1, 2):
+                fams["medium"] = binding.GEMM_MEDIUM
             for n in grid:
-                t_small = binding.time_gemm(n, prec, sym, binding.GEMM_SMALL, reps)
-                t_large = binding.time_gemm(n, prec, sym, binding.GEMM_LARGE, reps)
-                fam = binding.GEMM_SMALL if t_large is None or t_small <= t_large else binding.GEMM_LARGE
+                t = {name: binding.time_gemm(n, prec, sym, f, reps) for name, f in fams.items()}
+                # the fastest family that can run n (small always can); ties keep the smaller tiles
+                best = min((v, k) for k, v in t.items() if v is not None)[1]
+                fam = fams[best]
                 choice.append((n, fam))
-                timings.append({"prec": pname, "sym": sym, "n": n, "small_us": t_small, "large_us": t_large,
+                timings.append({"prec": pname, "sym": sym, "n": n, **{f"{k}_us": v for k, v in t.items()},
                                 "family": fam})
-            log(f"{pname} sym={sym}: " + " ".join(f"{n}:{'L' if f == 2 else 's'}" for n, f in choice))
+            log(f"{pname} sym={sym}: " + " ".join(f"{n}:{'sLM'[f - 1]}" for n, f in choice))
             # merge runs of one family into rows covering (previous n_max, n_max]
             for k, (n, fam) in enumerate(choice):
                 if k + 1 < len(choice) and choice[k + 1][1] == fam:
@@ -67,7 +72,7 @@ def main():
         raise SystemExit(f"{len(rows)} rows exceed the table's {binding.TILE_TABLE_MAX}")
     out = {"device": torch.cuda.get_device_name(0), "reps": args.reps,
            "seconds": time.perf_counter() - t,
-           "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6), sym, n_max, family (1 small, 2 large)]",
+           "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6), sym, n_max, family (1 small, 2 large, 3 medium)]",
            "rows": rows, "timings": timings}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)

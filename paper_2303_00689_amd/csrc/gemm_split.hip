@@ -552,9 +552,13 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles) or 5 (160);
-// STAGES k panels of B in LDS
-template <int MODE, int BNB, int STAGES>
+// BNB MFMA blocks of 16 per wave tile edge: 7 (224-row tiles), 5 (160) or 4
+// (128); STAGES k panels of B in LDS.  RAGGED: n % 32 != 0 (n % 4 == 0), the
+// last k panel runs past n: its A values there are zeroed after loads from a
+// valid address (the row's first column), so every load is still issued and
+// the counted waits below stay exact, and B's values there (the next row's,
+// or zeros past the buffer's range) multiply those zeros.
+template <int MODE, int BNB, int STAGES, bool RAGGED = false>
 __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   // BF16 splits only: the FP16 split's second accumulator does not fit
   static_assert(MODE == 0 || MODE == 1, "large-tile kernel: BF16 splits only");
@@ -581,10 +585,10 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
 #pragma unroll
     for (int c = 0; c < BNB; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // n is a multiple of 32, so every k panel is full.  Rows past n are read
-  // clamped to row n - 1: they only reach output rows and columns past n,
-  // which are not stored.
-  const int kt_per = n / TK;
+  // Unless RAGGED, n is a multiple of 32 and every k panel is full.  Rows
+  // past n are read clamped to row n - 1: they only reach output rows and
+  // columns past n, which are not stored.
+  const int kt_per = RAGGED ? (n + TK - 1) / TK : n / TK;
   const int ktiles = kt_per * p.nprod;
 
   // B panels: buffer loads to LDS, the BT rows x 32 k of a panel shared by the
@@ -624,22 +628,44 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   auto loadA = [&](int kt, int r, float (&x)[8]) {
     const int prod = kt / kt_per;
     const char *base = (const char *)p.A[prod] + aoff[r] + 4 * (kt - prod * kt_per) * TK;
-    const f4 lo = *(const f4 *)base;
-    const f4 hi = *(const f4 *)(base + 16);
+    if (RAGGED) {
+      // k of this lane's first value; n % 4 == 0, so each group of four is
+      // wholly below n or wholly past it
+      const int kl = (kt - prod * kt_per) * TK + 8 * fq;
+      const bool okl = kl < n, okh = kl + 4 < n;
+      const char *row0 = (const char *)p.A[prod] + (aoff[r] - 32u * (unsigned)fq);
+      const f4 lo = *(const f4 *)(okl ? base : row0);
+      const f4 hi = *(const f4 *)(okh ? base + 16 : row0);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x[v] = lo[v];
-      x[4 + v] = hi[v];
+      for (int v = 0; v < 4; ++v) {
+        x[v] = okl ? lo[v] : 0.f;
+        x[4 + v] = okh ? hi[v] : 0.f;
+      }
+    } else {
+      const f4 lo = *(const f4 *)base;
+      const f4 hi = *(const f4 *)(base + 16);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x[v] = lo[v];
+        x[4 + v] = hi[v];
+      }
     }
   };
-  // eight FP32 values of B stage row r, k 8 fq .. 8 fq + 7
-  auto fetch = [&](const float *st, int r, float (&x)[8]) {
+  // eight FP32 values of B stage row r, k 8 fq .. 8 fq + 7 of panel kt
+  // (RAGGED: zero past n, whatever the stage holds there)
+  auto fetch = [&](const float *st, int r, float (&x)[8], int kt) {
     const f4 lo = *(const f4 *)(st + r * LROW + 4 * swz(r, 2 * fq));
     const f4 hi = *(const f4 *)(st + r * LROW + 4 * swz(r, 2 * fq + 1));
+    bool okl = true, okh = true;
+    if (RAGGED) {
+      const int kl = (kt % kt_per) * TK + 8 * fq;
+      okl = kl < n;
+      okh = kl + 4 < n;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      x[v] = lo[v];
-      x[4 + v] = hi[v];
+      x[v] = okl ? lo[v] : 0.f;
+      x[4 + v] = okh ? hi[v] : 0.f;
     }
   };
   // the product terms of row block r and column block c, small terms first
@@ -680,7 +706,7 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
 #pragma unroll
   for (int c = 0; c < BNB; ++c) {
     float x[8];
-    fetch(stg[0], wn + 16 * c + fr, x);
+    fetch(stg[0], wn + 16 * c + fr, x, 0);
     split8_pk<MODE>(x, b[c]);
   }
   split8_pk<MODE>(xa[0], a);
@@ -702,8 +728,8 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
       // values unused), so that no branch separates the reads from their uses
       constexpr int nreads = (r == 0 ? 2 : 0) + (r + 1 < BNB ? 2 : 0);
       loadA(ka, r, xa[r]);
-      if (r == 0) fetch(nxt, wn + fr, xb[0]);
-      if (r + 1 < BNB) fetch(nxt, wn + 16 * (r + 1) + fr, xb[r + 1 < BNB ? r + 1 : 0]);
+      if (r == 0) fetch(nxt, wn + fr, xb[0], kt + 1);
+      if (r + 1 < BNB) fetch(nxt, wn + 16 * (r + 1) + fr, xb[r + 1 < BNB ? r + 1 : 0], kt + 1);
       // splits under this row block's MFMAs: the A block multiplied next (the
       // next panel's block 0 in the last row block) and the B block(s) loaded
       // at least one row block earlier
@@ -783,6 +809,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                                                                                                    int T) {
   gemm_split_big_body<MODE, BNB, BNB == 7 ? 4 : 3>(p, T);
 }
+// 128-row tiles (BNB = 4): three B stages (49 KB) and at most 256 registers,
+// so two workgroups share a compute unit and a second wave per SIMD hides
+// the first one's memory waits
+template <int MODE, bool RAGGED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_split_mid(GemmArgs p,
+                                                                                                  int T) {
+  gemm_split_big_body<MODE, 4, 3, RAGGED>(p, T);
+}
 
 // BF16x3, the response-chain mode of the mixed-precision step: two register
 // stages at two waves per SIMD
@@ -804,6 +838,23 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   const int blocks = tile_count(T, a.sym);
   int fam = a.family != GEMM_AUTO ? a.family : table_family(prec, a.sym, a.n);
   if (!family_runs(prec, fam, a.n)) fam = GEMM_AUTO;
+  if (fam == GEMM_MEDIUM) {
+    const int Tm = (a.n + 127) / 128;
+    const int bm = tile_count(Tm, a.sym);
+    const bool rag = a.n % 32 != 0;
+    if (prec == 2) {
+      if (rag)
+        hipLaunchKernelGGL((k_gemm_split_mid<1, true>), dim3(bm), dim3(256), 0, s, a, Tm);
+      else
+        hipLaunchKernelGGL((k_gemm_split_mid<1, false>), dim3(bm), dim3(256), 0, s, a, Tm);
+    } else {
+      if (rag)
+        hipLaunchKernelGGL((k_gemm_split_mid<0, true>), dim3(bm), dim3(256), 0, s, a, Tm);
+      else
+        hipLaunchKernelGGL((k_gemm_split_mid<0, false>), dim3(bm), dim3(256), 0, s, a, Tm);
+    }
+    return;
+  }
   const bool big = fam == GEMM_AUTO ? (family_runs(prec, GEMM_LARGE, a.n) && blocks >= 192) : fam == GEMM_LARGE;
   if (big) {
     if (a.sym) {

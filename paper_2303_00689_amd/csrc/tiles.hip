@@ -23,6 +23,7 @@ int table_count = 0;
 
 bool family_runs(int prec, int fam, int n) {
   if (fam == GEMM_AUTO || fam == GEMM_SMALL) return n >= 1;
+  if (fam == GEMM_MEDIUM) return (prec == 1 || prec == 2) && n % 4 == 0 && n >= 128 && n <= 32767;
   if (fam != GEMM_LARGE) return false;
   if (prec == 0) return n % 16 == 0 && n >= 128 && n <= 23170;
   if (prec == 1 || prec == 2) return n % 32 == 0 && n >= 128 && n <= 32767;
@@ -46,7 +47,7 @@ extern "C" xlbomd_status xlbomd_set_tile_table(const int *rows, int count) {
   for (int i = 0; i < count; ++i) {
     const int *r = rows + 4 * i;
     if (r[0] < 0 || r[0] > 3 || (r[1] != 0 && r[1] != 1) || r[2] < 1 || r[3] < xl::GEMM_AUTO ||
-        r[3] > xl::GEMM_LARGE)
+        r[3] > xl::GEMM_MEDIUM)
       return XLBOMD_E_ARG;
     tmp[i] = {r[0], r[1], r[2], r[3]};
   }
@@ -61,7 +62,8 @@ extern "C" xlbomd_status xlbomd_set_tile_table(const int *rows, int count) {
 extern "C" xlbomd_status xlbomd_time_gemm(int n, int prec, int sym, int family, int reps, void *stream,
                                           double *us) {
   if (n < 1 || prec < 0 || prec > 3 || (sym != 0 && sym != 1) || reps < 1 || !us ||
-      (family != xl::GEMM_SMALL && family != xl::GEMM_LARGE) || !xl::family_runs(prec, family, n))
+      (family != xl::GEMM_SMALL && family != xl::GEMM_LARGE && family != xl::GEMM_MEDIUM) ||
+      !xl::family_runs(prec, family, n))
     return XLBOMD_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t bytes = (size_t)n * n * (prec == 0 ? 8 : 4);

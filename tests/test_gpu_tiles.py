@@ -8,7 +8,8 @@ tilings; below the diagonal of a symmetric output one family mirrors where
 the other computes the diagonal tiles' lower halves); in split
 precision each stays within the split arithmetic's budget of
 tests/test_gpu_split.py, with the FP32-accumulation term at these sizes.
-Orders cover one tile, ragged last tiles and several tiles of each family.
+Orders cover one tile, ragged last tiles (and, for the medium tiles, a ragged
+last k panel: n % 32 != 0) and several tiles of each family.
 """
 
 import numpy as np
@@ -45,11 +46,11 @@ def _product(binding, h, A, B, sym, prec, family):
 
 
 @pytest.mark.parametrize("mode", ["fp64", "bf16x3", "bf16x6"])
-@pytest.mark.parametrize("n_atoms", [32, 100, 264])
+@pytest.mark.parametrize("n_atoms", [32, 37, 100, 264])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_families_agree(binding, mode, n_atoms, sym):
     s = carbon_cluster(n_atoms, 3)
-    n = s.n_orb        # 128, 400, 1056: one tile, ragged tiles, several
+    n = s.n_orb        # 128, 148, 400, 1056: one tile, ragged tiles and k, several
     h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
     try:
         rng = np.random.default_rng(n + 5)
@@ -60,6 +61,8 @@ def test_families_agree(binding, mode, n_atoms, sym):
         small = _product(binding, h, A, B, sym, prec, binding.GEMM_SMALL)
         large_runs = binding.time_gemm(n, prec, sym, binding.GEMM_LARGE, 1) is not None
         large = _product(binding, h, A, B, sym, prec, binding.GEMM_LARGE) if large_runs else None
+        mid_runs = prec != 0 and binding.time_gemm(n, prec, sym, binding.GEMM_MEDIUM, 1) is not None
+        mid = _product(binding, h, A, B, sym, prec, binding.GEMM_MEDIUM) if mid_runs else None
     finally:
         binding.set_tile_table([])
         h.close()
@@ -83,7 +86,7 @@ def test_families_agree(binding, mode, n_atoms, sym):
     ref = A32 @ B32
     S = float((np.abs(A32) @ np.abs(B32)).max())
     acc = 4.0 * np.sqrt(n) * 2.0**-24 * S / np.abs(ref).max()
-    for name, C in (("small", small), ("large", large)):
+    for name, C in (("small", small), ("large", large), ("medium", mid)):
         if C is None:
             continue
         err = _rel(C, ref)
@@ -98,7 +101,11 @@ def test_time_gemm_and_table_arguments(binding):
     assert binding.time_gemm(96, 0, 0, binding.GEMM_LARGE, 1) is None        # below 128
     assert binding.time_gemm(256, 3, 0, binding.GEMM_LARGE, 1) is None       # FP16x3: one family
     assert binding.time_gemm(256, 3, 0, binding.GEMM_SMALL, 1) > 0.0
-    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 3]],
+    assert binding.time_gemm(256, 0, 0, binding.GEMM_MEDIUM, 1) is None      # split only
+    assert binding.time_gemm(400, 2, 1, binding.GEMM_MEDIUM, 1) > 0.0       # ragged last k panel
+    assert binding.time_gemm(402, 1, 1, binding.GEMM_MEDIUM, 1) is None      # 402 % 4 != 0
+    assert binding.time_gemm(416, 1, 1, binding.GEMM_MEDIUM, 1) > 0.0
+    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 4]],
                 [[0, 0, 100, 1]] * (binding.TILE_TABLE_MAX + 1)):
         with pytest.raises(binding.XLBOMDError):
             binding.set_tile_table(bad)
