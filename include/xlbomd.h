@@ -282,7 +282,9 @@ xlbomd_status xlbomd_fermi_dm_nonorth(xlbomd_handle h, const double *F, const do
 /* Canonical response of eq. 36: P1 = Z P1_perp Z^T, P1_perp the response of
  * the cached chain to Z^T F1 Z (Tr P1 S = 0).  Z must be the one of the last
  * xlbomd_fermi_dm_nonorth.  F1: DEVICE n x n symmetric; P1: DEVICE n x n
- * output, not aliasing F1 or Z.  XLBOMD_E_STATE if no chain is cached. */
+ * output, not aliasing F1 or Z.  XLBOMD_E_STATE unless the cached chain is
+ * that of an xlbomd_fermi_dm_nonorth (any later density-matrix evaluation on
+ * the handle replaces it). */
 xlbomd_status xlbomd_dm_response_nonorth(xlbomd_handle h, const double *F1, const double *Z, double *P1);
 
 /* Pulay force term of eq. 41: forces[I] = + Tr[Z Z^T F P S_{R_I}] for the

@@ -243,6 +243,7 @@ struct xlbomd_ctx {
   int Lalloc = 0;  // chain levels with storage (grown on demand up to LMAX)
   int mu_passes = 0;
   bool chain_valid = false;
+  bool chain_nonorth = false;  // the cached chain is of F_perp (xlbomd_fermi_dm_nonorth)
   double mu_chain = 0.0;
   // Trace tolerance of the chemical-potential passes.  With FP32 storage of the
   // Fermi chain, Tr D and Tr D(I - D) carry the chain's rounding; in a strongly
@@ -1002,6 +1003,7 @@ bool chain_sound(const xlbomd_ctx *c, const double tm[2]) {
 }
 
 xlbomd_status fermi(xlbomd_ctx *c, const double *F, double *mu_io, double *P, bool sync_check) {
+  c->chain_nonorth = false;
   double lohi[2], gersh[2];
   xlbomd_status st = spectral_bounds(c, F, lohi, gersh);
   if (st) return st;
@@ -1541,6 +1543,7 @@ xlbomd_status xlbomd_fermi_dm_nonorth(xlbomd_handle c, const double *F, const do
   double *U = c->no_w[0], *Fp = c->no_w[1], *Pp = c->no_w[2];
   congruence_t(c, Z, F, U, Fp);
   if ((st = fermi(c, Fp, mu, Pp, true))) return st;
+  c->chain_nonorth = true;
   if (entropy && (st = ::entropy(c, Fp, *mu, entropy))) return st;
   congruence(c, Z, Pp, U, P);
   HIPCHK(c, hipGetLastError());
@@ -1550,7 +1553,8 @@ xlbomd_status xlbomd_fermi_dm_nonorth(xlbomd_handle c, const double *F, const do
 xlbomd_status xlbomd_dm_response_nonorth(xlbomd_handle c, const double *F1, const double *Z, double *P1) {
   if (!c || !F1 || !Z || !P1 || P1 == F1 || P1 == Z)
     return c ? fail(c, XLBOMD_E_ARG, "bad dm_response_nonorth arguments") : XLBOMD_E_ARG;
-  if (!c->chain_valid) return fail(c, XLBOMD_E_STATE, "no Fermi chain cached");
+  if (!c->chain_valid || !c->chain_nonorth)
+    return fail(c, XLBOMD_E_STATE, "no chain of xlbomd_fermi_dm_nonorth cached");
   xlbomd_status st = ensure_nonorth(c);
   if (st) return st;
   double *U = c->no_w[0], *F1p = c->no_w[1], *P1p = c->no_w[2];

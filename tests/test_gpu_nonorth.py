@@ -6,7 +6,8 @@ and 100 atoms for the default overlap and a stronger one, and at 840 atoms.
 Bars: S to 1e-14 (its entries are at most 1; the two sides' exp differ in
 the last bits); Z to 1e-12 of max|Z| and Z^T S Z = I to 1e-12; P, P1 and the
 Pulay forces to 1e-10 of the largest reference entry, with mu to the bound
-the electron count fixes it to, as in tests/test_gpu_parity.py.  The eq. 37
+the electron count fixes it to, as in tests/test_gpu_parity.py.  One atom
+(S = I, no Pulay term) and two atoms (one pair) are the smallest cases.  The eq. 37
 forces for S != I are xlbomd_forces plus the Pulay term, against the oracle's
 two parts.
 """
@@ -107,7 +108,7 @@ def run_case(lib, s, T_e, ov, seed=0, m=3, check_response=True, prec="fp64", p1_
     return out
 
 
-@pytest.mark.parametrize("n_atoms,seed,T_e", [(10, 1, 3000.0), (100, 2, 5000.0)])
+@pytest.mark.parametrize("n_atoms,seed,T_e", [(1, 1, 3000.0), (2, 4, 3000.0), (10, 1, 3000.0), (100, 2, 5000.0)])
 @pytest.mark.parametrize("ov", [OverlapModel(), STRONG], ids=["default", "strong"])
 def test_nonorth_calls_match_oracle(lib, n_atoms, seed, T_e, ov):
     run_case(lib, carbon_cluster(n_atoms, seed), T_e, ov, seed=n_atoms)
@@ -175,5 +176,12 @@ def test_nonorth_arguments(lib):
         P1 = torch.empty_like(S)
         with pytest.raises(lib.XLBOMDError):
             h.dm_response_nonorth(S, S.clone(), P1)           # no chain cached
+        # a chain of the orthogonal call is not the one the response differentiates
+        X = t(np.eye(n) * s.n_elec / n)
+        F = torch.empty_like(S)
+        h.fock(X, F, include_h=True)
+        h.fermi_dm(F, torch.empty_like(S), entropy=False)
+        with pytest.raises(lib.XLBOMDError):
+            h.dm_response_nonorth(F, t(np.eye(n)), P1)
     finally:
         h.close()
