@@ -114,11 +114,11 @@ def test_nonorth_calls_match_oracle(lib, n_atoms, seed, T_e, ov):
     run_case(lib, carbon_cluster(n_atoms, seed), T_e, ov, seed=n_atoms)
 
 
-@pytest.mark.parametrize("prec,p1_bar", [("dm64_bf16x3", 1e-3), ("dm64_bf16x6", 1e-3)])
+@pytest.mark.parametrize("prec,p1_bar", [("dm64_bf16x3", 5e-4), ("dm64_bf16x6", 2e-5)])
 def test_nonorth_mixed_precision(lib, prec, p1_bar):
     # FP64 transforms and density matrix (1e-10), split response chain: the
-    # dm64_bf16x3 response bound of tests/test_gpu_split.py at 100 atoms (the
-    # response error of the DM64 modes is set by the FP32 storage of the chain)
+    # response is held to about three times its measured error (1.5e-4 and
+    # 4.6e-6 of max|P1|), as the split-mode bounds of tests/test_gpu_split.py
     run_case(lib, carbon_cluster(100, 2), 5000.0, OverlapModel(), seed=5, prec=prec, p1_bar=p1_bar)
 
 
