@@ -48,8 +48,10 @@ KERNEL = {"gemm_f64": "k_gemm_f64_big (128 x 128 tiles)",
           "gemm_bf16x3_sym": "k_gemm_split_big<0, 5> (BF16x3, 160 x 160 upper tiles)",
           "gemm_bf16x6": "k_gemm_split_big<1, 7> (BF16x6, 224 x 224 tiles)",
           "gemm_bf16x6_sym": "k_gemm_split_big<1, 5> (BF16x6, 160 x 160 upper tiles)",
-          "gemm_fp16x3": "k_gemm_split_lds<2> (FP16x3, 128 x 128 tiles)",
-          "gemm_fp16x3_sym": "k_gemm_split_lds<2> (FP16x3, 128 x 128 upper tiles)"}
+          "gemm_fp16x3": "k_gemm_split_big<2, 5> (FP16x3, 160 x 160 tiles)",
+          "gemm_fp16x3_sym": "k_gemm_split_big<2, 5> (FP16x3, 160 x 160 upper tiles)"}
+# (the kernels that serve the 840-atom products, n = 3360, under the installed
+# tile table; other orders may take other tile families)
 
 
 def log(*a):

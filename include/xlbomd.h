@@ -405,10 +405,11 @@ xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
  * the Fermi and response chains.  Families: 1 = small tiles (FP64 64 x 64;
  * split 128 x 128), 2 = large tiles (FP64 128 x 128, and 128 x 64 over the
  * upper triangle for symmetric outputs, n % 16 == 0, 128 <= n <= 23170;
- * BF16x3 / BF16x6 224 x 224, and 160 x 160 for symmetric outputs,
- * n % 32 == 0, 128 <= n <= 32767), 3 = medium tiles (BF16x3 / BF16x6 only:
- * the large-tile kernel with 128 x 128 tiles at two workgroups per compute
- * unit, same conditions on n), 0 = the library's built-in rule.
+ * split 224 x 224, and 160 x 160 for symmetric outputs and for FP16x3,
+ * n % 32 == 0, 128 <= n <= 32767), 3 = medium tiles (split only: the
+ * large-tile kernel with 128 x 128 tiles at two workgroups per compute unit,
+ * n % 4 == 0 (FP16x3: n % 32 == 0), 128 <= n <= 32767), 0 = the
+ * library's built-in rule.
  *   rows    HOST, count x 4 ints {prec, sym, n_max, family}: prec is the
  *           arithmetic of the product, numbered as the precision enum's first
  *           four values: 0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3; sym 0 full / 1

@@ -6,9 +6,10 @@ tile table the binding installs with the library (xlbomd_set_tile_table).
 
 For each (precision, output kind) and each order n of the grid, every family
 that can run n is timed (FP64: small and large tiles, large needing
-n % 16 == 0; BF16x3 and BF16x6: small, large and medium tiles, the last two
-needing n % 32 == 0; all large and medium tiles n >= 128; FP16x3 has one
-family), and the fastest is kept; runs of equal choices merge into one row covering (previous n, n].
+n % 16 == 0; the splits: small, large and medium tiles, large needing
+n % 32 == 0 and medium n % 4 == 0 (FP16x3 n % 32 == 0); large and medium
+tiles n >= 128), and the
+fastest is kept; runs of equal choices merge into one row covering (previous n, n].
 Orders between grid points take the next grid point's row; orders a row's
 family cannot run, and orders past the grid, take the library's built-in rule.
 """
@@ -26,7 +27,7 @@ sys.path.insert(0, os.path.dirname(HERE))
 
 from paper_2303_00689_amd import binding  # noqa: E402
 
-PRECS = {0: "fp64", 1: "bf16x3", 2: "bf16x6"}
+PRECS = {0: "fp64", 1: "bf16x3", 2: "bf16x6", 3: "fp16x3"}
 # the ensemble's orbital counts (4 x 20..300 atoms) in steps of 32, then the
 # larger single systems up to 4096
 GRID = list(range(128, 1281, 32)) + [1536, 2048, 2560, 3072, 3360, 4096]
@@ -38,7 +39,7 @@ def tune(reps: int, grid=GRID, log=print):
         for sym in (0, 1):
             choice = []
             fams = {"small": binding.GEMM_SMALL, "large": binding.GEMM_LARGE}
-            if prec in (1, 2):
+            if prec in (1, 2, 3):
                 fams["medium"] = binding.GEMM_MEDIUM
             for n in grid:
                 t = {name: binding.time_gemm(n, prec, sym, f, reps) for name, f in fams.items()}
@@ -72,7 +73,8 @@ def main():
         raise SystemExit(f"{len(rows)} rows exceed the table's {binding.TILE_TABLE_MAX}")
     out = {"device": torch.cuda.get_device_name(0), "reps": args.reps,
            "seconds": time.perf_counter() - t,
-           "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6), sym, n_max, family (1 small, 2 large, 3 medium)]",
+           "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3), sym, n_max, family (1 small, 2 large, "
+                          "3 medium)]",
            "rows": rows, "timings": timings}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)

@@ -33,11 +33,11 @@ struct GemmArgs {
 // Kernel families of an n x n product.  FP64: GEMM_SMALL = 64 x 64 tiles,
 // GEMM_LARGE = 128 x 128 (128 x 64 over the upper triangle for symmetric
 // outputs; n % 16 == 0, n <= 23170).  Split: GEMM_SMALL = 128 x 128 tiles,
-// GEMM_LARGE = 224 x 224 full / 160 x 160 symmetric (BF16x3 and BF16x6 only;
-// n % 32 == 0, n <= 32767), GEMM_MEDIUM = the large-tile kernel with
-// 128 x 128 tiles at two workgroups per compute unit (BF16x3 and BF16x6;
-// n % 4 == 0, a ragged last k panel when n % 32 != 0).  A family that cannot
-// run n falls back to the built-in rule.
+// GEMM_LARGE = 224 x 224 full / 160 x 160 symmetric (FP16x3: 160 x 160 for
+// both; n % 32 == 0, n <= 32767), GEMM_MEDIUM = the large-tile kernel with
+// 128 x 128 tiles at two workgroups per compute unit (n % 4 == 0, a ragged
+// last k panel when n % 32 != 0; FP16x3 n % 32 == 0).  A family that cannot run n falls back to
+// the built-in rule.
 enum { GEMM_AUTO = 0, GEMM_SMALL = 1, GEMM_LARGE = 2, GEMM_MEDIUM = 3 };
 // The tile table's family for a product of order n (prec 0 = FP64, 1..3 as
 // below), or GEMM_AUTO when no row matches.

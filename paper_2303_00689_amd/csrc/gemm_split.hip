@@ -13,8 +13,10 @@
 // Three kernels share these conventions:
 //  * k_gemm_split_bf16x3 (BF16x3) and k_gemm_split_lds (BF16x6, FP16x3):
 //    128 x 128 tiles, any n with n % 4 == 0;
-//  * k_gemm_split_big (BF16x3 and BF16x6, n % 32 == 0, large n): 224 x 224
-//    tiles for full outputs, 160 x 160 for symmetric ones.
+//  * k_gemm_split_big (n % 32 == 0, large n): 224 x 224 tiles for full
+//    outputs, 160 x 160 for symmetric ones (FP16x3: 160 x 160 for both), and
+//    k_gemm_split_mid, the same kernel at 128 x 128 tiles and two workgroups
+//    per compute unit (n % 4 == 0; FP16x3 n % 32 == 0).
 //
 // Tile 128 x 128 per workgroup of 256 threads (2 x 2 wavefronts of 64 x 64,
 // i.e. 4 x 4 MFMA blocks of 16 x 16 each).  K advances by 32 through
@@ -515,10 +517,29 @@ typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 __device__ inline unsigned cvt_pk_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned, __builtin_convertvector((f2){a, b}, bf2));
 }
+// FP16 parts of a pair, rounded to nearest even
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ inline unsigned cvt_pk_f16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f2){a, b}, h2v));
+}
 template <int MODE>
 __device__ inline void split8_pk(const float (&x)[8], us8 (&o)[3]) {
   typedef unsigned u4 __attribute__((ext_vector_type(4)));
   u4 h, l, l2;
+  if (MODE == 2) {
+    // FP16 parts, the low part scaled by 2^11 (out of the subnormal range)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float a = x[2 * v], b = x[2 * v + 1];
+      const unsigned hp = cvt_pk_f16(a, b);
+      const h2v hv = __builtin_bit_cast(h2v, hp);
+      h[v] = hp;
+      l[v] = cvt_pk_f16((a - (float)hv[0]) * 2048.0f, (b - (float)hv[1]) * 2048.0f);
+    }
+    o[0] = __builtin_bit_cast(us8, h);
+    o[1] = __builtin_bit_cast(us8, l);
+    return;
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const float a = x[2 * v], b = x[2 * v + 1];
@@ -560,8 +581,10 @@ __device__ __forceinline__ void static_for(F &&f) {
 // or zeros past the buffer's range) multiply those zeros.
 template <int MODE, int BNB, int STAGES, bool RAGGED = false>
 __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
-  // BF16 splits only: the FP16 split's second accumulator does not fit
-  static_assert(MODE == 0 || MODE == 1, "large-tile kernel: BF16 splits only");
+  // every split; FP16x3 keeps its scaled cross terms in a second accumulator,
+  // which fits the 160- and 128-row tiles, not the 224-row ones
+  static_assert(MODE >= 0 && MODE <= 2, "split mode");
+  static_assert(MODE != 2 || BNB <= 5, "FP16x3: the second accumulator needs BNB <= 5");
   static_assert(STAGES >= 2 && STAGES <= 4, "2 to 4 LDS stages");
   constexpr int BW = 16 * BNB;           // wave tile edge
   constexpr int BT = 2 * BW;             // tile edge
@@ -579,11 +602,17 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   const int wm = (wave >> 1) * BW, wn = (wave & 1) * BW;
   const int fr = lane & 15, fq = lane >> 4;  // fragment row, k group (8 values)
 
-  f4 acc[BNB][BNB];
+  // FP16x3: the cross terms h l + l h, scaled by 2^11, accumulate in acc2
+  constexpr int NB2 = MODE == 2 ? BNB : 1;
+  f4 acc[BNB][BNB], acc2[NB2][NB2];
 #pragma unroll
   for (int r = 0; r < BNB; ++r)
 #pragma unroll
     for (int c = 0; c < BNB; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int r = 0; r < NB2; ++r)
+#pragma unroll
+    for (int c = 0; c < NB2; ++c) acc2[r][c] = f4{0.f, 0.f, 0.f, 0.f};
 
   // Unless RAGGED, n is a multiple of 32 and every k panel is full.  Rows
   // past n are read clamped to row n - 1: they only reach output rows and
@@ -670,6 +699,12 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   };
   // the product terms of row block r and column block c, small terms first
   auto mma = [&](int r, int c, const us8 (&a)[3], const us8 (&bc)[3]) {
+    if (MODE == 2) {
+      acc[r][c] = mfma(a[0], bc[0], acc[r][c], true);
+      acc2[r % NB2][c % NB2] = mfma(a[0], bc[1], acc2[r % NB2][c % NB2], true);
+      acc2[r % NB2][c % NB2] = mfma(a[1], bc[0], acc2[r % NB2][c % NB2], true);
+      return;
+    }
     if (MODE == 1) {
       acc[r][c] = mfma(a[1], bc[1], acc[r][c], false);
       acc[r][c] = mfma(a[0], bc[2], acc[r][c], false);
@@ -681,7 +716,7 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
   };
   constexpr int TERMS = (MODE == 1) ? 6 : 3;
   constexpr int RM = BNB * TERMS;                    // MFMAs per row block
-  constexpr int SPLIT_VALU = (MODE == 1) ? 44 : 24;  // VALU instructions of one split8_pk
+  constexpr int SPLIT_VALU = MODE == 1 ? 44 : (MODE == 2 ? 32 : 24);  // VALU instructions of one split8_pk
 
   // Software pipeline over k panels, a full panel ahead: panel p of B lives
   // in stage p % STAGES, and while panel k is multiplied from registers, the
@@ -788,7 +823,8 @@ __device__ __forceinline__ void gemm_split_big_body(GemmArgs p, int T) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = ib + q;
-        float x = alpha * acc[r][c][q];
+        const float a = MODE == 2 ? acc[r][c][q] + acc2[r % NB2][c % NB2][q] * (1.0f / 2048.0f) : acc[r][c][q];
+        float x = alpha * a;
         if (i < n && j < n) {
           const size_t off = (size_t)i * n + j;
           if (C1) x += b1 * C1[off];
@@ -833,7 +869,8 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   // compute unit (192 of the 256); below that the 128-row tiles fill the chip
   // better
   // the requested family, else the tile table's, else the rule above
-  const int edge = a.sym ? 160 : 224;
+  // FP16x3 takes 160-row tiles for full outputs too (its second accumulator)
+  const int edge = a.sym || prec == 3 ? 160 : 224;
   const int T = (a.n + edge - 1) / edge;
   const int blocks = tile_count(T, a.sym);
   int fam = a.family != GEMM_AUTO ? a.family : table_family(prec, a.sym, a.n);
@@ -842,7 +879,10 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
     const int Tm = (a.n + 127) / 128;
     const int bm = tile_count(Tm, a.sym);
     const bool rag = a.n % 32 != 0;
-    if (prec == 2) {
+    if (prec == 3) {
+      // n % 32 == 0 (family_runs): the ragged FP16x3 instantiation would spill
+      hipLaunchKernelGGL((k_gemm_split_mid<2, false>), dim3(bm), dim3(256), 0, s, a, Tm);
+    } else if (prec == 2) {
       if (rag)
         hipLaunchKernelGGL((k_gemm_split_mid<1, true>), dim3(bm), dim3(256), 0, s, a, Tm);
       else
@@ -857,7 +897,9 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   }
   const bool big = fam == GEMM_AUTO ? (family_runs(prec, GEMM_LARGE, a.n) && blocks >= 192) : fam == GEMM_LARGE;
   if (big) {
-    if (a.sym) {
+    if (prec == 3) {
+      hipLaunchKernelGGL((k_gemm_split_big<2, 5>), dim3(blocks), dim3(256), 0, s, a, T);
+    } else if (a.sym) {
       if (prec == 2)
         hipLaunchKernelGGL((k_gemm_split_big<1, 5>), dim3(blocks), dim3(256), 0, s, a, T);
       else

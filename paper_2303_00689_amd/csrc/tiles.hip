@@ -23,10 +23,13 @@ int table_count = 0;
 
 bool family_runs(int prec, int fam, int n) {
   if (fam == GEMM_AUTO || fam == GEMM_SMALL) return n >= 1;
-  if (fam == GEMM_MEDIUM) return (prec == 1 || prec == 2) && n % 4 == 0 && n >= 128 && n <= 32767;
+  // medium tiles: a ragged last k panel (n % 32 != 0) for BF16x3 and BF16x6
+  // only; FP16x3's ragged instantiation would spill
+  if (fam == GEMM_MEDIUM)
+    return prec >= 1 && prec <= 3 && n % (prec == 3 ? 32 : 4) == 0 && n >= 128 && n <= 32767;
   if (fam != GEMM_LARGE) return false;
   if (prec == 0) return n % 16 == 0 && n >= 128 && n <= 23170;
-  if (prec == 1 || prec == 2) return n % 32 == 0 && n >= 128 && n <= 32767;
+  if (prec >= 1 && prec <= 3) return n % 32 == 0 && n >= 128 && n <= 32767;
   return false;
 }
 

@@ -77,14 +77,14 @@ def test_split_matmul(binding, mode, n_atoms, sym):
     h.close()
 
 
-@pytest.mark.parametrize("mode", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("mode", ["bf16x3", "bf16x6", "fp16x3"])
 @pytest.mark.parametrize("n_atoms", [840, 848])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_split_matmul_large_tiles(binding, mode, n_atoms, sym):
     """n = 3360 (15 tiles of 224 rows, 21 of 160) and n = 3392 (ragged last
-    tiles): sizes at which the BF16 splits run the large-tile kernels, 224-row
-    tiles for full outputs and 160-row tiles for symmetric ones.  A second call
-    gives the same bits."""
+    tiles): sizes at which the splits run the large-tile kernels, 224-row
+    tiles for full outputs and 160-row tiles for symmetric ones (FP16x3:
+    160-row tiles for both).  A second call gives the same bits."""
     s = carbon_cluster(n_atoms, 2)
     h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
     n = s.n_orb

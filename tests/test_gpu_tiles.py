@@ -20,8 +20,8 @@ from synth import carbon_cluster
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MM_BOUND = {"fp64": 1e-13, "bf16x3": 5e-5, "bf16x6": 2.5e-6}
-PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2}
+MM_BOUND = {"fp64": 1e-13, "bf16x3": 5e-5, "bf16x6": 2.5e-6, "fp16x3": 1.5e-6}
+PREC = {"fp64": 0, "bf16x3": 1, "bf16x6": 2, "fp16x3": 3}
 
 
 @pytest.fixture(scope="module")
@@ -45,7 +45,7 @@ def _product(binding, h, A, B, sym, prec, family):
     return C.cpu().numpy()
 
 
-@pytest.mark.parametrize("mode", ["fp64", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3", "bf16x6", "fp16x3"])
 @pytest.mark.parametrize("n_atoms", [32, 37, 100, 264])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_families_agree(binding, mode, n_atoms, sym):
@@ -99,7 +99,8 @@ def test_time_gemm_and_table_arguments(binding):
     assert binding.time_gemm(400, 1, 0, binding.GEMM_LARGE, 1) is None       # 400 % 32 != 0
     assert binding.time_gemm(1040, 0, 1, binding.GEMM_LARGE, 1) > 0.0        # 1040 % 16 == 0
     assert binding.time_gemm(96, 0, 0, binding.GEMM_LARGE, 1) is None        # below 128
-    assert binding.time_gemm(256, 3, 0, binding.GEMM_LARGE, 1) is None       # FP16x3: one family
+    assert binding.time_gemm(256, 3, 0, binding.GEMM_LARGE, 1) > 0.0        # FP16x3: 160-row tiles
+    assert binding.time_gemm(400, 3, 1, binding.GEMM_MEDIUM, 1) is None      # FP16x3 medium: n % 32 == 0
     assert binding.time_gemm(256, 3, 0, binding.GEMM_SMALL, 1) > 0.0
     assert binding.time_gemm(256, 0, 0, binding.GEMM_MEDIUM, 1) is None      # split only
     assert binding.time_gemm(400, 2, 1, binding.GEMM_MEDIUM, 1) > 0.0       # ragged last k panel
