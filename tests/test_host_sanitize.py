@@ -201,7 +201,7 @@ static int api_mode() {
   REPORT("time_gemm_reps_0", xlbomd_time_gemm(256, 0, 0, 1, 0, nullptr, &us));
   REPORT("time_gemm_us_null", xlbomd_time_gemm(256, 0, 0, 1, 1, nullptr, nullptr));
   REPORT("time_gemm_large_ragged", xlbomd_time_gemm(400, 1, 0, 2, 1, nullptr, &us));
-  REPORT("time_gemm_large_fp16", xlbomd_time_gemm(256, 3, 0, 2, 1, nullptr, &us));
+  REPORT("time_gemm_medium_fp16_ragged", xlbomd_time_gemm(400, 3, 1, 3, 1, nullptr, &us));
   return 0;
 }
 
