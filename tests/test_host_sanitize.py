@@ -2,7 +2,7 @@
 
 Every source of the library is compiled with the sanitizers on the host
 pass (device code is built but never launched, so no GPU is needed), with a
-small driver, and the driver exercises what the host side does on its own:
+small C++ test program that exercises what the host side does on its own:
 
 * the implicit-QL solve of the Lanczos tridiagonal on the seeded cases of
   tests/test_host_eig.py plus the largest order and an order past it;
@@ -15,8 +15,8 @@ small driver, and the driver exercises what the host side does on its own:
   any HIP call;
 * the tile table: validation, ordering by n_max, first-match lookup.
 
-A sanitizer finding aborts the driver with a non-zero status and its report
-on stderr, which the test shows.
+A sanitizer finding aborts the test program with a non-zero status and its
+report on stderr, which the test shows.
 """
 
 import os
@@ -392,7 +392,7 @@ def test_spectral_bounds_hold_the_spectrum(driver):
 
 def test_every_entry_point_rejects_bad_arguments_before_hip(driver):
     lines = [ln for ln in run(driver, "api") if ln.strip()]
-    assert len(lines) == 64          # every call of the driver reported
+    assert len(lines) == 64          # every call of the test program reported
     for line in lines:
         name, st = line.split()
         assert int(st) == E_ARG, f"{name} returned {st}"
