@@ -122,6 +122,13 @@ def test_nonorth_mixed_precision(lib, prec, p1_bar):
     run_case(lib, carbon_cluster(100, 2), 5000.0, OverlapModel(), seed=5, prec=prec, p1_bar=p1_bar)
 
 
+def test_nonorth_allones_pattern(lib):
+    # the all-ones 10 x 10 pattern J of the two-centre blocks (every G term on)
+    from synth import ModelParams
+    s = carbon_cluster(100, 2, params=ModelParams(j_pattern="allones"))
+    run_case(lib, s, 5000.0, STRONG, seed=9)
+
+
 def test_nonorth_at_840_atoms(lib):
     s, w = workload("c840")
     run_case(lib, s, w["T_e"], OverlapModel(), seed=7, m=w["m"], check_response=False)
