@@ -170,18 +170,26 @@ def run_ensemble(args, binding, torch, dev):
             st.head, st.mu, st.mu_prev = sn[5], sn[6], sn[7]
         torch.cuda.synchronize()
 
-    def timed(fn):
+    windows = []
+
+    def timed(fn, record=False):
         tot = 0.0
         for k in range(args.warmup + args.steps):
             restore()
-            t0 = time.perf_counter()
+            t0, m0 = time.perf_counter(), time.monotonic_ns()
             fn()
             torch.cuda.synchronize()
             if k >= args.warmup:
                 tot += time.perf_counter() - t0
+                if record:
+                    windows.append((m0, time.monotonic_ns()))
         return tot / args.steps
 
-    t_ens = timed(lambda: binding.ensemble_step(hs, states, 1, report=False))
+    t_ens = timed(lambda: binding.ensemble_step(hs, states, 1, report=False), record=True)
+    if args.windows_json:
+        # CLOCK_MONOTONIC windows of the timed batch steps, to cut a kernel trace
+        with open(args.windows_json, "w") as f:
+            json.dump({"clock": "CLOCK_MONOTONIC ns", "windows": windows}, f)
     log("ensemble steps done")
     # the same batch with the members handed over largest first
     order = sorted(range(len(hs)), key=lambda i: -hs[i].n)
@@ -582,6 +590,9 @@ def main():
                          "its own")
     ap.add_argument("--study-steps", type=int, default=200)
     ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
+    ap.add_argument("--windows-json", default="", metavar="PATH",
+                    help="with --ensemble: write the CLOCK_MONOTONIC window of every timed batch step to PATH "
+                         "(to cut a kernel trace to the batch steps)")
     ap.add_argument("--reports-jsonl", default="", metavar="PATH",
                     help="write every per-step report of the untimed trajectories (free NVE leg, split-vs-FP64 "
                          "legs, the study's) to PATH, one JSON object per step")
