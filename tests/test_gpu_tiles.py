@@ -46,11 +46,11 @@ def _product(binding, h, A, B, sym, prec, family):
 
 
 @pytest.mark.parametrize("mode", ["fp64", "bf16x3", "bf16x6", "fp16x3"])
-@pytest.mark.parametrize("n_atoms", [32, 37, 100, 264])
+@pytest.mark.parametrize("n_atoms", [32, 37, 100, 264, 840])
 @pytest.mark.parametrize("sym", [0, 1])
 def test_families_agree(binding, mode, n_atoms, sym):
     s = carbon_cluster(n_atoms, 3)
-    n = s.n_orb        # 128, 148, 400, 1056: one tile, ragged tiles and k, several
+    n = s.n_orb        # 128, 148, 400, 1056, 3360: one tile, ragged tiles and k, several, full size
     h = binding.Handle(s.n_atoms, s.n_elec, s.onecenter, s.noise, s.params, prec=mode)
     try:
         rng = np.random.default_rng(n + 5)
