@@ -408,8 +408,9 @@ xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
  * split 224 x 224, and 160 x 160 for symmetric outputs and for FP16x3,
  * n % 32 == 0, 128 <= n <= 32767), 3 = medium tiles (split only: the
  * large-tile kernel with 128 x 128 tiles at two workgroups per compute unit,
- * n % 4 == 0 (FP16x3: n % 32 == 0), 128 <= n <= 32767), 0 = the
- * library's built-in rule.
+ * n % 4 == 0 (FP16x3: n % 32 == 0), 128 <= n <= 32767), 4 = compact tiles
+ * (split only: the same kernel with 64 x 64 tiles, n % 4 == 0,
+ * 64 <= n <= 32767), 0 = the library's built-in rule.
  *   rows    HOST, count x 4 ints {prec, sym, n_max, family}: prec is the
  *           arithmetic of the product, numbered as the precision enum's first
  *           four values: 0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3; sym 0 full / 1
@@ -428,7 +429,7 @@ xlbomd_status xlbomd_set_tile_table(const int *rows, int count);
 
 /* Autotuning: the average time, in microseconds, of reps products C = A B of
  * order n in arithmetic prec (0..3 as above) with output kind sym, run by
- * kernel family `family` (1, 2 or 3) on `stream` (hipStream_t, may be null),
+ * kernel family `family` (1 to 4) on `stream` (hipStream_t, may be null),
  * after one warm-up product.  Allocates and frees its own operands (for
  * offline tuning, not for a stepping loop).  Returns XLBOMD_E_ARG if the
  * family cannot run n, XLBOMD_E_HIP if an allocation or launch fails. */

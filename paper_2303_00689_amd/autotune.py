@@ -41,6 +41,7 @@ def tune(reps: int, grid=GRID, log=print):
             fams = {"small": binding.GEMM_SMALL, "large": binding.GEMM_LARGE}
             if prec in (1, 2, 3):
                 fams["medium"] = binding.GEMM_MEDIUM
+                fams["compact"] = binding.GEMM_COMPACT
             for n in grid:
                 t = {name: binding.time_gemm(n, prec, sym, f, reps) for name, f in fams.items()}
                 # the fastest family that can run n (small always can); ties keep the smaller tiles
@@ -49,7 +50,7 @@ def tune(reps: int, grid=GRID, log=print):
                 choice.append((n, fam))
                 timings.append({"prec": pname, "sym": sym, "n": n, **{f"{k}_us": v for k, v in t.items()},
                                 "family": fam})
-            log(f"{pname} sym={sym}: " + " ".join(f"{n}:{'sLM'[f - 1]}" for n, f in choice))
+            log(f"{pname} sym={sym}: " + " ".join(f"{n}:{'sLMC'[f - 1]}" for n, f in choice))
             # merge runs of one family into rows covering (previous n_max, n_max]
             for k, (n, fam) in enumerate(choice):
                 if k + 1 < len(choice) and choice[k + 1][1] == fam:
@@ -74,7 +75,7 @@ def main():
     out = {"device": torch.cuda.get_device_name(0), "reps": args.reps,
            "seconds": time.perf_counter() - t,
            "rows_format": "[prec (0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3), sym, n_max, family (1 small, 2 large, "
-                          "3 medium)]",
+                          "3 medium, 4 compact)]",
            "rows": rows, "timings": timings}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)

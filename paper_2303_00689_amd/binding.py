@@ -36,7 +36,7 @@ SYMBOLS = ["xlbomd_create", "xlbomd_destroy", "xlbomd_last_error", "xlbomd_n_orb
            "xlbomd_pulay_forces"]
 
 # GEMM kernel families of the tile table (xlbomd_set_tile_table)
-GEMM_AUTO, GEMM_SMALL, GEMM_LARGE, GEMM_MEDIUM = 0, 1, 2, 3
+GEMM_AUTO, GEMM_SMALL, GEMM_LARGE, GEMM_MEDIUM, GEMM_COMPACT = 0, 1, 2, 3, 4
 TILE_TABLE_MAX = 256
 # the tile table the autotuner wrote (autotune.py), loaded with the library;
 # XLBOMD_TILE_TABLE names another file, or "none" for the built-in rule

@@ -853,6 +853,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                                                                   int T) {
   gemm_split_big_body<MODE, 4, 3, RAGGED>(p, T);
 }
+// 64-row tiles (BNB = 2) for small orders: 24 KB of LDS and few registers,
+// so several workgroups share a compute unit
+template <int MODE, bool RAGGED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_split_compact(GemmArgs p,
+                                                                                                   int T) {
+  gemm_split_big_body<MODE, 2, 3, RAGGED>(p, T);
+}
 
 // BF16x3, the response-chain mode of the mixed-precision step: two register
 // stages at two waves per SIMD
@@ -875,6 +882,25 @@ void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   const int blocks = tile_count(T, a.sym);
   int fam = a.family != GEMM_AUTO ? a.family : table_family(prec, a.sym, a.n);
   if (!family_runs(prec, fam, a.n)) fam = GEMM_AUTO;
+  if (fam == GEMM_COMPACT) {
+    const int Tc = (a.n + 63) / 64;
+    const int bc = tile_count(Tc, a.sym);
+    const bool rag = a.n % 32 != 0;
+#define XL_COMPACT(M)                                                                              \
+  if (rag)                                                                                         \
+    hipLaunchKernelGGL((k_gemm_split_compact<M, true>), dim3(bc), dim3(256), 0, s, a, Tc);         \
+  else                                                                                             \
+    hipLaunchKernelGGL((k_gemm_split_compact<M, false>), dim3(bc), dim3(256), 0, s, a, Tc);
+    if (prec == 3) {
+      XL_COMPACT(2)
+    } else if (prec == 2) {
+      XL_COMPACT(1)
+    } else {
+      XL_COMPACT(0)
+    }
+#undef XL_COMPACT
+    return;
+  }
   if (fam == GEMM_MEDIUM) {
     const int Tm = (a.n + 127) / 128;
     const int bm = tile_count(Tm, a.sym);

@@ -27,6 +27,7 @@ bool family_runs(int prec, int fam, int n) {
   // only; FP16x3's ragged instantiation would spill
   if (fam == GEMM_MEDIUM)
     return prec >= 1 && prec <= 3 && n % (prec == 3 ? 32 : 4) == 0 && n >= 128 && n <= 32767;
+  if (fam == GEMM_COMPACT) return prec >= 1 && prec <= 3 && n % 4 == 0 && n >= 64 && n <= 32767;
   if (fam != GEMM_LARGE) return false;
   if (prec == 0) return n % 16 == 0 && n >= 128 && n <= 23170;
   if (prec >= 1 && prec <= 3) return n % 32 == 0 && n >= 128 && n <= 32767;
@@ -50,7 +51,7 @@ extern "C" xlbomd_status xlbomd_set_tile_table(const int *rows, int count) {
   for (int i = 0; i < count; ++i) {
     const int *r = rows + 4 * i;
     if (r[0] < 0 || r[0] > 3 || (r[1] != 0 && r[1] != 1) || r[2] < 1 || r[3] < xl::GEMM_AUTO ||
-        r[3] > xl::GEMM_MEDIUM)
+        r[3] > xl::GEMM_COMPACT)
       return XLBOMD_E_ARG;
     tmp[i] = {r[0], r[1], r[2], r[3]};
   }
@@ -65,7 +66,7 @@ extern "C" xlbomd_status xlbomd_set_tile_table(const int *rows, int count) {
 extern "C" xlbomd_status xlbomd_time_gemm(int n, int prec, int sym, int family, int reps, void *stream,
                                           double *us) {
   if (n < 1 || prec < 0 || prec > 3 || (sym != 0 && sym != 1) || reps < 1 || !us ||
-      (family != xl::GEMM_SMALL && family != xl::GEMM_LARGE && family != xl::GEMM_MEDIUM) ||
+      (family < xl::GEMM_SMALL || family > xl::GEMM_COMPACT) ||
       !xl::family_runs(prec, family, n))
     return XLBOMD_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);

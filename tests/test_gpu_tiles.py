@@ -63,6 +63,7 @@ def test_families_agree(binding, mode, n_atoms, sym):
         large = _product(binding, h, A, B, sym, prec, binding.GEMM_LARGE) if large_runs else None
         mid_runs = prec != 0 and binding.time_gemm(n, prec, sym, binding.GEMM_MEDIUM, 1) is not None
         mid = _product(binding, h, A, B, sym, prec, binding.GEMM_MEDIUM) if mid_runs else None
+        cpt = _product(binding, h, A, B, sym, prec, binding.GEMM_COMPACT) if prec != 0 else None
     finally:
         binding.set_tile_table([])
         h.close()
@@ -86,7 +87,7 @@ def test_families_agree(binding, mode, n_atoms, sym):
     ref = A32 @ B32
     S = float((np.abs(A32) @ np.abs(B32)).max())
     acc = 4.0 * np.sqrt(n) * 2.0**-24 * S / np.abs(ref).max()
-    for name, C in (("small", small), ("large", large), ("medium", mid)):
+    for name, C in (("small", small), ("large", large), ("medium", mid), ("compact", cpt)):
         if C is None:
             continue
         err = _rel(C, ref)
@@ -106,7 +107,10 @@ def test_time_gemm_and_table_arguments(binding):
     assert binding.time_gemm(400, 2, 1, binding.GEMM_MEDIUM, 1) > 0.0       # ragged last k panel
     assert binding.time_gemm(402, 1, 1, binding.GEMM_MEDIUM, 1) is None      # 402 % 4 != 0
     assert binding.time_gemm(416, 1, 1, binding.GEMM_MEDIUM, 1) > 0.0
-    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 4]],
+    assert binding.time_gemm(148, 3, 1, binding.GEMM_COMPACT, 1) > 0.0       # ragged, FP16x3 too
+    assert binding.time_gemm(60, 1, 1, binding.GEMM_COMPACT, 1) is None       # below 64
+    assert binding.time_gemm(256, 0, 0, binding.GEMM_COMPACT, 1) is None      # split only
+    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 5]],
                 [[0, 0, 100, 1]] * (binding.TILE_TABLE_MAX + 1)):
         with pytest.raises(binding.XLBOMDError):
             binding.set_tile_table(bad)

@@ -196,7 +196,7 @@ static int api_mode() {
   REPORT("time_gemm_prec_4", xlbomd_time_gemm(256, 4, 0, 1, 1, nullptr, &us));
   REPORT("time_gemm_sym_2", xlbomd_time_gemm(256, 0, 2, 1, 1, nullptr, &us));
   REPORT("time_gemm_family_auto", xlbomd_time_gemm(256, 0, 0, 0, 1, nullptr, &us));
-  REPORT("time_gemm_family_4", xlbomd_time_gemm(256, 0, 0, 4, 1, nullptr, &us));
+  REPORT("time_gemm_family_5", xlbomd_time_gemm(256, 0, 0, 5, 1, nullptr, &us));
   REPORT("time_gemm_medium_fp64", xlbomd_time_gemm(256, 0, 0, 3, 1, nullptr, &us));
   REPORT("time_gemm_reps_0", xlbomd_time_gemm(256, 0, 0, 1, 0, nullptr, &us));
   REPORT("time_gemm_us_null", xlbomd_time_gemm(256, 0, 0, 1, 1, nullptr, nullptr));
@@ -408,7 +408,7 @@ def test_tile_table_orders_and_matches_rows(driver):
     assert out[0] == "0"
     # sorted by n_max, ties in the caller's order, first match wins, none: auto (0)
     assert [int(x) for x in out[1:]] == [1, 1, 2, 2, 0, 1, 0, 1, 0, 0]
-    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 4]], [[0, 0, 100, -1]]):
+    for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 5]], [[0, 0, 100, -1]]):
         text = ["1", " ".join(map(str, bad[0])), "1", "0 0 50"]
         out = [ln for ln in run(driver, "tiles", "\n".join(text) + "\n") if ln.strip()]
         assert out == [str(E_ARG), "0"]
