@@ -409,8 +409,8 @@ xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
  * n % 32 == 0, 128 <= n <= 32767), 3 = medium tiles (split only: the
  * large-tile kernel with 128 x 128 tiles at two workgroups per compute unit,
  * n % 4 == 0 (FP16x3: n % 32 == 0), 128 <= n <= 32767), 4 = compact tiles
- * (split only: the same kernel with 64 x 64 tiles, n % 4 == 0,
- * 64 <= n <= 32767), 0 = the library's built-in rule.
+ * (FP64 32 x 32, n % 4 == 0; split: the large-tile kernel at 64 x 64,
+ * n % 4 == 0, 64 <= n <= 32767), 0 = the library's built-in rule.
  *   rows    HOST, count x 4 ints {prec, sym, n_max, family}: prec is the
  *           arithmetic of the product, numbered as the precision enum's first
  *           four values: 0 FP64, 1 BF16x3, 2 BF16x6, 3 FP16x3; sym 0 full / 1

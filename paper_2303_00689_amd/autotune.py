@@ -5,7 +5,7 @@ tile table the binding installs with the library (xlbomd_set_tile_table).
     python -m paper_2303_00689_amd.autotune [--out PATH] [--reps K]
 
 For each (precision, output kind) and each order n of the grid, every family
-that can run n is timed (FP64: small and large tiles, large needing
+that can run n is timed (FP64: small, large and compact tiles, large needing
 n % 16 == 0; the splits: small, large and medium tiles, large needing
 n % 32 == 0 and medium n % 4 == 0 (FP16x3 n % 32 == 0); large and medium
 tiles n >= 128), and the
@@ -38,10 +38,9 @@ def tune(reps: int, grid=GRID, log=print):
     for prec, pname in PRECS.items():
         for sym in (0, 1):
             choice = []
-            fams = {"small": binding.GEMM_SMALL, "large": binding.GEMM_LARGE}
+            fams = {"small": binding.GEMM_SMALL, "large": binding.GEMM_LARGE, "compact": binding.GEMM_COMPACT}
             if prec in (1, 2, 3):
                 fams["medium"] = binding.GEMM_MEDIUM
-                fams["compact"] = binding.GEMM_COMPACT
             for n in grid:
                 t = {name: binding.time_gemm(n, prec, sym, f, reps) for name, f in fams.items()}
                 # the fastest family that can run n (small always can); ties keep the smaller tiles

@@ -38,9 +38,9 @@ struct GemmArgs {
 // 128 x 128 tiles at two workgroups per compute unit (n % 4 == 0, a ragged
 // last k panel when n % 32 != 0; FP16x3 n % 32 == 0).  A family that cannot run n falls back to
 // the built-in rule.
-// GEMM_COMPACT = the same kernel with 64 x 64 tiles (2 x 2 MFMA blocks per
-// wave) for small orders: four times the workgroups of the medium tiles (split
-// only, n % 4 == 0).
+// GEMM_COMPACT: small tiles for small orders, four times the workgroups of
+// the next family up: split, the large-tile kernel at 64 x 64 (2 x 2 MFMA
+// blocks per wave, n % 4 == 0, n >= 64); FP64, 32 x 32 tiles (n % 4 == 0).
 enum { GEMM_AUTO = 0, GEMM_SMALL = 1, GEMM_LARGE = 2, GEMM_MEDIUM = 3, GEMM_COMPACT = 4 };
 // The tile table's family for a product of order n (prec 0 = FP64, 1..3 as
 // below), or GEMM_AUTO when no row matches.

@@ -154,6 +154,105 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p, int T) {
 }
 
 // ---------------------------------------------------------------------------
+// Compact FP64 GEMM for small orders: 32 x 32 tiles, four waves of one 16 x 16
+// block each, so an order gives four times the workgroups of the 64 x 64
+// kernel (its products are latency-bound there, and more workgroups keep more
+// compute units busy).  Same conventions as k_gemm_f64: K advances by 16
+// through double-buffered LDS panels, loads from clamped in-bounds addresses
+// (n % 4 == 0: a pair of consecutive columns is all in range or all out),
+// zeroed after the loads.
+constexpr int CM = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_f64_c32(GemmArgs p, int T) {
+  const int n = p.n;
+  int bi, bj;
+  tile_of(blockIdx.x, T, p.sym, TILE_GROUP, bi, bj);
+  const int i0 = bi * CM, j0 = bj * CM;
+  __shared__ double As[2][BK][CM];
+  __shared__ double Bs[2][BK][CM];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 16, wn = (wave & 1) * 16;
+  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  const int kt_per = (n + BK - 1) / BK;
+  const int ktiles = kt_per * p.nprod;
+  // A panel (and B not transposed) k (16) x m (32): thread -> (k = tid / 16, m = 2 (tid % 16));
+  // B transposed, rows j (32) x 16 k: thread -> (j = tid / 8, k = 2 (tid % 8))
+  const int la_k = tid >> 4, la_m = (tid & 15) * 2;
+  const int lbt_j = tid >> 3, lbt_k = (tid & 7) * 2;
+  typedef double dd2 __attribute__((ext_vector_type(2)));
+  dd2 ua, ub;
+  bool oka = true, okb = true;
+  auto load = [&](int kt) {
+    const int prod = kt / kt_per;
+    const int k0 = (kt - prod * kt_per) * BK;
+    const double *A = (const double *)p.A[prod];
+    const double *B = (const double *)p.B[prod];
+    {
+      const int k = k0 + la_k, m = i0 + la_m;
+      oka = k < n && m < n;
+      ua = *(const dd2 *)(A + (size_t)(k < n ? k : n - 1) * n + (m < n ? m : n - 2));
+    }
+    if (!p.btrans) {
+      const int k = k0 + la_k, j = j0 + la_m;
+      okb = k < n && j < n;
+      ub = *(const dd2 *)(B + (size_t)(k < n ? k : n - 1) * n + (j < n ? j : n - 2));
+    } else {
+      const int j = j0 + lbt_j, k = k0 + lbt_k;
+      okb = k < n && j < n;
+      ub = *(const dd2 *)(B + (size_t)(j < n ? j : n - 1) * n + (k < n ? k : n - 2));
+    }
+  };
+  auto store = [&](int buf) {
+    As[buf][la_k][la_m] = oka ? ua[0] : 0.0;
+    As[buf][la_k][la_m + 1] = oka ? ua[1] : 0.0;
+    if (!p.btrans) {
+      Bs[buf][la_k][la_m] = okb ? ub[0] : 0.0;
+      Bs[buf][la_k][la_m + 1] = okb ? ub[1] : 0.0;
+    } else {
+      Bs[buf][lbt_k][lbt_j] = okb ? ub[0] : 0.0;
+      Bs[buf][lbt_k + 1][lbt_j] = okb ? ub[1] : 0.0;
+    }
+  };
+
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < ktiles) load(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[buf][kr][wm + (lane & 15)], Bs[buf][kr][wn + (lane & 15)], acc,
+                                                 0, 0, 0);
+    }
+    if (kt + 1 < ktiles) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  const double *C1 = (const double *)p.C1;
+  const double *C2 = (const double *)p.C2;
+  double *out = (double *)p.out;
+  const bool mirror = p.sym && (bi != bj);
+  const int j = j0 + wn + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = i0 + wm + (lane >> 4) + 4 * q;
+    if (i < n && j < n) {
+      const size_t off = (size_t)i * n + j;
+      double x = p.alpha * acc[q];
+      if (C1) x += p.beta1 * C1[off];
+      if (C2) x += p.beta2 * C2[off];
+      if (i == j) x += p.gamma;
+      out[off] = x;
+      if (mirror) out[(size_t)j * n + i] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Large-tile FP64 GEMM: 128 x 128 tiles, four waves of 64 x 64 (4 x 4 blocks
 // of v_mfma_f64_16x16x4f64), two workgroups per compute unit.  Against the
 // 64 x 64 kernel the workgroup reads half the operand bytes per flop from L2.
@@ -371,6 +470,11 @@ void gemm_f64(const GemmArgs &a, hipStream_t s) {
   // n = 1024 on (n % 16 == 0; the buffer range limits n to 23170)
   int fam = a.family != GEMM_AUTO ? a.family : table_family(0, a.sym, a.n);
   if (!family_runs(0, fam, a.n)) fam = GEMM_AUTO;
+  if (fam == GEMM_COMPACT) {
+    const int Tc = (a.n + CM - 1) / CM;
+    hipLaunchKernelGGL(k_gemm_f64_c32, dim3(a.sym ? Tc * (Tc + 1) / 2 : Tc * Tc), dim3(256), 0, s, a, Tc);
+    return;
+  }
   const bool large = fam == GEMM_AUTO ? (a.n % 16 == 0 && a.n >= 1024 && a.n <= 23170) : fam == GEMM_LARGE;
   if (large) {
     const int TI = (a.n + FT - 1) / FT;

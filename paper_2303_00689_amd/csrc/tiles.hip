@@ -27,7 +27,7 @@ bool family_runs(int prec, int fam, int n) {
   // only; FP16x3's ragged instantiation would spill
   if (fam == GEMM_MEDIUM)
     return prec >= 1 && prec <= 3 && n % (prec == 3 ? 32 : 4) == 0 && n >= 128 && n <= 32767;
-  if (fam == GEMM_COMPACT) return prec >= 1 && prec <= 3 && n % 4 == 0 && n >= 64 && n <= 32767;
+  if (fam == GEMM_COMPACT) return prec >= 0 && prec <= 3 && n % 4 == 0 && n >= (prec == 0 ? 4 : 64) && n <= 32767;
   if (fam != GEMM_LARGE) return false;
   if (prec == 0) return n % 16 == 0 && n >= 128 && n <= 23170;
   if (prec >= 1 && prec <= 3) return n % 32 == 0 && n >= 128 && n <= 32767;

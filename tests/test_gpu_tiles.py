@@ -63,13 +63,19 @@ def test_families_agree(binding, mode, n_atoms, sym):
         large = _product(binding, h, A, B, sym, prec, binding.GEMM_LARGE) if large_runs else None
         mid_runs = prec != 0 and binding.time_gemm(n, prec, sym, binding.GEMM_MEDIUM, 1) is not None
         mid = _product(binding, h, A, B, sym, prec, binding.GEMM_MEDIUM) if mid_runs else None
-        cpt = _product(binding, h, A, B, sym, prec, binding.GEMM_COMPACT) if prec != 0 else None
+        cpt = _product(binding, h, A, B, sym, prec, binding.GEMM_COMPACT)
     finally:
         binding.set_tile_table([])
         h.close()
     if mode == "fp64":
         ref = A @ B
         assert _rel(small, ref) <= MM_BOUND[mode]
+        # compact tiles sum every element's k terms in the same order as the
+        # small ones: the same bits on and above the diagonal
+        iu = np.triu_indices(n)
+        assert np.array_equal(small[iu], cpt[iu])
+        if not sym:
+            assert np.array_equal(small, cpt)
         if large is not None:
             assert _rel(large, ref) <= MM_BOUND[mode]
             if sym:
@@ -109,7 +115,7 @@ def test_time_gemm_and_table_arguments(binding):
     assert binding.time_gemm(416, 1, 1, binding.GEMM_MEDIUM, 1) > 0.0
     assert binding.time_gemm(148, 3, 1, binding.GEMM_COMPACT, 1) > 0.0       # ragged, FP16x3 too
     assert binding.time_gemm(60, 1, 1, binding.GEMM_COMPACT, 1) is None       # below 64
-    assert binding.time_gemm(256, 0, 0, binding.GEMM_COMPACT, 1) is None      # split only
+    assert binding.time_gemm(256, 0, 0, binding.GEMM_COMPACT, 1) > 0.0       # FP64 32-row tiles
     for bad in ([[4, 0, 100, 1]], [[0, 2, 100, 1]], [[0, 0, 0, 1]], [[0, 0, 100, 5]],
                 [[0, 0, 100, 1]] * (binding.TILE_TABLE_MAX + 1)):
         with pytest.raises(binding.XLBOMDError):
