@@ -492,6 +492,48 @@ def run_study_lowgap(args, binding, torch, np, dev):
         "split_vs_fp64": cmp}))
 
 
+def run_study_cscan(args, binding, torch, np, dev):
+    """The original XL-BOMD kernel (m = 0, K = -cI) with c = 1 and c = 0.9
+    against the rank-m KSA kernel on the low-gap 840-atom cluster (the
+    comparison of the Results' low-gap fullerene test), FP64, from the same
+    start: per step ||D0[X] - X||_F and T_ion, over --study-steps steps each
+    (each run stops at its first failing status)."""
+    from synth import workload
+    sys_, w = workload("c840_lowgap")
+    X0, init = initial_scf(binding, torch, sys_, w, dev, args.init_mix, args.init_newton)
+    R0 = torch.tensor(sys_.R, dtype=torch.float64, device=dev)
+    runs = {}
+    for label, m, c in (("original_c1", 0, 1.0), ("original_c0.9", 0, 0.9), (f"ksa_rank{w['m']}", w["m"], 1.0)):
+        h = binding.Handle(sys_.n_atoms, sys_.n_elec, sys_.onecenter, sys_.noise, sys_.params, prec="fp64",
+                           T_e=w["T_e"], m=m, dt=w["dt"], kernel_c=c)
+        h.set_geometry(R0)
+        st = md_start(binding, torch, sys_, X0, dev)
+        h.md_init(st)
+        W0, T, E, stop = [], [], [], None
+        t0 = time.perf_counter()
+        for k in range(args.study_steps):
+            status, reps = h.step(st, 1, report=True, check=False)
+            if status != 0:
+                stop = {"step": k + 1, "status": binding.STATUS.get(status, status)}
+                break
+            r = reps[0]
+            W0.append(r["W0"])
+            T.append(r["T_ion"])
+            E.append(r["E_tot"])
+        h.close()
+        torch.cuda.synchronize()
+        runs[label] = {"m": m, "kernel_c": c, "steps_run": len(W0), "stopped": stop, "W0": W0, "T_ion_K": T,
+                       "E_tot": E, "seconds": time.perf_counter() - t0}
+        log(f"  {label}: {len(W0)} steps, W0 {W0[0] if W0 else float('nan'):.3g} -> "
+            f"{W0[-1] if W0 else float('nan'):.3g}, T_ion {T[-1] if T else float('nan'):.0f} K")
+    print(json.dumps({
+        "study": "cscan_c840_lowgap",
+        "workload": (f"840-atom carbon cluster, hopping x0.6, s-p split 4 eV, T_e {w['T_e']:.0f} K, dt {w['dt']} fs, "
+                     f"FP64; from the SCF iterate after {init['mix_steps']} mixing + {init['newton_steps']} "
+                     f"Newton-Krylov steps (residual {init['residual']:.3g})"),
+        "steps": args.study_steps, "init": init, "runs": runs}))
+
+
 def run_study_nonorth(args, binding, torch, np, dev):
     """The non-orthogonal basis at 840 atoms (Methods section 3; eq. 41): the
     time of each call beside its orthogonal counterpart on the same F, with
@@ -581,13 +623,14 @@ def main():
                          "after another")
     ap.add_argument("--hw-queues", type=int, default=16, choices=range(1, 33), metavar="1..32",
                     help="hardware queues of the process in the ensemble mode (GPU_MAX_HW_QUEUES)")
-    ap.add_argument("--study", default="", choices=["", "lowgap", "nonorth"],
+    ap.add_argument("--study", default="", choices=["", "lowgap", "nonorth", "cscan"],
                     help="instead: the low-gap trajectory study (840 atoms, hopping x0.6, s-p split 4 eV, "
                          "10000 K, rank 8): --study-steps NVE steps of --study-prec against FP64 from the "
                          "same start, with drift and force error; or the non-orthogonal calls at 840 atoms "
                          "(overlap, Loewdin Z, density matrix, response, Pulay forces), each timed over "
-                         "--study-steps repetitions beside its orthogonal counterpart; prints one JSON line of "
-                         "its own")
+                         "--study-steps repetitions beside its orthogonal counterpart; or the original XL-BOMD "
+                         "kernel (c = 1, c = 0.9) against KSA on the low-gap cluster, --study-steps steps each; "
+                         "prints one JSON line of its own")
     ap.add_argument("--study-steps", type=int, default=200)
     ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
     ap.add_argument("--windows-json", default="", metavar="PATH",
@@ -634,6 +677,9 @@ def main():
         return
     if args.study == "nonorth":
         run_study_nonorth(args, binding, torch, np, dev)
+        return
+    if args.study == "cscan":
+        run_study_cscan(args, binding, torch, np, dev)
         return
     sys_, w = workload(args.workload)
     n = sys_.n_orb
