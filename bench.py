@@ -534,6 +534,48 @@ def run_study_cscan(args, binding, torch, np, dev):
         "steps": args.study_steps, "init": init, "runs": runs}))
 
 
+def run_study_scf(args, binding, torch, np, dev):
+    """SCF ground states (Results, SCF Optimization): linear mixing
+    X <- X + a (D0[X] - X) at a = 0.9 (the paper's 10 % of the old density),
+    0.5 and 0.1, against rank-2, 3, 6 and 20 KSA Newton-Krylov steps
+    (xlbomd_scf with no mixing), from the uniform density, FP64, to a residual
+    ||D0[X] - X||_F of 1e-8 or --study-steps iterations: iterations, residual
+    reached and milliseconds per iteration, on seeded clusters of 10 and 40
+    atoms."""
+    from synth import carbon_cluster
+    out = {}
+    for na, seed in ((10, 1), (40, 3)):
+        sys_ = carbon_cluster(na, seed)
+        n = sys_.n_orb
+        h = binding.Handle(sys_.n_atoms, sys_.n_elec, sys_.onecenter, sys_.noise, sys_.params, prec="fp64",
+                           T_e=3000.0, m=3)
+        h.set_geometry(torch.tensor(sys_.R, dtype=torch.float64, device=dev))
+        res = {}
+        for label, kw in (("mixing_0.9", dict(max_iter=0, mix=0.9, max_mix=args.study_steps)),
+                          ("mixing_0.5", dict(max_iter=0, mix=0.5, max_mix=args.study_steps)),
+                          ("mixing_0.1", dict(max_iter=0, mix=0.1, max_mix=args.study_steps)),
+                          ("ksa_rank2", dict(m=2, max_iter=args.study_steps, max_mix=0)),
+                          ("ksa_rank3", dict(m=3, max_iter=args.study_steps, max_mix=0)),
+                          ("ksa_rank6", dict(m=6, max_iter=args.study_steps, max_mix=0)),
+                          ("ksa_rank20", dict(m=20, max_iter=args.study_steps, max_mix=0))):
+            X = torch.eye(n, dtype=torch.float64, device=dev) * (sys_.n_elec / n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = h.scf(X, tol=1e-8, mix_tol=0.0, allow_noconv=True, history=2 * args.study_steps + 2,
+                      **({"m": 2} | kw))
+            torch.cuda.synchronize()
+            it = r["mix_steps"] + r["newton_steps"]
+            sec = time.perf_counter() - t0
+            res[label] = {"iterations": it, "residual": r["residual"], "converged": r["residual"] <= 1e-8,
+                          "evaluations": r["evaluations"], "responses": r["responses"],
+                          "ms_per_iteration": 1e3 * sec / max(it, 1), "history": r["history"][:40]}
+            log(f"  {na} atoms {label}: {it} iterations, residual {r['residual']:.2e}, "
+                f"{1e3 * sec / max(it, 1):.2f} ms/iteration")
+        h.close()
+        out[f"c{na}"] = res
+    print(json.dumps({"study": "scf", "tolerance": 1e-8, "max_iterations": args.study_steps, "runs": out}))
+
+
 def run_study_nonorth(args, binding, torch, np, dev):
     """The non-orthogonal basis at 840 atoms (Methods section 3; eq. 41): the
     time of each call beside its orthogonal counterpart on the same F, with
@@ -623,14 +665,15 @@ def main():
                          "after another")
     ap.add_argument("--hw-queues", type=int, default=16, choices=range(1, 33), metavar="1..32",
                     help="hardware queues of the process in the ensemble mode (GPU_MAX_HW_QUEUES)")
-    ap.add_argument("--study", default="", choices=["", "lowgap", "nonorth", "cscan"],
+    ap.add_argument("--study", default="", choices=["", "lowgap", "nonorth", "cscan", "scf"],
                     help="instead: the low-gap trajectory study (840 atoms, hopping x0.6, s-p split 4 eV, "
                          "10000 K, rank 8): --study-steps NVE steps of --study-prec against FP64 from the "
                          "same start, with drift and force error; or the non-orthogonal calls at 840 atoms "
                          "(overlap, Loewdin Z, density matrix, response, Pulay forces), each timed over "
                          "--study-steps repetitions beside its orthogonal counterpart; or the original XL-BOMD "
                          "kernel (c = 1, c = 0.9) against KSA on the low-gap cluster, --study-steps steps each; "
-                         "prints one JSON line of its own")
+                         "or SCF by linear mixing against rank-2/3 KSA on 10 and 40 atoms, at most --study-steps "
+                         "iterations each; prints one JSON line of its own")
     ap.add_argument("--study-steps", type=int, default=200)
     ap.add_argument("--study-prec", default="fp16x3", choices=MODES)
     ap.add_argument("--windows-json", default="", metavar="PATH",
@@ -680,6 +723,9 @@ def main():
         return
     if args.study == "cscan":
         run_study_cscan(args, binding, torch, np, dev)
+        return
+    if args.study == "scf":
+        run_study_scf(args, binding, torch, np, dev)
         return
     sys_, w = workload(args.workload)
     n = sys_.n_orb

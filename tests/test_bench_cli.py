@@ -24,7 +24,7 @@ def test_help_lists_the_legs():
     r = _run("--help")
     assert r.returncode == 0
     for flag in ("--steps", "--warmup", "--fp64-steps", "--free-steps", "--report-steps", "--compare-steps",
-                 "--ensemble", "--hw-queues", "--study", "--reports-jsonl", "--windows-json", "cscan", "nonorth"):
+                 "--ensemble", "--hw-queues", "--study", "--reports-jsonl", "--windows-json", "cscan", "nonorth", "scf"):
         assert flag in r.stdout
 
 
