@@ -430,8 +430,10 @@ xlbomd_status xlbomd_set_tile_table(const int *rows, int count);
 /* Autotuning: the average time, in microseconds, of reps products C = A B of
  * order n in arithmetic prec (0..3 as above) with output kind sym, run by
  * kernel family `family` (1 to 4) on `stream` (hipStream_t, may be null),
- * after one warm-up product.  Allocates and frees its own operands (for
- * offline tuning, not for a stepping loop).  Returns XLBOMD_E_ARG if the
+ * after one warm-up product.  Allocates and frees its own operands, filled
+ * with one constant byte pattern (for offline tuning, not for a stepping
+ * loop); random operands draw more power and run up to ~12% slower, so the
+ * times rank the families rather than predict a step.  Returns XLBOMD_E_ARG if the
  * family cannot run n, XLBOMD_E_HIP if an allocation or launch fails. */
 xlbomd_status xlbomd_time_gemm(int n, int prec, int sym, int family, int reps, void *stream, double *us);
 
