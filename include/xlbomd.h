@@ -398,7 +398,9 @@ xlbomd_status xlbomd_profile(xlbomd_handle h, int enable);
  * BF16x6, [6] / [7] FP16x3 (work = executed MFMA flops: 2n^3 per product, n^3
  * for a product with symmetric output, times the 3 or 6 MFMA products a split
  * product runs), [8] Fock build and [9] forces (work = algorithmic HBM bytes:
- * 220 per atom pair plus 16 n^2). */
+ * 220 per atom pair of FP32 noise, 128 per atom block on or above the
+ * diagonal of each symmetric input read (P; P0 and X), and 8 n^2 for the F
+ * the Fock build writes). */
 xlbomd_status xlbomd_profile_read(xlbomd_handle h, double *out);
 
 /* GEMM tile table (process-wide): which kernel family runs an n x n product of

@@ -367,15 +367,23 @@ PairSys pairsys(xlbomd_ctx *c);
 
 // algorithmic HBM bytes of one pair pass: the FP32 noise blocks, two n x n FP64
 // matrices read or written (P and F, or P0 and X)
-double pair_pass_bytes(xlbomd_ctx *c) {
+// Algorithmic HBM bytes of the pair passes.  Both read the 55 FP32 noise
+// values of every atom pair (220 B) and, of each symmetric n x n input, only
+// the atom blocks on and above the diagonal (16 doubles per block).  The Fock
+// build writes all of F; the force pass writes O(N) values.
+double fock_bytes(xlbomd_ctx *c) {
   const double np = 0.5 * c->N * (c->N - 1.0);
-  return 220.0 * np + 16.0 * (double)c->n2;
+  return 220.0 * np + 128.0 * (np + c->N) + 8.0 * (double)c->n2;
+}
+double force_bytes(xlbomd_ctx *c) {
+  const double np = 0.5 * c->N * (c->N - 1.0);
+  return 220.0 * np + 2.0 * 128.0 * (np + c->N);
 }
 
 void fock_t(xlbomd_ctx *c, const double *P, double *F, int include_h) {
   const int e = prof_begin(c);
   fock(pairsys(c), P, F, include_h, c->part, c->s);
-  prof_end(c, e, PC_FOCK, pair_pass_bytes(c));
+  prof_end(c, e, PC_FOCK, fock_bytes(c));
 }
 
 PairSys pairsys(xlbomd_ctx *c) {
@@ -1160,7 +1168,7 @@ xlbomd_status energy_forces(xlbomd_ctx *c, const double *P0, const double *X, do
                             double e[3]) {
   const int ev = prof_begin(c);
   forces(pairsys(c), P0, X, frc, c->dscal + S_ENER, c->pk3, c->fpart, c->epart, c->s);
-  prof_end(c, ev, PC_FORCE, pair_pass_bytes(c));
+  prof_end(c, ev, PC_FORCE, force_bytes(c));
   if (e) return get_scalars(c, S_ENER, 3, e);
   return XLBOMD_OK;
 }

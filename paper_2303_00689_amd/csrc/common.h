@@ -97,7 +97,7 @@ struct PairSys {
   int n_tiles;             // atom tiles of 16
   const double *R;         // n_atoms x 3
   const double *onecenter; // n_atoms x 5
-  const float *noise_t;    // tile-major noise [tilepair][55][256]
+  const float *noise_t;    // tile-major noise, float4 groups [tilepair][14][256][4], 16-byte aligned
   const double *j55;       // device, 55
   double eps_s, eps_p, t0, r0_hop, lam_hop, coul_k, coul_a, noise_amp, z_core, a_rep, r0_rep,
       rho_rep;

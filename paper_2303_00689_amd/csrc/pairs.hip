@@ -3,10 +3,13 @@
 //
 // Work is organised in tiles of 16 x 16 atom pairs (upper triangle of atom
 // tiles, 256 threads, one thread per pair A < B).  The R-independent factor
-// noise_AB of every two-centre block is stored tile-major,
-//   noise_t[(tilepair * 55 + k) * 256 + slot],  slot = 16 * a_local + b_local,
-// so that the 55 loads of a tile are 55 fully coalesced 1 KiB rows.  W_AB is
-// formed in registers as gamma(R) * (J[k] + noise_amp * noise[k]).
+// noise_AB of every two-centre block is stored tile-major in groups of four
+// integrals, as float4 elements
+//   noise_t4[(tilepair * 14 + q) * 256 + slot] = noise[4q .. 4q + 3],
+//   slot = 16 * a_local + b_local (the 56th value is a zero pad),
+// so that a tile's 55 values reach each thread in 14 loads of 16 bytes, each
+// a fully coalesced 4 KiB row of the workgroup.  W_AB is formed in registers
+// as gamma(R) * (J[k] + noise_amp * noise[k]).
 //
 // Per-atom sums over all partners (the two-centre Coulomb term of the
 // diagonal blocks, the force on each atom) are reduced deterministically:
@@ -20,6 +23,7 @@ namespace xl {
 namespace {
 
 constexpr int TA = 16;
+typedef double d2v __attribute__((ext_vector_type(2)));
 
 // packed orbital pairs of one atom (row-major upper triangle of the 4x4 block)
 __device__ constexpr int PM[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
@@ -39,7 +43,9 @@ __device__ inline void tri_tile(int bid, int T, int &ta, int &tb) {
   tb = r + (bid - start);
 }
 
-__global__ void k_repack(int N, int T, const float *src, float *dst) {
+constexpr int NQ = 14;  // float4 groups of the 55 noise values (one pad)
+
+__global__ void k_repack(int N, int T, const float *src, float4 *dst) {
   const int tp = blockIdx.x;
   int ta, tb;
   tri_tile(tp, T, ta, tb);
@@ -47,8 +53,27 @@ __global__ void k_repack(int N, int T, const float *src, float *dst) {
   const int A = ta * TA + slot / TA, B = tb * TA + slot % TA;
   const bool valid = A < N && B < N && A < B;
   const size_t p = valid ? ((size_t)A * N - (size_t)A * (A + 1) / 2 + (B - A - 1)) : 0;
-  for (int k = 0; k < 55; ++k)
-    dst[((size_t)tp * 55 + k) * 256 + slot] = valid ? src[p * 55 + k] : 0.0f;
+  for (int q = 0; q < NQ; ++q) {
+    float v[4];
+    for (int e = 0; e < 4; ++e) {
+      const int k = 4 * q + e;
+      v[e] = valid && k < 55 ? src[p * 55 + k] : 0.0f;
+    }
+    dst[((size_t)tp * NQ + q) * 256 + slot] = float4{v[0], v[1], v[2], v[3]};
+  }
+}
+
+// the 55 noise values of the calling thread's pair (14 loads of 16 bytes)
+__device__ inline void load_noise(const float *noise_t, int tp, int slot, float nz[4 * NQ]) {
+  const float4 *src = reinterpret_cast<const float4 *>(noise_t) + (size_t)tp * NQ * 256 + slot;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const float4 v = src[(size_t)q * 256];
+    nz[4 * q] = v.x;
+    nz[4 * q + 1] = v.y;
+    nz[4 * q + 2] = v.z;
+    nz[4 * q + 3] = v.w;
+  }
 }
 
 struct PairGeo {
@@ -138,13 +163,14 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
       pA[r] = spk[al * 10 + r];
       pB[r] = spk[(TA + bl) * 10 + r];
     }
-    const float *nz = ps.noise_t + (size_t)tp * 55 * 256 + slot;
+    float nz[4 * NQ];
+    load_noise(ps.noise_t, tp, slot, nz);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
 #pragma unroll
       for (int c = r; c < 10; ++c) {
         const int k = pidx55(r, c);
-        const double w = g.gamma * (ps.j55[k] + ps.noise_amp * (double)nz[(size_t)k * 256]);
+        const double w = g.gamma * (ps.j55[k] + ps.noise_amp * (double)nz[k]);
         // position (r, c): r is A's orbital pair, c is B's
         cA[r] += w * pB[c];
         cB[c] += w * pA[r];
@@ -217,7 +243,8 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
   __syncthreads();
   // 8 threads per row, two consecutive columns per store: 128 contiguous
   // bytes of a row per store instruction, for the block and for its transpose
-  // (a column of the staged block)
+  // (a column of the staged block).  Non-temporal stores: F streams out and
+  // is not read again by the build.
   const int k8 = slot & 7;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
@@ -231,9 +258,9 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
       const int cc = 16 * s8 + 2 * k8;  // two consecutive columns of one atom
       const int ca = tb * TA + cc / 4, cb = ta * TA + cc / 4;
       if (ra < N && ca < N && (ta != tb || ra != ca))
-        *(double2 *)(F + ga + cc) = double2{ft[row * FTP + cc], ft[row * FTP + cc + 1]};
+        __builtin_nontemporal_store(d2v{ft[row * FTP + cc], ft[row * FTP + cc + 1]}, (d2v *)(F + ga + cc));
       if (ta != tb && rb < N && cb < N)
-        *(double2 *)(F + gb + cc) = double2{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]};
+        __builtin_nontemporal_store(d2v{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]}, (d2v *)(F + gb + cc));
     }
   }
 }
@@ -352,7 +379,8 @@ __global__ __launch_bounds__(256) void k_force_pairs(PairSys ps, int n, const do
     for (int k = 0; k < 3; ++k)
       dE[k] = 2.0 * g.dt * phi * g.l[k] + 2.0 * g.t / g.r * (gv[k] - gl * g.l[k]);
     // terms linear in W, evaluated with the base block b = J + noise_amp * noise
-    const float *nz = ps.noise_t + (size_t)tp * 55 * 256 + slot;
+    float nz[4 * NQ];
+    load_noise(ps.noise_t, tp, slot, nz);
     const double Z = ps.z_core;
     double bcore = 0.0, bee = 0.0, bnn = 0.0;
 #pragma unroll
@@ -360,7 +388,7 @@ __global__ __launch_bounds__(256) void k_force_pairs(PairSys ps, int n, const do
 #pragma unroll
       for (int c = r; c < 10; ++c) {
         const int k = pidx55(r, c);
-        const double b = ps.j55[k] + ps.noise_amp * (double)nz[(size_t)k * 256];
+        const double b = ps.j55[k] + ps.noise_amp * (double)nz[k];
         // position (r, c)
         double ex = 0.0;
         {
@@ -427,30 +455,39 @@ __global__ void k_zero(size_t m, double *p) {
     p[i] = 0.0;
 }
 
+// one thread per (atom, packed orbital pair)
 __global__ void k_pack3(int N, int n, const double *P0, const double *X, double *pk3) {
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= N) return;
-  for (int r = 0; r < 10; ++r) {
-    const int m = PM[r], q = PN[r];
-    const size_t off = (size_t)(4 * A + m) * n + 4 * A + q;
-    const double f = (m != q) ? 2.0 : 1.0;
-    pk3[A * 10 + r] = f * P0[off];
-    pk3[(size_t)N * 10 + A * 10 + r] = f * X[off];
-    pk3[(size_t)2 * N * 10 + A * 10 + r] = f * (P0[off] - 0.5 * X[off]);
-  }
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= 10 * N) return;
+  const int A = v / 10, r = v % 10;
+  const int m = PM[r], q = PN[r];
+  const size_t off = (size_t)(4 * A + m) * n + 4 * A + q;
+  const double f = (m != q) ? 2.0 : 1.0;
+  pk3[v] = f * P0[off];
+  pk3[(size_t)N * 10 + v] = f * X[off];
+  pk3[(size_t)2 * N * 10 + v] = f * (P0[off] - 0.5 * X[off]);
 }
 
-// per-atom: total force, and per-atom energies (on-site h, one-centre ee)
-__global__ void k_force_atoms(PairSys ps, int n, const double *P0, const double *X,
-                              const double *fpart, double *frc, double *eatom) {
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+// per-atom: total force, and per-atom energies (on-site h, one-centre ee).
+// One wavefront per atom: lane l adds the force partials of partner tiles
+// l, l + 64, ... in that order, then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(256) void k_force_atoms(PairSys ps, int n, const double *P0, const double *X,
+                                                     const double *fpart, double *frc, double *eatom) {
+  const int A = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int N = ps.n_atoms;
   if (A >= N) return;
-  for (int k = 0; k < 3; ++k) {
-    double v = 0.0;
-    for (int t = 0; t < ps.n_tiles; ++t) v += fpart[((size_t)t * N + A) * 3 + k];
-    frc[3 * A + k] = v;  // partials already hold -dE/dR of their pairs
-  }
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int t = lane; t < ps.n_tiles; t += 64)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] += fpart[((size_t)t * N + A) * 3 + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) f[k] += __shfl_xor(f[k], o, 64);
+  if (lane != 0) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) frc[3 * A + k] = f[k];  // partials already hold -dE/dR of their pairs
   double Xd[4][4], G1[4][4];
   double e_on = 0.0, e_1c = 0.0;
   for (int i = 0; i < 4; ++i)
@@ -497,12 +534,13 @@ __global__ void k_energy_final(int ntp, const double *epart, int N, const double
 
 size_t noise_tile_floats(int n_atoms) {
   const int T = (n_atoms + TA - 1) / TA;
-  return (size_t)T * (T + 1) / 2 * 55 * 256;
+  return (size_t)T * (T + 1) / 2 * 4 * NQ * 256;
 }
 
 void repack_noise(int n_atoms, const float *src, float *dst, hipStream_t s) {
   const int T = (n_atoms + TA - 1) / TA;
-  hipLaunchKernelGGL(k_repack, dim3(T * (T + 1) / 2), dim3(256), 0, s, n_atoms, T, src, dst);
+  hipLaunchKernelGGL(k_repack, dim3(T * (T + 1) / 2), dim3(256), 0, s, n_atoms, T, src,
+                     reinterpret_cast<float4 *>(dst));
 }
 
 void fock(const PairSys &ps, const double *P, double *F, int include_h, double *part, hipStream_t s) {
@@ -534,15 +572,14 @@ void forces(const PairSys &ps, const double *P0, const double *X, double *frc, d
   const int N = ps.n_atoms, n = 4 * N, T = ps.n_tiles;
   const int ntp = T * (T + 1) / 2;
   double *eatom = epart + (size_t)ntp * 5;
-  hipLaunchKernelGGL(k_pack3, dim3((N + 127) / 128), dim3(128), 0, s, N, n, P0, X, pk3);
+  hipLaunchKernelGGL(k_pack3, dim3((10 * N + 255) / 256), dim3(256), 0, s, N, n, P0, X, pk3);
   if (N > 1) {
     hipLaunchKernelGGL(k_force_pairs, dim3(ntp), dim3(256), 0, s, ps, n, P0, X, pk3, fpart, epart);
   } else {
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)3 * N * T, fpart);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (size_t)5 * ntp, epart);
   }
-  hipLaunchKernelGGL(k_force_atoms, dim3((N + 127) / 128), dim3(128), 0, s, ps, n, P0, X, fpart, frc,
-                     eatom);
+  hipLaunchKernelGGL(k_force_atoms, dim3((N + 3) / 4), dim3(256), 0, s, ps, n, P0, X, fpart, frc, eatom);
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, s, ntp, epart, N, eatom, e);
 }
 
