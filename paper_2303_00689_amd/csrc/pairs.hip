@@ -23,7 +23,6 @@ namespace xl {
 namespace {
 
 constexpr int TA = 16;
-typedef double d2v __attribute__((ext_vector_type(2)));
 
 // packed orbital pairs of one atom (row-major upper triangle of the 4x4 block)
 __device__ constexpr int PM[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
@@ -243,8 +242,7 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
   __syncthreads();
   // 8 threads per row, two consecutive columns per store: 128 contiguous
   // bytes of a row per store instruction, for the block and for its transpose
-  // (a column of the staged block).  Non-temporal stores: F streams out and
-  // is not read again by the build.
+  // (a column of the staged block)
   const int k8 = slot & 7;
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
@@ -258,9 +256,9 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
       const int cc = 16 * s8 + 2 * k8;  // two consecutive columns of one atom
       const int ca = tb * TA + cc / 4, cb = ta * TA + cc / 4;
       if (ra < N && ca < N && (ta != tb || ra != ca))
-        __builtin_nontemporal_store(d2v{ft[row * FTP + cc], ft[row * FTP + cc + 1]}, (d2v *)(F + ga + cc));
+        *(double2 *)(F + ga + cc) = double2{ft[row * FTP + cc], ft[row * FTP + cc + 1]};
       if (ta != tb && rb < N && cb < N)
-        __builtin_nontemporal_store(d2v{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]}, (d2v *)(F + gb + cc));
+        *(double2 *)(F + gb + cc) = double2{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]};
     }
   }
 }
