@@ -893,8 +893,17 @@ xlbomd_status response(xlbomd_ctx *c, const double *F1, double *P1, const double
   } else {
     axpby((int)c->n2, sc, F1, 0.0, nullptr, V1, 0, s);
   }
-  mr(c, Vr, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, Vr);          // V V1 + V1 V
-  mr(c, Sr, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, Sr);          // S dS + dS S
+  if (i32 && split_sum_by_transpose(c->prec_rs, n)) {
+    // A B + B A = (2 A B + (2 A B)^T) / 2 for symmetric A, B (V1 and dS are
+    // symmetric: F1, and the average itself)
+    mr(c, Vr, V1, dS, 2.0, 0);                                                          // V V1 + V1 V
+    symmetrize(n, dS, 1, s);
+    mr(c, Sr, dS, dS2, 2.0, 0);                                                         // S dS + dS S
+    symmetrize(n, dS2, 1, s);
+  } else {
+    mr(c, Vr, V1, dS, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, V1, Vr);          // V V1 + V1 V
+    mr(c, Sr, dS, dS2, 1.0, 1, nullptr, 0.0, nullptr, 0.0, 0.0, 0, dS, Sr);          // S dS + dS S
+  }
   void *dB = c->w[7], *dP = G;
   axpby((int)c->n2, TC3, dS, TC4, dS2, dB, i32, s);                                       // dB
   // dP = c1 dS + dS2 B + S2 dB (symmetric as a sum: S2 B = B S2)

@@ -50,6 +50,13 @@ bool family_runs(int prec, int fam, int n);
 void gemm_f64(const GemmArgs &a, hipStream_t s);
 // Split-precision GEMM on FP32 storage (prec: 1 = BF16x3, 2 = BF16x6, 3 = FP16x3).
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s);
+// Whether A B + B A (A, B symmetric, split precision prec) is cheaper as one
+// full-output product 2 A B and the in-place transpose average than as one
+// two-product launch over the upper triangle: where both run the large tiles
+// (224 rows full, 160 symmetric; BF16x3 and BF16x6) and the 224-row tiles of
+// the full output fit one round of the 256 compute units, the full-output
+// tiles' higher MFMA rate outweighs the extra pass over the result.
+bool split_sum_by_transpose(int prec, int n);
 
 // ------------------------------------------------------------- BLAS-1 (FP64 or FP32)
 // Elementwise kernels operate on n*n matrices of the given element type

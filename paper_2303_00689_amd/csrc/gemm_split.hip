@@ -870,6 +870,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 }  // namespace
 
+// whether gemm_split runs the large-tile kernel for this product (the rule below)
+static bool split_runs_large(int prec, int sym, int n) {
+  const int edge = sym || prec == 3 ? 160 : 224;
+  const int T = (n + edge - 1) / edge;
+  int fam = table_family(prec, sym, n);
+  if (!family_runs(prec, fam, n)) fam = GEMM_AUTO;
+  if (fam == GEMM_AUTO) return family_runs(prec, GEMM_LARGE, n) && tile_count(T, sym) >= 192;
+  return fam == GEMM_LARGE;
+}
+
+bool split_sum_by_transpose(int prec, int n) {
+  if (prec != 1 && prec != 2) return false;
+  const int T = (n + 223) / 224;
+  return T * T <= 256 && split_runs_large(prec, 0, n) && split_runs_large(prec, 1, n);
+}
+
 void gemm_split(const GemmArgs &a, int prec, hipStream_t s) {
   // large tiles (224 rows for full outputs, 160 for symmetric ones) need
   // n % 32 == 0 and pay once they give at least 3/4 of a workgroup per
