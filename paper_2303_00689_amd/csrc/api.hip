@@ -111,42 +111,6 @@ __global__ void k_sum_fixed(int m, const double *part, double *out) {
   *out = s;
 }
 
-// out = v - sum_j c_j V_j (Gram-Schmidt sweep), c on device.  Two elements per
-// thread per step (16-byte loads), the loads of all k + 1 streams issued before
-// the first product; KB (4, 8 or MMAX) bounds k for the register arrays.  The
-// subtractions run in j order as in a plain loop.
-template <int KB>
-__global__ __launch_bounds__(256) void k_orth(size_t n2, int k, const double *v, const double *const *Vs,
-                                              const double *c, double *out) {
-  __shared__ double cs[MMAX];
-  __shared__ const double *vp[MMAX];
-  if (threadIdx.x < k) {
-    cs[threadIdx.x] = c[threadIdx.x];
-    vp[threadIdx.x] = Vs[threadIdx.x];
-  }
-  __syncthreads();
-  const size_t h = n2 / 2, stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < h; q += stride) {
-    double2 x = ((const double2 *)v)[q], w[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) w[j] = ((const double2 *)vp[j])[q];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      if (j < k) {
-        x.x -= cs[j] * w[j].x;
-        x.y -= cs[j] * w[j].y;
-      }
-    }
-    ((double2 *)out)[q] = x;
-  }
-  if ((n2 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    double x = v[n2 - 1];
-    for (int j = 0; j < k; ++j) x -= cs[j] * vp[j][n2 - 1];
-    out[n2 - 1] = x;
-  }
-}
-
 // copy the dots results into row k of O and rhs; <W_k, W_k> is the squared
 // norm of the next Krylov source
 __global__ void k_store_orow(int k, const double *d, double *O, double *rhs, double *src_sq) {
@@ -1059,7 +1023,7 @@ xlbomd_status ensure_krylov(xlbomd_ctx *c, int m) {
     if (!dev_alloc((void **)&c->Vk[k], c->n2 * 8) || !dev_alloc((void **)&c->Wk[k], c->n2 * 8))
       return fail(c, XLBOMD_E_NOMEM, "Krylov workspace allocation failed");
     ++c->kalloc;
-    // the basis pointers live on the device for k_orth / lincomb; uploading
+    // the basis pointers live on the device for orth_dots / lincomb; uploading
     // them once here keeps pageable copies out of the step
     if (c->kalloc == m &&
         hipMemcpy(c->dptr, c->Vk, sizeof(double *) * c->kalloc, hipMemcpyHostToDevice) != hipSuccess)
@@ -1107,10 +1071,11 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
   double kres[3] = {0.0, 0.0, 0.0};
   for (; k < m;) {
     // classical Gram-Schmidt applied twice; the sweeps read the previous W (or
-    // W0) in place and write the two work vectors in turn
+    // W0) in place and write the two work vectors in turn.  The first sweep's
+    // update also forms the second sweep's coefficients <V_j, v>, and the
+    // second's the squared norm, in the same pass over the elements.
     const double *cur = src;
-    double *out = v;
-    for (int sweep = 0; sweep < 2 && k > 0; ++sweep) {
+    if (k > 0) {
       const void *xs[MMAX], *ys[MMAX];
       for (int j = 0; j < k; ++j) {
         xs[j] = c->Vk[j];
@@ -1118,17 +1083,10 @@ xlbomd_status krylov(xlbomd_ctx *c, const double *X, const double *P0, int m, do
       }
       for (int j0 = 0; j0 < k; j0 += 16)
         dots(n2, std::min(16, k - j0), xs + j0, ys + j0, c->dscal + S_ORTH + j0, 0, c->red, s);
-      if (k <= 4)
-        hipLaunchKernelGGL(k_orth<4>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH, out);
-      else if (k <= 8)
-        hipLaunchKernelGGL(k_orth<8>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH, out);
-      else
-        hipLaunchKernelGGL(k_orth<MMAX>, dim3(2048), dim3(256), 0, s, c->n2, k, cur, c->dptr, c->dscal + S_ORTH,
-                           out);
-      cur = out;
-      out = out == v ? tmp : v;
-    }
-    {
+      orth_dots(n2, k, cur, c->dptr, c->dscal + S_ORTH, v, 0, c->dscal + S_ORTH, c->red, s);
+      orth_dots(n2, k, v, c->dptr, c->dscal + S_ORTH, tmp, 1, ctl, c->red, s);
+      cur = tmp;
+    } else {
       const void *a[1] = {cur};
       dots(n2, 1, a, a, ctl, 0, c->red, s);
     }

@@ -236,6 +236,79 @@ __global__ __launch_bounds__(256) void k_dots_partial(size_t n2, int k, PtrPack 
   }
 }
 
+// Gram-Schmidt update with the next reduction in the same pass:
+// out = v - sum_{j<k} c_j V_j (subtractions in j order), and the block
+// partials of <V_j, out> for j < k (SELF = false, the next sweep's
+// coefficients) or of <out, out> (SELF = true, the norm).  The pointers V_j
+// and the coefficients c_j are device arrays.  Each thread takes two
+// consecutive elements per step; an odd last element goes to thread 0 of
+// block 0.  Partials: part[a * gridDim.x + block].
+constexpr int ORTH_KMAX = 32;
+template <int KB, bool SELF>
+__global__ __launch_bounds__(256) void k_orth_dots(size_t n2, int k, const double *v, const double *const *Vs,
+                                                   const double *c, double *out, double *part) {
+  __shared__ double cs[ORTH_KMAX];
+  __shared__ const double *vp[ORTH_KMAX];
+  __shared__ double sh[4];
+  if (threadIdx.x < k) {
+    cs[threadIdx.x] = c[threadIdx.x];
+    vp[threadIdx.x] = Vs[threadIdx.x];
+  }
+  __syncthreads();
+  constexpr int ND = SELF ? 1 : KB;
+  double d[ND];
+#pragma unroll
+  for (int a = 0; a < ND; ++a) d[a] = 0.0;
+  const size_t h = n2 / 2, stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < h; q += stride) {
+    double2 x = ((const double2 *)v)[q], w[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) w[j] = ((const double2 *)vp[j])[q];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      if (j < k) {
+        x.x -= cs[j] * w[j].x;
+        x.y -= cs[j] * w[j].y;
+      }
+    }
+    ((double2 *)out)[q] = x;
+    if (SELF) {
+      d[0] += x.x * x.x;
+      d[0] += x.y * x.y;
+    } else {
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        if (j < k) {
+          d[j] += w[j].x * x.x;
+          d[j] += w[j].y * x.y;
+        }
+      }
+    }
+  }
+  if ((n2 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const size_t i = n2 - 1;
+    double x = v[i];
+    for (int j = 0; j < k; ++j) x -= cs[j] * vp[j][i];
+    out[i] = x;
+    if (SELF) {
+      d[0] += x * x;
+    } else {
+#pragma unroll
+      for (int j = 0; j < ND; ++j)
+        if (j < k) d[j] += vp[j][i] * x;
+    }
+  }
+  const int nd = SELF ? 1 : k;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    if (a < nd) {
+      const double t = block_sum(d[a], sh);
+      if (threadIdx.x == 0) part[(size_t)a * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_final(int k, int nb, const double *part, double *res) {
   __shared__ double sh[4];
   for (int a = 0; a < k; ++a) {
@@ -668,6 +741,28 @@ void dots(int n2, int k, const void *const *X, const void *const *Y, double *res
       hipLaunchKernelGGL((k_dots_partial<double, 16>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, pp, partials);
   }
   hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, k, nb, partials, res);
+}
+
+void orth_dots(int n2, int k, const double *v, const double *const *Vs, const double *c, double *out, int self,
+               double *res, double *partials, hipStream_t s) {
+  int nb = grid_for(n2);
+  if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+#define XL_ORTH(KB)                                                                                       \
+  if (self)                                                                                               \
+    hipLaunchKernelGGL((k_orth_dots<KB, true>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, v, Vs, c, out,  \
+                       partials);                                                                         \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_orth_dots<KB, false>), dim3(nb), dim3(256), 0, s, (size_t)n2, k, v, Vs, c, out, \
+                       partials);
+  if (k <= 4) {
+    XL_ORTH(4)
+  } else if (k <= 8) {
+    XL_ORTH(8)
+  } else {
+    XL_ORTH(ORTH_KMAX)
+  }
+#undef XL_ORTH
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, self ? 1 : k, nb, partials, res);
 }
 
 void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s) {

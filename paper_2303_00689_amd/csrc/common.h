@@ -87,6 +87,12 @@ void lincomb_dev(int n2, int k, const double *const *M, const double *coef, doub
 // (library buffers, or halves of them at offsets of 4 n^2 bytes with n = 4 N_atoms)
 void dots(int n2, int k, const void *const *X, const void *const *Y, double *res, int is32,
           double *partials, hipStream_t s);
+// Gram-Schmidt update out = v - sum_{j<k} c_j V_j (1 <= k <= 32; c: k device
+// doubles; Vs: device array of k device pointers; out must not alias v or a
+// V_j) and, in the same pass, res[j] = <V_j, out> for j < k (self = 0) or
+// res[0] = <out, out> (self = 1)
+void orth_dots(int n2, int k, const double *v, const double *const *Vs, const double *c, double *out, int self,
+               double *res, double *partials, hipStream_t s);
 // res[0] = trace(M)
 void trace(int n, const void *M, double *res, int is32, double *partials, hipStream_t s);
 // Gershgorin bounds of a symmetric matrix: res[0] = min(F_ii - r_i), res[1] = max(F_ii + r_i)
