@@ -110,6 +110,13 @@ __device__ inline PairGeo pair_geo(const PairSys &ps, int A, int B) {
 //      diagonal atom blocks are k_fock_diag's.
 constexpr int FT = 4 * TA;       // F rows (and columns) of a tile: 64
 constexpr int FTP = FT + 1;      // padded LDS row of the staged block (doubles)
+// LDS row of the Coulomb sums, one per packed pair (doubles): 261 rather than
+// 256 puts the ten rows that the lanes of one reduction read on different banks
+constexpr int CRS = 261;
+// staged block entry (row, col): columns rotated by row / 2 within the row, so
+// that the 4 x 4 block stores and the row and column reads of the F store
+// phase spread over the LDS banks
+__device__ inline int ft_at(int row, int col) { return row * FTP + ((col + (row >> 1)) & (FT - 1)); }
 
 __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const double *P, double zsub,
                                                      int include_h, double *F, double *part) {
@@ -123,9 +130,9 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
 
   // LDS, reused by the phases: packed diagonals (phase 1-2), Coulomb sums
   // (phase 3), the staged F block (phase 4)
-  __shared__ double sh[2 * 10 * 256];
-  double *spk = sh + 2 * 10 * 256 - 32 * 10;  // [32][10]: A atoms 0..15, B atoms 16..31 (top of sh)
-  double *shA = sh, *shB = sh + 10 * 256;     // [10][256] each
+  __shared__ double sh[2 * 10 * CRS];
+  double *spk = sh + 2 * 10 * CRS - 32 * 10;  // [32][10]: A atoms 0..15, B atoms 16..31 (top of sh)
+  double *shA = sh, *shB = sh + 10 * CRS;     // [10][CRS] each
   double *ft = sh;                            // [FT][FTP]
 
   for (int v = slot; v < 320; v += 256) {
@@ -206,16 +213,16 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
   __syncthreads();  // every read of the packed diagonals is done
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    shA[r * 256 + slot] = cA[r];
-    shB[r * 256 + slot] = cB[r];
+    shA[r * CRS + slot] = cA[r];
+    shB[r * CRS + slot] = cB[r];
   }
   __syncthreads();
   if (slot < 160) {
     const int x = slot / 10, r = slot % 10;
     double row = 0.0, col = 0.0;
     for (int q = 0; q < TA; ++q) {
-      row += shA[r * 256 + x * TA + q];  // atom ta*16+x as A, over partners b
-      col += shB[r * 256 + q * TA + x];  // atom tb*16+x as B, over partners a
+      row += shA[r * CRS + x * TA + q];  // atom ta*16+x as A, over partners b
+      col += shB[r * CRS + q * TA + x];  // atom tb*16+x as B, over partners a
     }
     if (ta == tb) {
       const int X = ta * TA + x;
@@ -235,8 +242,8 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        ft[(4 * al + i) * FTP + 4 * bl + j] = G[i][j];
-        if (ta == tb) ft[(4 * bl + j) * FTP + 4 * al + i] = G[i][j];
+        ft[ft_at(4 * al + i, 4 * bl + j)] = G[i][j];
+        if (ta == tb) ft[ft_at(4 * bl + j, 4 * al + i)] = G[i][j];
       }
   }
   __syncthreads();
@@ -256,9 +263,9 @@ __global__ __launch_bounds__(256) void k_fock_pairs(PairSys ps, int n, const dou
       const int cc = 16 * s8 + 2 * k8;  // two consecutive columns of one atom
       const int ca = tb * TA + cc / 4, cb = ta * TA + cc / 4;
       if (ra < N && ca < N && (ta != tb || ra != ca))
-        *(double2 *)(F + ga + cc) = double2{ft[row * FTP + cc], ft[row * FTP + cc + 1]};
+        *(double2 *)(F + ga + cc) = double2{ft[ft_at(row, cc)], ft[ft_at(row, cc + 1)]};
       if (ta != tb && rb < N && cb < N)
-        *(double2 *)(F + gb + cc) = double2{ft[cc * FTP + row], ft[(cc + 1) * FTP + row]};
+        *(double2 *)(F + gb + cc) = double2{ft[ft_at(cc, row)], ft[ft_at(cc + 1, row)]};
     }
   }
 }
