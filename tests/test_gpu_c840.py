@@ -122,8 +122,9 @@ def test_mixed_precision_forces_meet_target(binding, ref, prec):
     assert perr <= TOL
     assert ferr <= 1e-4
     # split response: about three times the measured error (MI355X, relative
-    # max-abs): dm64_bf16x3 3.8e-4 / 9.5e-5 / 8.0e-5 and dm64_fp16x3
-    # 2.1e-5 / 6.6e-6 / 1.2e-5 for the benchmark, all-ones J and low-gap clusters
+    # max-abs): dm64_bf16x3 4.2e-4 / 9.5e-5 / 6.5e-5 (3.8e-4 / 9.5e-5 / 8.0e-5
+    # with A B + B A as one two-product launch) and dm64_fp16x3
+    # 2.1e-5 / 6.5e-6 / 1.2e-5 for the benchmark, all-ones J and low-gap clusters
     bound = {"dm64_bf16x3": {"c840": 1.2e-3, "c840_allones": 3e-4, "c840_lowgap": 2.5e-4},
              "dm64_fp16x3": {"c840": 6e-5, "c840_allones": 2e-5, "c840_lowgap": 4e-5}}[prec]
     key = "c840_allones" if ref.j_pattern == "allones" else ("c840_lowgap" if ref.w["T_e"] == 10000.0 else "c840")
